@@ -1,0 +1,97 @@
+/*
+ * Oracle for whole-body MPPI: a plain, slow FP64 CPU implementation of what the
+ * GPU hot path computes.  TEST INFRASTRUCTURE ONLY: it is used by the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark, never by the product
+ * library, and it shares no code with it.
+ *
+ * Method: MPPI (paper Sec. II-B, Eqs. 1-2, Algorithm 1) over cubic-spline knots
+ * (Sec. III-B) with whole-body floating-base dynamics and penalty contact in place
+ * of the MuJoCo simulator (Sec. III-A).
+ *
+ * State layout (robot, 37 doubles):
+ *   [p_w(3), quat wxyz(4), q_joint(12), v_w(3), omega_body(3), qd_joint(12)]
+ * joints ordered FL, FR, RL, RR x (abduction, flexion, knee).
+ * Scene 3 (free box) appends [p(3), quat wxyz(4), v_w(3), omega_body(3)] -> 50.
+ */
+#ifndef MPPI_ORACLE_H
+#define MPPI_ORACLE_H
+#include <stdint.h>
+
+#define ORC_NB 13
+#define ORC_NQ 19
+#define ORC_NV 18
+#define ORC_NX 37
+#define ORC_NX_BOX 50
+
+enum { ORC_SCENE_FLAT = 0, ORC_SCENE_HEIGHTFIELD = 1, ORC_SCENE_STATIC_BOX = 2, ORC_SCENE_FREE_BOX = 3 };
+
+typedef struct orc_model {
+    double trunk_size[3];
+    double trunk_mass;
+    double hip_x, hip_y;
+    double thigh_len, thigh_mass;
+    double calf_len, calf_mass;
+    double foot_r;
+    double gravity;
+    double k, c, mu, vs;          /* contact stiffness, damping, friction, slip velocity */
+    int32_t scene;
+    int32_t hf_nx, hf_ny, pad0;
+    double hf_cell, hf_x0, hf_y0;
+    const double *hf;             /* heights, hf[iy*nx + ix] */
+    double sbox_center[3], sbox_half[3];   /* static (climb) box, axis aligned */
+    double box_half[3], box_mass;          /* free box */
+} orc_model;
+
+typedef struct orc_params {
+    int32_t K, H, nk, pad0;
+    double dt, sigma, lambda, kp, kd;
+    double w_h, h_ref, w_o, w_v, v_ref, w_tau, w_reach, w_box;
+    double goal[2];
+    uint64_t seed;
+    uint32_t instance, pad1;
+} orc_params;
+
+int  orc_nx(const orc_model *m);
+
+/* Counter-based generator (Salmon et al., SC'11) and the Gaussian map. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_sample_eps(const orc_params *p, uint32_t step, double *eps /* K x 12nk */);
+void orc_philox_raw(const orc_params *p, uint32_t step, uint32_t *raw /* K x 4*ceil(D/4) */);
+
+/* Spline (Sec. III-B): basis H x nk, shift nk x nk. */
+void orc_spline_basis(int nk, int H, double dt, double *B);
+void orc_spline_eval(int nk, double T, const double *knots, double t, double *out);
+void orc_shift_matrix(int nk, int H, double dt, double *S);
+
+/* Rigid-body terms (no contact). */
+void orc_fk(const orc_model *m, const double *q, double *R /*13x9*/, double *pos /*13x3*/, double *com /*13x3*/);
+void orc_foot_positions(const orc_model *m, const double *q, double *feet /*4x3*/);
+void orc_mass_matrix(const orc_model *m, const double *q, double *M /*18x18*/);
+void orc_bias(const orc_model *m, const double *q, const double *v, double *b /*18*/);
+double orc_kinetic_energy(const orc_model *m, const double *q, const double *v);
+double orc_kinetic_energy_fd(const orc_model *m, const double *q, const double *v, double eps);
+double orc_potential_energy(const orc_model *m, const double *q);
+void orc_momentum(const orc_model *m, const double *q, const double *v, double *P /*3*/, double *Lo /*3*/);
+void orc_retract(const double *q, const double *v, double t, double *qo);
+void orc_accel(const orc_model *m, const double *q, const double *v, const double *tau_gen /*18*/, double *vdot);
+void orc_rk4(const orc_model *m, double *q, double *v, const double *tau_gen, double dt, int nsteps, int spring,
+             const double *kp_target, double kp);
+
+/* One discrete step (linearly implicit velocity update, semi-implicit positions). */
+int  orc_step(const orc_model *m, const double *x, const double *u, double kp, double kd, double dt,
+              double *xo, double *tau_out);
+void orc_contact_total(const orc_model *m, const double *x, double *F_robot /*3*/, double *F_box /*3*/, int *n_active);
+
+/* Cost, rollout and MPPI (Eqs. 1-2, Algorithm 1). */
+double orc_stage_cost(const orc_model *m, const orc_params *p, const double *x, const double *tau);
+double orc_rollout(const orc_model *m, const orc_params *p, const double *x0, const double *theta, double *traj);
+void orc_rollout_batch(const orc_model *m, const orc_params *p, const double *x0, const double *mu,
+                       const double *eps, double *costs, double *traj, int nthreads);
+int  orc_weights(int K, double lambda, const double *costs, double *w);
+int  orc_update(const orc_params *p, const double *costs, const double *mu, const double *eps,
+                double *mu_out, double *w_out);
+void orc_shift(const orc_params *p, const double *mu_prime, double *mu_out, double *u0);
+int  orc_mppi_step(const orc_model *m, const orc_params *p, uint32_t step, const double *x0, double *mu,
+                   double *u0, double *costs, int nthreads);
+
+#endif

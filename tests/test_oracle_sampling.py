@@ -1,0 +1,118 @@
+"""Pins of the oracle's noise generator and spline (CPU only).
+
+The generator is Philox4x32-10 (Salmon et al., SC'11), pinned to the published
+known-answer vectors; the Gaussian map is checked statistically.  The spline is the
+not-a-knot cubic of Sec. III-B, pinned to scipy's CubicSpline and to exactness on
+cubic polynomials.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import interpolate, stats
+
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+
+
+def _kat():
+    rows = []
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(t, 16) for t in line.split()]
+        rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+@pytest.mark.parametrize("ctr,key,want", _kat())
+def test_philox_known_answers(ctr, key, want):
+    assert O.philox(ctr, key).tolist() == want
+
+
+def _p(K=4096, nk=6, seed=12345, instance=0):
+    return dict(K=K, H=10, nk=nk, dt=0.01, sigma=0.3, lam=0.1, kp=40, kd=1, w_h=0, h_ref=0, w_o=0, w_v=0, v_ref=0,
+                w_tau=0, w_reach=0, w_box=0, seed=seed, instance=instance)
+
+
+def test_gaussian_moments_and_ks():
+    eps = O.sample_eps(_p(K=8192, nk=8), step=3).ravel()
+    n = eps.size
+    assert abs(eps.mean()) < 5 / math.sqrt(n)
+    assert abs(eps.var() - 1) < 5 * math.sqrt(2 / n)
+    assert abs(stats.skew(eps)) < 5 * math.sqrt(6 / n)
+    assert abs(stats.kurtosis(eps)) < 5 * math.sqrt(24 / n)
+    assert stats.kstest(eps, "norm").pvalue > 1e-3
+
+
+def test_gaussian_pairs_uncorrelated():
+    eps = O.sample_eps(_p(K=8192, nk=8), step=0)
+    a, b = eps[:, 0::2].ravel(), eps[:, 1::2].ravel()
+    assert abs(np.corrcoef(a, b)[0, 1]) < 5 / math.sqrt(a.size)
+
+
+def test_counter_layout_streams_differ():
+    base = O.philox_raw(_p(K=8, nk=4), 0)
+    assert not np.array_equal(base, O.philox_raw(_p(K=8, nk=4), 1))
+    assert not np.array_equal(base, O.philox_raw(_p(K=8, nk=4, instance=1), 0))
+    assert not np.array_equal(base, O.philox_raw(_p(K=8, nk=4, seed=7), 0))
+    # sample n, block c uses counter (c, n, step, instance) with key (seed_lo, seed_hi)
+    seed = (5 << 32) | 99
+    raw = O.philox_raw(_p(K=3, nk=4, seed=seed, instance=2), 7)
+    assert raw[2, 4:8].tolist() == O.philox([1, 2, 7, 2], [99, 5]).tolist()
+
+
+def test_uniform_map_open_interval():
+    # 24-bit uniforms never hit 0 or 1, so the log of Box-Muller stays finite
+    eps = O.sample_eps(_p(K=2048, nk=8), step=1)
+    assert np.isfinite(eps).all()
+
+
+@pytest.mark.parametrize("nk", [2, 3, 4, 5, 6, 8])
+def test_spline_matches_scipy_not_a_knot(nk):
+    rng = np.random.default_rng(nk)
+    H, dt = 37, 0.013
+    T = H * dt
+    B = O.spline_basis(nk, H, dt)
+    tk = np.linspace(0, T, nk)
+    t = dt * np.arange(H)
+    for _ in range(3):
+        y = rng.normal(size=nk)
+        if nk >= 3:
+            want = interpolate.CubicSpline(tk, y, bc_type="not-a-knot")(t)
+        else:
+            want = np.interp(t, tk, y)
+        np.testing.assert_allclose(B @ y, want, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("nk", [4, 6, 8])
+def test_spline_reproduces_cubics(nk):
+    H, dt = 50, 0.01
+    T = H * dt
+    tk = np.linspace(0, T, nk)
+    t = dt * np.arange(H)
+    poly = np.array([0.3, -1.2, 2.5, -4.0])
+    y = np.polyval(poly, tk)
+    np.testing.assert_allclose(O.spline_basis(nk, H, dt) @ y, np.polyval(poly, t), atol=1e-12)
+
+
+def test_four_knots_is_lagrange_cubic():
+    H, dt = 25, 0.02
+    tk = np.linspace(0, H * dt, 4)
+    y = np.array([0.1, -0.4, 0.7, 0.2])
+    coef = np.polyfit(tk, y, 3)
+    np.testing.assert_allclose(O.spline_basis(4, H, dt) @ y, np.polyval(coef, dt * np.arange(H)), atol=1e-12)
+
+
+@pytest.mark.parametrize("nk", [4, 6, 8])
+def test_shift_of_constant_and_line(nk):
+    H, dt = 50, 0.01
+    T = H * dt
+    S = O.shift_matrix(nk, H, dt)
+    np.testing.assert_allclose(S @ np.full(nk, 0.7), np.full(nk, 0.7), atol=1e-13)
+    tk = np.linspace(0, T, nk)
+    line = 0.2 + 1.5 * tk
+    want = 0.2 + 1.5 * np.minimum(tk + dt, T)
+    np.testing.assert_allclose(S @ line, want, atol=1e-12)
