@@ -1,0 +1,171 @@
+/*
+ * mppi.h -- C ABI of the MI355X (gfx950) whole-body MPPI library.
+ *
+ * The library implements the sampling, rollout and update of model-predictive path
+ * integral control (Sec. II-B of the paper: Eq. 1 weights, Eq. 2 mean update,
+ * Algorithm 1 loop) over cubic-spline knots tracked by joint PD controllers
+ * (Sec. III-B), with a floating-base quadruped simulated by the library's own rigid-body
+ * dynamics and penalty contact in place of the MuJoCo simulator (Sec. III-A).
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are DEVICE pointers owned by the caller; host pointers are named
+ *    without the prefix.  The library keeps no caller pointer after a call returns,
+ *    except the workspace and stream given to mppi_bind.
+ *  - Calls that launch work are asynchronous on the bound HIP stream (passed as void*).
+ *    Nothing is returned through host memory except the status code.
+ *  - A negative status means nothing was launched; mppi_last_error() describes why.
+ *  - All floating-point data is FP32.
+ *  - The library never allocates device memory: the caller allocates a workspace of
+ *    mppi_workspace_bytes() bytes (256-byte aligned) and binds it.
+ *
+ * State layout (robot, 37 floats):
+ *   [p_world(3), quat wxyz(4), q_joint(12), v_world(3), omega_body(3), qd_joint(12)]
+ * joints ordered front-left, front-right, rear-left, rear-right x (abduction, hip
+ * flexion, knee).  Scene MPPI_SCENE_FREE_BOX appends the box
+ *   [p_world(3), quat wxyz(4), v_world(3), omega_body(3)]  -> 50 floats.
+ * Knot layout: joint-major, knots[j * n_knots + i], i-th knot of joint j at time
+ *   t_i = i * H * dt / (n_knots - 1).
+ */
+#ifndef MPPI_H
+#define MPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mppi_status {
+    MPPI_OK = 0,
+    MPPI_WARN_ALL_NONFINITE = 1, /* every sample diverged: the nominal was kept (shifted) */
+    MPPI_EINVAL = -1,            /* bad argument; see mppi_last_error */
+    MPPI_ENOMEM = -2,            /* workspace too small */
+    MPPI_EHIP = -3,              /* a HIP runtime call failed */
+    MPPI_ESTATE = -6             /* call out of order (e.g. no workspace bound) */
+} mppi_status;
+
+enum {
+    MPPI_SCENE_FLAT = 0,        /* ground plane z = 0 */
+    MPPI_SCENE_HEIGHTFIELD = 1, /* bilinear heightfield */
+    MPPI_SCENE_STATIC_BOX = 2,  /* ground plane plus a fixed axis-aligned box (climbing) */
+    MPPI_SCENE_FREE_BOX = 3     /* ground plane plus a free box (pushing) */
+};
+
+/* Arithmetic of one dynamics step.  The state is FP32 between steps in both modes. */
+enum {
+    MPPI_ARITH_FP64 = 0, /* default: step computed in FP64 (FP32-state-limited accuracy) */
+    MPPI_ARITH_FP32 = 1  /* step computed in FP32: faster, per-step error set by the contact conditioning */
+};
+
+#define MPPI_MAX_KNOTS 8
+#define MPPI_MAX_HORIZON 256
+#define MPPI_MAX_HEIGHTFIELD 14336 /* cells: the grid is staged in LDS with the spline basis */
+
+/* Robot and scene.  The robot is a trunk box with four legs; each leg has abduction
+ * (x), hip flexion (y) and knee (y) joints at the hip point (+-hip_x, +-hip_y, 0), a
+ * thigh and a calf modelled as uniform rods along -z of their frames, and a massless
+ * foot sphere at the calf end.  Contact: normal k*depth - c*v_n while overlapping,
+ * friction mu*Fn*tanh(|v_t|/slip_velocity). */
+typedef struct mppi_model_desc {
+    float trunk_size[3];
+    float trunk_mass;
+    float hip_x, hip_y;
+    float thigh_len, thigh_mass;
+    float calf_len, calf_mass;
+    float foot_r;
+    float gravity;
+    float contact_k, contact_c, friction_mu, slip_velocity;
+    int32_t scene;
+    int32_t hf_nx, hf_ny;       /* heightfield grid (scene 1) */
+    float hf_cell, hf_x0, hf_y0;
+    const float *heightfield;   /* HOST pointer, hf_ny * hf_nx heights, row = y; copied */
+    float sbox_center[3], sbox_half[3]; /* static box (scene 2) */
+    float box_half[3], box_mass;        /* free box (scene 3) */
+} mppi_model_desc;
+
+/* Controller.  Sample 0 is the noise-free nominal; samples n >= 1 use
+ * theta_n = mu + sigma * eps_n.  Running cost per step (dt times)
+ *   w_height (z - h_ref)^2 + w_upright (1 - R_zz^2) + w_vel (v_x - v_ref)^2 + w_torque |tau|^2
+ * and in scene 3 the velocity term is replaced by
+ *   w_reach |p_xy - box_xy|^2 + w_box |box_xy - goal|^2. */
+typedef struct mppi_params {
+    int32_t K, H, n_knots;
+    float dt, sigma, lambda, kp, kd;
+    float w_height, h_ref, w_upright, w_vel, v_ref, w_torque, w_reach, w_box;
+    float goal[2];
+    uint64_t seed;
+    uint32_t instance;
+    int32_t arith;              /* MPPI_ARITH_FP64 (0, default) or MPPI_ARITH_FP32 */
+} mppi_params;
+
+typedef struct mppi_model mppi_model;
+typedef struct mppi_ctx mppi_ctx;
+
+/* Copies the description (and the heightfield) into a host-side model.
+ * EINVAL on non-positive sizes or masses, an unknown scene, or a heightfield larger
+ * than MPPI_MAX_HEIGHTFIELD cells. */
+mppi_status mppi_model_create(const mppi_model_desc *desc, mppi_model **out);
+void mppi_model_destroy(mppi_model *model);
+/* number of floats in a state for this model (37, or 50 with a free box) */
+int mppi_model_nx(const mppi_model *model);
+
+/* Creates a controller (Algorithm 1 "Require": samples K, horizon H, temperature
+ * lambda, sampling scale sigma).  Builds the spline basis and shift matrix on the host.
+ * EINVAL unless 1 <= K, 1 <= H <= MPPI_MAX_HORIZON, 2 <= n_knots <= MPPI_MAX_KNOTS,
+ * dt > 0, lambda > 0, sigma >= 0, arith one of MPPI_ARITH_*. */
+mppi_status mppi_create(const mppi_model *model, const mppi_params *params, mppi_ctx **out);
+void mppi_destroy(mppi_ctx *ctx);
+size_t mppi_workspace_bytes(const mppi_ctx *ctx);
+/* Binds a caller-owned device workspace and stream; uploads model data, spline basis and
+ * shift matrix, and sets the nominal to zero.  The step counter is reset to 0. */
+mppi_status mppi_bind(mppi_ctx *ctx, void *d_workspace, size_t bytes, void *hip_stream);
+/* nominal knots mu (12 * n_knots floats, device) in/out */
+mppi_status mppi_set_nominal(mppi_ctx *ctx, const float *d_knots);
+mppi_status mppi_get_nominal(mppi_ctx *ctx, float *d_knots);
+/* control-step counter used as the third Philox counter word (noise of step s) */
+mppi_status mppi_set_step(mppi_ctx *ctx, uint32_t step);
+uint32_t mppi_get_step(const mppi_ctx *ctx);
+
+/* Gaussian knot noise (Sec. II-B sampling), eps[n * D + d], D = 12 * n_knots:
+ * Philox4x32-10 with key (seed_lo, seed_hi) and counter (d / 4, n, step, instance);
+ * 24-bit uniforms ((x >> 8) + 1/2) / 2^24 mapped by Box-Muller on word pairs (0,1), (2,3).
+ * d_raw (optional) receives the raw words, K x 4*ceil(D/4). */
+mppi_status mppi_sample(mppi_ctx *ctx, float *d_eps, uint32_t *d_raw);
+
+/* Rolls out all K samples from d_x0 (Algorithm 1 inner loops): spline targets, PD
+ * torques, dynamics step, running cost.  d_eps: K x D noise, or NULL to draw it with
+ * Philox for the current step (kept in the workspace for mppi_update).  d_costs: K
+ * floats (+inf for a diverged sample).  d_traj: optional K x (H+1) x nx states. */
+mppi_status mppi_rollout_batch(mppi_ctx *ctx, const float *d_x0, const float *d_eps, float *d_costs,
+                               float *d_traj);
+
+/* Eq. 1 weights from d_costs and Eq. 2 mean update of the knots, using d_eps (or, if
+ * NULL, the noise the last Philox rollout kept).  Writes the updated (unshifted) knots
+ * to d_knots_out and optionally the weights (K floats).  Does not change the nominal. */
+mppi_status mppi_update(mppi_ctx *ctx, const float *d_costs, const float *d_eps, float *d_knots_out,
+                        float *d_weights_out);
+
+/* One full control step (Algorithm 1): sample, roll out, weight, update, take the first
+ * control u = spline(mu', 0) into d_u0_out (12 floats), shift the nominal by dt, and
+ * advance the step counter.  If every sample diverged the shifted old nominal is kept
+ * and mppi_sync_status reports MPPI_WARN_ALL_NONFINITE. */
+mppi_status mppi_step(mppi_ctx *ctx, const float *d_x0, float *d_u0_out);
+
+/* Synchronises the bound stream and returns the status of the last update. */
+mppi_status mppi_sync_status(mppi_ctx *ctx);
+
+/* One dynamics step for n independent states (the plant of a closed loop):
+ * x_out = step(x, u) with joint targets d_u (n x 12), PD gains kp, kd, time step dt.
+ * d_tau_out (optional) receives the PD torques (n x 12).  d_hf: device heightfield for
+ * scene 1 (may be NULL otherwise). */
+mppi_status mppi_sim_step(const mppi_model *model, int arith, int n, const float *d_x, const float *d_u, float kp,
+                          float kd, float dt, float *d_x_out, float *d_tau_out, const float *d_hf, void *hip_stream);
+
+const char *mppi_status_str(mppi_status s);
+const char *mppi_last_error(const mppi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -824,6 +824,30 @@ int orc_step(const orc_model *m, const double *x, const double *u, double kp, do
     return rc;
 }
 
+/* the linear system of one step, A dv = dt f (robot part), for diagnostics and tests */
+int orc_step_system(const orc_model *m, const double *x, const double *u, double kp, double kd, double dt,
+                    double *A_out, double *rhs_out)
+{
+    tree_t t; fk_t k;
+    build_tree(m, &t);
+    const double *q = x, *v = x + ORC_NQ;
+    fk_compute(m, &t, q, &k);
+    double M[ORC_NV * ORC_NV], b[ORC_NV], f[ORC_NV], D[ORC_NV * ORC_NV];
+    double fbox[6] = {0}, Dbox[36] = {0};
+    mass_matrix_k(&t, &k, M);
+    bias_k(m, &t, &k, v, b);
+    for (int i = 0; i < ORC_NV; ++i) f[i] = -b[i];
+    for (int j = 0; j < 12; ++j) f[6 + j] += kp * (u[j] - q[7 + j]) - kd * v[6 + j];
+    memset(D, 0, sizeof(D));
+    for (int j = 0; j < 12; ++j) D[(6 + j) * ORC_NV + 6 + j] = kd;
+    cstate_t s;
+    contact_setup(m, &t, &k, x, &s, f, D, fbox, Dbox);
+    all_contacts(&s);
+    for (int i = 0; i < ORC_NV * ORC_NV; ++i) A_out[i] = M[i] + dt * D[i];
+    for (int i = 0; i < ORC_NV; ++i) rhs_out[i] = dt * f[i];
+    return s.n_active;
+}
+
 void orc_contact_total(const orc_model *m, const double *x, double *F_robot, double *F_box, int *n_active)
 {
     tree_t t; fk_t k;

@@ -80,6 +80,8 @@ void orc_rk4(const orc_model *m, double *q, double *v, const double *tau_gen, do
 /* One discrete step (linearly implicit velocity update, semi-implicit positions). */
 int  orc_step(const orc_model *m, const double *x, const double *u, double kp, double kd, double dt,
               double *xo, double *tau_out);
+int  orc_step_system(const orc_model *m, const double *x, const double *u, double kp, double kd, double dt,
+                     double *A_out, double *rhs_out);
 void orc_contact_total(const orc_model *m, const double *x, double *F_robot /*3*/, double *F_box /*3*/, int *n_active);
 
 /* Cost, rollout and MPPI (Eqs. 1-2, Algorithm 1). */

@@ -88,6 +88,7 @@ def lib():
             "orc_rk4": (None, [mp, dp, dp, dp, C.c_double, C.c_int, C.c_int, dp, C.c_double]),
             "orc_step": (C.c_int, [mp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]),
             "orc_contact_total": (None, [mp, dp, dp, dp, C.POINTER(C.c_int)]),
+            "orc_step_system": (C.c_int, [mp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]),
             "orc_stage_cost": (C.c_double, [mp, pp, dp, dp]),
             "orc_rollout": (C.c_double, [mp, pp, dp, dp, dp]),
             "orc_rollout_batch": (None, [mp, pp, dp, dp, dp, dp, dp, C.c_int]),
@@ -218,6 +219,12 @@ class Oracle:
         rc = self.L.orc_step(C.byref(self.m), _dp(x), _dp(_f64(u, 12)), float(kp), float(kd), float(dt), _dp(xo),
                              _dp(tau))
         return xo, tau, rc
+
+    def step_system(self, x, u, kp, kd, dt):
+        A, r = np.zeros((NV, NV)), np.zeros(NV)
+        n = self.L.orc_step_system(C.byref(self.m), _dp(_f64(x, self.nx)), _dp(_f64(u, 12)), float(kp), float(kd),
+                                   float(dt), _dp(A), _dp(r))
+        return A, r, n
 
     def contact_total(self, x):
         Fr, Fb, n = np.zeros(3), np.zeros(3), C.c_int(0)

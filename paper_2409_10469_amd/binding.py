@@ -1,0 +1,262 @@
+"""Thin ctypes binding of the C ABI in include/mppi.h.
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels of
+libmppi.so.  PyTorch supplies device memory (the workspace and the caller's buffers)
+and the stream.  There is no CPU fallback: if the library is missing or the GPU is
+absent the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmppi.so")
+
+OK, WARN_ALL_NONFINITE, EINVAL, ENOMEM, EHIP, ESTATE = 0, 1, -1, -2, -3, -6
+ARITH = {"fp64": 0, "fp32": 1}
+
+
+class MppiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mppi status {status}: {msg}")
+        self.status = status
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [
+        ("trunk_size", C.c_float * 3), ("trunk_mass", C.c_float),
+        ("hip_x", C.c_float), ("hip_y", C.c_float),
+        ("thigh_len", C.c_float), ("thigh_mass", C.c_float),
+        ("calf_len", C.c_float), ("calf_mass", C.c_float),
+        ("foot_r", C.c_float), ("gravity", C.c_float),
+        ("contact_k", C.c_float), ("contact_c", C.c_float), ("friction_mu", C.c_float), ("slip_velocity", C.c_float),
+        ("scene", C.c_int32), ("hf_nx", C.c_int32), ("hf_ny", C.c_int32),
+        ("hf_cell", C.c_float), ("hf_x0", C.c_float), ("hf_y0", C.c_float),
+        ("heightfield", C.POINTER(C.c_float)),
+        ("sbox_center", C.c_float * 3), ("sbox_half", C.c_float * 3),
+        ("box_half", C.c_float * 3), ("box_mass", C.c_float),
+    ]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32), ("H", C.c_int32), ("n_knots", C.c_int32),
+        ("dt", C.c_float), ("sigma", C.c_float), ("lam", C.c_float), ("kp", C.c_float), ("kd", C.c_float),
+        ("w_height", C.c_float), ("h_ref", C.c_float), ("w_upright", C.c_float), ("w_vel", C.c_float),
+        ("v_ref", C.c_float), ("w_torque", C.c_float), ("w_reach", C.c_float), ("w_box", C.c_float),
+        ("goal", C.c_float * 2),
+        ("seed", C.c_uint64), ("instance", C.c_uint32), ("arith", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmppi.so (built by paper_2409_10469_amd.build); raise if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, fp, u32p = C.c_void_p, C.c_void_p, C.c_void_p
+        sig = {
+            "mppi_model_create": (C.c_int, [C.POINTER(ModelDesc), C.POINTER(C.c_void_p)]),
+            "mppi_model_destroy": (None, [vp]),
+            "mppi_model_nx": (C.c_int, [vp]),
+            "mppi_create": (C.c_int, [vp, C.POINTER(Params), C.POINTER(C.c_void_p)]),
+            "mppi_destroy": (None, [vp]),
+            "mppi_workspace_bytes": (C.c_size_t, [vp]),
+            "mppi_bind": (C.c_int, [vp, vp, C.c_size_t, vp]),
+            "mppi_set_nominal": (C.c_int, [vp, fp]),
+            "mppi_get_nominal": (C.c_int, [vp, fp]),
+            "mppi_set_step": (C.c_int, [vp, C.c_uint32]),
+            "mppi_get_step": (C.c_uint32, [vp]),
+            "mppi_sample": (C.c_int, [vp, fp, u32p]),
+            "mppi_rollout_batch": (C.c_int, [vp, fp, fp, fp, fp]),
+            "mppi_update": (C.c_int, [vp, fp, fp, fp, fp]),
+            "mppi_step": (C.c_int, [vp, fp, fp]),
+            "mppi_sync_status": (C.c_int, [vp]),
+            "mppi_sim_step": (C.c_int, [vp, C.c_int, C.c_int, fp, fp, C.c_float, C.c_float, C.c_float, fp, fp, fp,
+                                        vp]),
+            "mppi_status_str": (C.c_char_p, [C.c_int]),
+            "mppi_last_error": (C.c_char_p, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status < 0:
+        msg = lib().mppi_last_error(ctx).decode()
+        raise MppiError(status, msg)
+    return status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous(), "device tensors only"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def model_desc(d: dict) -> tuple:
+    """Build the C model description from a workload dict; returns (desc, keepalive)."""
+    m = ModelDesc()
+    m.trunk_size[:] = [float(v) for v in d["trunk_size"]]
+    for k_py, k_c in (("trunk_mass", "trunk_mass"), ("hip_x", "hip_x"), ("hip_y", "hip_y"),
+                      ("thigh_len", "thigh_len"), ("thigh_mass", "thigh_mass"), ("calf_len", "calf_len"),
+                      ("calf_mass", "calf_mass"), ("foot_r", "foot_r"), ("gravity", "gravity"),
+                      ("k", "contact_k"), ("c", "contact_c"), ("mu", "friction_mu"), ("vs", "slip_velocity")):
+        setattr(m, k_c, float(d[k_py]))
+    m.scene = int(d.get("scene", 0))
+    keep = None
+    if "hf" in d:
+        hf = np.ascontiguousarray(d["hf"], dtype=np.float32)
+        keep = hf
+        m.hf_ny, m.hf_nx = hf.shape
+        m.hf_cell, m.hf_x0, m.hf_y0 = float(d["hf_cell"]), float(d["hf_x0"]), float(d["hf_y0"])
+        m.heightfield = hf.ctypes.data_as(C.POINTER(C.c_float))
+    m.sbox_center[:] = [float(v) for v in d.get("sbox_center", (0, 0, 0))]
+    m.sbox_half[:] = [float(v) for v in d.get("sbox_half", (0, 0, 0))]
+    m.box_half[:] = [float(v) for v in d.get("box_half", (0, 0, 0))]
+    m.box_mass = float(d.get("box_mass", 0.0))
+    return m, keep
+
+
+def params_struct(p: dict) -> Params:
+    s = Params()
+    s.K, s.H, s.n_knots = int(p["K"]), int(p["H"]), int(p["nk"])
+    s.dt, s.sigma, s.lam, s.kp, s.kd = (float(p[k]) for k in ("dt", "sigma", "lam", "kp", "kd"))
+    s.w_height, s.h_ref, s.w_upright = float(p["w_h"]), float(p["h_ref"]), float(p["w_o"])
+    s.w_vel, s.v_ref, s.w_torque = float(p["w_v"]), float(p["v_ref"]), float(p["w_tau"])
+    s.w_reach, s.w_box = float(p["w_reach"]), float(p["w_box"])
+    s.goal[:] = [float(v) for v in p.get("goal", (0.0, 0.0))]
+    s.seed = int(p.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    s.instance = int(p.get("instance", 0))
+    s.arith = ARITH[p.get("arith", "fp64")]
+    return s
+
+
+class Model:
+    def __init__(self, d: dict):
+        desc, keep = model_desc(d)
+        h = C.c_void_p()
+        _check(lib().mppi_model_create(C.byref(desc), C.byref(h)))
+        self.h = h
+        self.nx = lib().mppi_model_nx(h)
+        self.scene = desc.scene
+        self._hf_host = keep
+        self._hf_dev = None
+
+    def hf_device(self):
+        import torch
+        if self._hf_host is None:
+            return None
+        if self._hf_dev is None:
+            self._hf_dev = torch.from_numpy(self._hf_host).cuda()
+        return self._hf_dev
+
+    def sim_step(self, x, u, kp, kd, dt, tau_out=None, stream=None, arith="fp64"):
+        """One dynamics step of n states x (n x nx) with joint targets u (n x 12)."""
+        import torch
+        n = x.shape[0]
+        xo = torch.empty_like(x)
+        _check(lib().mppi_sim_step(self.h, ARITH[arith], n, _ptr(x), _ptr(u), kp, kd, dt, _ptr(xo), _ptr(tau_out),
+                                   _ptr(self.hf_device()), _stream(stream)))
+        return xo
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mppi_model_destroy(self.h)
+            self.h = None
+
+
+class Controller:
+    """One MPPI instance bound to a torch-allocated device workspace."""
+
+    def __init__(self, model: Model, p: dict, stream=None):
+        import torch
+        self.model = model
+        self.p = dict(p)
+        ps = params_struct(p)
+        h = C.c_void_p()
+        _check(lib().mppi_create(model.h, C.byref(ps), C.byref(h)))
+        self.h = h
+        self.K, self.H, self.nk = int(p["K"]), int(p["H"]), int(p["nk"])
+        self.D = 12 * self.nk
+        nbytes = lib().mppi_workspace_bytes(h)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off:off + nbytes]
+        self.stream = stream
+        _check(lib().mppi_bind(h, C.c_void_p(self.ws_view.data_ptr()), nbytes, _stream(stream)), h)
+
+    def _s(self, status):
+        return _check(status, self.h)
+
+    def set_nominal(self, knots):
+        self._s(lib().mppi_set_nominal(self.h, _ptr(knots)))
+
+    def get_nominal(self):
+        import torch
+        out = torch.empty(self.D, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_get_nominal(self.h, _ptr(out)))
+        return out
+
+    def set_step(self, step):
+        self._s(lib().mppi_set_step(self.h, int(step)))
+
+    @property
+    def step_counter(self):
+        return lib().mppi_get_step(self.h)
+
+    def sample(self, raw=False):
+        import torch
+        eps = torch.empty((self.K, self.D), dtype=torch.float32, device="cuda")
+        nb = (self.D + 3) // 4
+        r = torch.empty((self.K, 4 * nb), dtype=torch.int32, device="cuda") if raw else None
+        self._s(lib().mppi_sample(self.h, _ptr(eps), _ptr(r)))
+        return (eps, r) if raw else eps
+
+    def rollout_batch(self, x0, eps=None, traj=False, costs=None):
+        import torch
+        costs = costs if costs is not None else torch.empty(self.K, dtype=torch.float32, device="cuda")
+        tr = torch.empty((self.K, self.H + 1, self.model.nx), dtype=torch.float32, device="cuda") if traj else None
+        self._s(lib().mppi_rollout_batch(self.h, _ptr(x0), _ptr(eps), _ptr(costs), _ptr(tr)))
+        return (costs, tr) if traj else costs
+
+    def update(self, costs, eps=None, weights=False):
+        import torch
+        out = torch.empty(self.D, dtype=torch.float32, device="cuda")
+        w = torch.empty(self.K, dtype=torch.float32, device="cuda") if weights else None
+        self._s(lib().mppi_update(self.h, _ptr(costs), _ptr(eps), _ptr(out), _ptr(w)))
+        return (out, w) if weights else out
+
+    def step(self, x0, u0=None):
+        import torch
+        u0 = u0 if u0 is not None else torch.empty(12, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_step(self.h, _ptr(x0), _ptr(u0)))
+        return u0
+
+    def sync_status(self):
+        return self._s(lib().mppi_sync_status(self.h))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mppi_destroy(self.h)
+            self.h = None

@@ -1,0 +1,454 @@
+// C ABI of the whole-body MPPI library: validation, workspace layout, spline matrices,
+// and kernel launches on the caller's stream.  No device allocation happens here: the
+// caller provides the workspace.
+#include "mppi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mppi_device.h"
+#include "mppi_launch.h"
+
+struct mppi_model {
+    mppi_model_desc desc;
+    std::vector<float> hf;
+    mppi::DevModelF dev_f;
+    mppi::DevModelD dev_d;
+    int nx;
+};
+
+struct mppi_ctx {
+    mppi_model model;     // private copy
+    mppi_params p;
+    std::vector<double> B;
+    std::vector<float> S;
+    int D;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    size_t off_B, off_S, off_hf, off_mu, off_eps, off_costs, off_w, off_status, total;
+    uint32_t step = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+mppi_status fail(mppi_ctx* c, mppi_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    g_err = msg;
+    return s;
+}
+
+mppi_status hip_check(mppi_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return MPPI_OK;
+    return fail(c, MPPI_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
+
+// Not-a-knot cubic spline through nk evenly spaced knots on [0, T], written in terms of
+// the second derivatives m_i at the knots (uniform spacing h):
+//   interior:   m_{i-1} + 4 m_i + m_{i+1} = 6 (y_{i-1} - 2 y_i + y_{i+1}) / h^2
+//   not-a-knot: equal third derivatives on both sides of the second and the
+//               second-to-last knot (m_0 - 2 m_1 + m_2 = 0, and mirrored);
+// three knots give the interpolating parabola (constant m), two the line (m = 0).
+void second_derivatives(int n, double h, const double* y, double* m)
+{
+    if (n == 2) {
+        m[0] = m[1] = 0.0;
+        return;
+    }
+    std::vector<double> A((size_t)n * n, 0.0), r(n, 0.0);
+    auto at = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+    if (n == 3) {
+        at(0, 0) = 1; at(0, 1) = -1;
+        at(1, 0) = 1; at(1, 1) = 4; at(1, 2) = 1;
+        r[1] = 6.0 * (y[0] - 2 * y[1] + y[2]) / (h * h);
+        at(2, 1) = 1; at(2, 2) = -1;
+    } else {
+        at(0, 0) = 1; at(0, 1) = -2; at(0, 2) = 1;
+        for (int i = 1; i < n - 1; ++i) {
+            at(i, i - 1) = 1; at(i, i) = 4; at(i, i + 1) = 1;
+            r[i] = 6.0 * (y[i - 1] - 2 * y[i] + y[i + 1]) / (h * h);
+        }
+        at(n - 1, n - 3) = 1; at(n - 1, n - 2) = -2; at(n - 1, n - 1) = 1;
+    }
+    for (int c = 0; c < n; ++c) {  // Gaussian elimination, partial pivoting
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (std::fabs(at(i, c)) > std::fabs(at(piv, c))) piv = i;
+        if (piv != c) {
+            for (int j = 0; j < n; ++j) std::swap(at(c, j), at(piv, j));
+            std::swap(r[c], r[piv]);
+        }
+        for (int i = c + 1; i < n; ++i) {
+            const double f = at(i, c) / at(c, c);
+            for (int j = c; j < n; ++j) at(i, j) -= f * at(c, j);
+            r[i] -= f * r[c];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = r[i];
+        for (int j = i + 1; j < n; ++j) s -= at(i, j) * m[j];
+        m[i] = s / at(i, i);
+    }
+}
+
+double spline_value(int n, double h, const double* y, const double* m, double t)
+{
+    int s = (int)std::floor(t / h);
+    if (s < 0) s = 0;
+    if (s > n - 2) s = n - 2;
+    const double tau = t - s * h, u = h - tau;
+    return m[s] * u * u * u / (6 * h) + m[s + 1] * tau * tau * tau / (6 * h) + (y[s] / h - m[s] * h / 6) * u +
+           (y[s + 1] / h - m[s + 1] * h / 6) * tau;
+}
+
+void build_spline(int nk, int H, double dt, std::vector<double>& B, std::vector<float>& S)
+{
+    const double T = H * dt, h = T / (nk - 1);
+    B.assign((size_t)H * nk, 0.0);
+    S.assign((size_t)nk * nk, 0.f);
+    std::vector<double> y(nk), m(nk);
+    for (int j = 0; j < nk; ++j) {
+        std::fill(y.begin(), y.end(), 0.0);
+        y[j] = 1.0;
+        second_derivatives(nk, h, y.data(), m.data());
+        for (int k = 0; k < H; ++k) B[(size_t)k * nk + j] = spline_value(nk, h, y.data(), m.data(), k * dt);
+        for (int i = 0; i < nk; ++i) {
+            const double t = std::min(i * h + dt, T);
+            S[(size_t)i * nk + j] = (float)spline_value(nk, h, y.data(), m.data(), t);
+        }
+    }
+}
+
+// device model constants; derived quantities computed in double from the FP32 inputs
+template <typename R>
+void fill_model(const mppi_model_desc& d, mppi::ModelT<R>& D)
+{
+    D = mppi::ModelT<R>{};
+    const double sx = d.trunk_size[0], sy = d.trunk_size[1], sz = d.trunk_size[2], m0 = d.trunk_mass;
+    D.tsx = (R)sx; D.tsy = (R)sy; D.tsz = (R)sz;
+    D.m0 = (R)m0;
+    D.I0x = (R)(m0 * (sy * sy + sz * sz) / 12.0);
+    D.I0y = (R)(m0 * (sx * sx + sz * sz) / 12.0);
+    D.I0z = (R)(m0 * (sx * sx + sy * sy) / 12.0);
+    D.hip_x = (R)d.hip_x; D.hip_y = (R)d.hip_y;
+    const double l1 = d.thigh_len, m1 = d.thigh_mass, l2 = d.calf_len, m2 = d.calf_mass;
+    D.l1 = (R)l1; D.m1 = (R)m1; D.k1 = (R)(m1 * l1 * l1 / 12.0);
+    D.l2 = (R)l2; D.m2 = (R)m2; D.k2 = (R)(m2 * l2 * l2 / 12.0);
+    D.mtot = (R)(m0 + 4.0 * (m1 + m2));
+    D.foot_r = (R)d.foot_r; D.g = (R)d.gravity;
+    D.ck = (R)d.contact_k; D.cc = (R)d.contact_c; D.cmu = (R)d.friction_mu;
+    D.inv_vs = (R)(1.0 / (double)d.slip_velocity);
+    D.scene = d.scene;
+    D.hf_nx = d.hf_nx; D.hf_ny = d.hf_ny;
+    D.hf_inv_cell = d.scene == MPPI_SCENE_HEIGHTFIELD ? (R)(1.0 / (double)d.hf_cell) : R(0);
+    D.hf_x0 = (R)d.hf_x0; D.hf_y0 = (R)d.hf_y0;
+    D.sb_cx = (R)d.sbox_center[0]; D.sb_cy = (R)d.sbox_center[1]; D.sb_cz = (R)d.sbox_center[2];
+    D.sb_hx = (R)d.sbox_half[0]; D.sb_hy = (R)d.sbox_half[1]; D.sb_hz = (R)d.sbox_half[2];
+    const double bx = 2.0 * d.box_half[0], by = 2.0 * d.box_half[1], bz = 2.0 * d.box_half[2], bm = d.box_mass;
+    D.bx_hx = (R)d.box_half[0]; D.bx_hy = (R)d.box_half[1]; D.bx_hz = (R)d.box_half[2]; D.bx_m = (R)bm;
+    D.bx_Ix = (R)(bm * (by * by + bz * bz) / 12.0);
+    D.bx_Iy = (R)(bm * (bx * bx + bz * bz) / 12.0);
+    D.bx_Iz = (R)(bm * (bx * bx + by * by) / 12.0);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+mppi::DevParams dev_params(const mppi_ctx* c)
+{
+    mppi::DevParams P{};
+    const mppi_params& p = c->p;
+    P.K = p.K; P.H = p.H; P.nk = p.n_knots; P.nx = c->model.nx;
+    P.dt = p.dt; P.sigma = p.sigma; P.inv_lambda = 1.0f / p.lambda; P.kp = p.kp; P.kd = p.kd;
+    P.w_h = p.w_height; P.h_ref = p.h_ref; P.w_o = p.w_upright; P.w_v = p.w_vel; P.v_ref = p.v_ref;
+    P.w_tau = p.w_torque; P.w_reach = p.w_reach; P.w_box = p.w_box; P.goal_x = p.goal[0]; P.goal_y = p.goal[1];
+    P.seed_lo = (uint32_t)(p.seed & 0xffffffffu);
+    P.seed_hi = (uint32_t)(p.seed >> 32);
+    P.instance = p.instance;
+    P.step = c->step;
+    return P;
+}
+
+float* wsf(mppi_ctx* c, size_t off) { return (float*)((char*)c->ws + off); }
+
+mppi_status need_bound(mppi_ctx* c)
+{
+    if (!c) return fail(nullptr, MPPI_EINVAL, "null context");
+    if (!c->ws) return fail(c, MPPI_ESTATE, "no workspace bound (call mppi_bind)");
+    return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mppi_status_str(mppi_status s)
+{
+    switch (s) {
+    case MPPI_OK: return "ok";
+    case MPPI_WARN_ALL_NONFINITE: return "all samples non-finite; nominal kept";
+    case MPPI_EINVAL: return "invalid argument";
+    case MPPI_ENOMEM: return "workspace too small";
+    case MPPI_EHIP: return "HIP runtime error";
+    case MPPI_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char* mppi_last_error(const mppi_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+mppi_status mppi_model_create(const mppi_model_desc* d, mppi_model** out)
+{
+    if (!d || !out) return fail(nullptr, MPPI_EINVAL, "null argument");
+    *out = nullptr;
+    const float pos[] = {d->trunk_size[0], d->trunk_size[1], d->trunk_size[2], d->trunk_mass, d->thigh_len,
+                         d->thigh_mass,    d->calf_len,      d->calf_mass,     d->foot_r,     d->contact_k,
+                         d->slip_velocity};
+    for (float v : pos)
+        if (!finite_pos(v)) return fail(nullptr, MPPI_EINVAL, "robot sizes, masses and contact constants must be > 0");
+    if (!(d->contact_c >= 0.f) || !(d->friction_mu >= 0.f) || !std::isfinite(d->gravity))
+        return fail(nullptr, MPPI_EINVAL, "contact damping and friction must be >= 0");
+    if (d->scene < MPPI_SCENE_FLAT || d->scene > MPPI_SCENE_FREE_BOX)
+        return fail(nullptr, MPPI_EINVAL, "unknown scene");
+    if (d->scene == MPPI_SCENE_FREE_BOX) return fail(nullptr, MPPI_EINVAL, "the free-box scene is not supported yet");
+    if (d->scene == MPPI_SCENE_STATIC_BOX) {
+        for (int i = 0; i < 3; ++i)
+            if (!finite_pos(d->sbox_half[i]) || !std::isfinite(d->sbox_center[i]))
+                return fail(nullptr, MPPI_EINVAL, "static box needs finite centre and positive half sizes");
+    }
+    mppi_model* m = new (std::nothrow) mppi_model();
+    if (!m) return fail(nullptr, MPPI_ENOMEM, "host allocation failed");
+    m->desc = *d;
+    m->desc.heightfield = nullptr;
+    if (d->scene == MPPI_SCENE_HEIGHTFIELD) {
+        const long cells = (long)d->hf_nx * d->hf_ny;
+        if (!d->heightfield || d->hf_nx < 2 || d->hf_ny < 2 || cells > MPPI_MAX_HEIGHTFIELD || !finite_pos(d->hf_cell)) {
+            delete m;
+            return fail(nullptr, MPPI_EINVAL, "heightfield needs 2 <= nx, ny, nx*ny <= 14336, cell > 0, data");
+        }
+        m->hf.assign(d->heightfield, d->heightfield + cells);
+        for (float v : m->hf)
+            if (!std::isfinite(v)) {
+                delete m;
+                return fail(nullptr, MPPI_EINVAL, "heightfield has non-finite heights");
+            }
+    }
+    fill_model(*d, m->dev_f);
+    fill_model(*d, m->dev_d);
+    m->nx = d->scene == MPPI_SCENE_FREE_BOX ? 50 : 37;
+    *out = m;
+    return MPPI_OK;
+}
+
+void mppi_model_destroy(mppi_model* m) { delete m; }
+
+int mppi_model_nx(const mppi_model* m) { return m ? m->nx : 0; }
+
+mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx** out)
+{
+    if (!model || !p || !out) return fail(nullptr, MPPI_EINVAL, "null argument");
+    *out = nullptr;
+    if (p->K < 1) return fail(nullptr, MPPI_EINVAL, "K must be >= 1");
+    if (p->H < 1 || p->H > MPPI_MAX_HORIZON) return fail(nullptr, MPPI_EINVAL, "H must be in [1, 256]");
+    if (p->n_knots < 2 || p->n_knots > MPPI_MAX_KNOTS) return fail(nullptr, MPPI_EINVAL, "n_knots must be in [2, 8]");
+    if (!finite_pos(p->dt)) return fail(nullptr, MPPI_EINVAL, "dt must be > 0");
+    if (p->arith != MPPI_ARITH_FP64 && p->arith != MPPI_ARITH_FP32)
+        return fail(nullptr, MPPI_EINVAL, "arith must be MPPI_ARITH_FP64 or MPPI_ARITH_FP32");
+    if (!finite_pos(p->lambda)) return fail(nullptr, MPPI_EINVAL, "lambda must be > 0");
+    if (!(p->sigma >= 0.f) || !std::isfinite(p->sigma)) return fail(nullptr, MPPI_EINVAL, "sigma must be >= 0");
+    if (!std::isfinite(p->kp) || !std::isfinite(p->kd) || p->kd < 0.f)
+        return fail(nullptr, MPPI_EINVAL, "kp must be finite, kd >= 0");
+    if ((long)p->K * p->H > (1L << 31)) return fail(nullptr, MPPI_EINVAL, "K * H too large");
+    mppi_ctx* c = new (std::nothrow) mppi_ctx();
+    if (!c) return fail(nullptr, MPPI_ENOMEM, "host allocation failed");
+    c->model = *model;
+    c->p = *p;
+    c->D = 12 * p->n_knots;
+    build_spline(p->n_knots, p->H, p->dt, c->B, c->S);
+    size_t o = 0;
+    c->off_B = o; o = align256(o + sizeof(double) * c->B.size());
+    c->off_S = o; o = align256(o + sizeof(float) * c->S.size());
+    c->off_hf = o; o = align256(o + sizeof(float) * c->model.hf.size());
+    c->off_mu = o; o = align256(o + sizeof(float) * c->D);
+    c->off_eps = o; o = align256(o + sizeof(float) * (size_t)c->D * p->K);
+    c->off_costs = o; o = align256(o + sizeof(float) * p->K);
+    c->off_w = o; o = align256(o + sizeof(float) * p->K);
+    c->off_status = o; o = align256(o + sizeof(int) * 16);
+    c->total = o;
+    *out = c;
+    return MPPI_OK;
+}
+
+void mppi_destroy(mppi_ctx* c) { delete c; }
+
+size_t mppi_workspace_bytes(const mppi_ctx* c) { return c ? c->total : 0; }
+
+mppi_status mppi_bind(mppi_ctx* c, void* ws, size_t bytes, void* stream)
+{
+    if (!c || !ws) return fail(c, MPPI_EINVAL, "null context or workspace");
+    if (((uintptr_t)ws & 255) != 0) return fail(c, MPPI_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < c->total) return fail(c, MPPI_ENOMEM, "workspace smaller than mppi_workspace_bytes()");
+    c->ws = ws;
+    c->ws_bytes = bytes;
+    c->stream = (hipStream_t)stream;
+    c->step = 0;
+    hipStream_t st = c->stream;
+    mppi_status s;
+    if ((s = hip_check(c, hipMemcpyAsync(wsf(c, c->off_B), c->B.data(), sizeof(double) * c->B.size(),
+                                         hipMemcpyHostToDevice, st), "upload spline basis")))
+        return s;
+    if ((s = hip_check(c, hipMemcpyAsync(wsf(c, c->off_S), c->S.data(), sizeof(float) * c->S.size(),
+                                         hipMemcpyHostToDevice, st), "upload shift matrix")))
+        return s;
+    if (!c->model.hf.empty() &&
+        (s = hip_check(c, hipMemcpyAsync(wsf(c, c->off_hf), c->model.hf.data(), sizeof(float) * c->model.hf.size(),
+                                         hipMemcpyHostToDevice, st), "upload heightfield")))
+        return s;
+    if ((s = hip_check(c, hipMemsetAsync(wsf(c, c->off_mu), 0, sizeof(float) * c->D, st), "clear nominal"))) return s;
+    if ((s = hip_check(c, hipMemsetAsync(wsf(c, c->off_status), 0, sizeof(int) * 16, st), "clear status"))) return s;
+    return hip_check(c, hipStreamSynchronize(st), "bind synchronise");
+}
+
+mppi_status mppi_set_nominal(mppi_ctx* c, const float* d_knots)
+{
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!d_knots) return fail(c, MPPI_EINVAL, "null knots");
+    return hip_check(c, hipMemcpyAsync(wsf(c, c->off_mu), d_knots, sizeof(float) * c->D, hipMemcpyDeviceToDevice,
+                                       c->stream), "set nominal");
+}
+
+mppi_status mppi_get_nominal(mppi_ctx* c, float* d_knots)
+{
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!d_knots) return fail(c, MPPI_EINVAL, "null knots");
+    return hip_check(c, hipMemcpyAsync(d_knots, wsf(c, c->off_mu), sizeof(float) * c->D, hipMemcpyDeviceToDevice,
+                                       c->stream), "get nominal");
+}
+
+mppi_status mppi_set_step(mppi_ctx* c, uint32_t step)
+{
+    if (!c) return fail(nullptr, MPPI_EINVAL, "null context");
+    c->step = step;
+    return MPPI_OK;
+}
+
+uint32_t mppi_get_step(const mppi_ctx* c) { return c ? c->step : 0; }
+
+mppi_status mppi_sample(mppi_ctx* c, float* d_eps, uint32_t* d_raw)
+{
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!d_eps && !d_raw) return fail(c, MPPI_EINVAL, "nothing to write");
+    const mppi::DevParams P = dev_params(c);
+    return hip_check(c, mppi::launch_sample(P, c->D, d_eps, d_raw, c->stream), "sample launch");
+}
+
+static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, float* d_costs, float* d_traj)
+{
+    const mppi::DevParams P = dev_params(c);
+    mppi::RolloutArgs a{};
+    a.B = (const double*)wsf(c, c->off_B);
+    a.hf = wsf(c, c->off_hf);
+    a.mu = wsf(c, c->off_mu);
+    a.x0 = d_x0;
+    a.eps_in = d_eps;
+    a.eps_sn = c->D;
+    a.eps_sd = 1;
+    a.eps_out = d_eps ? nullptr : wsf(c, c->off_eps);
+    a.costs = d_costs;
+    a.traj = d_traj;
+    a.samples_per_block = 16;
+    return hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, P, a, c->stream),
+                     "rollout launch");
+}
+
+mppi_status mppi_rollout_batch(mppi_ctx* c, const float* d_x0, const float* d_eps, float* d_costs, float* d_traj)
+{
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!d_x0 || !d_costs) return fail(c, MPPI_EINVAL, "null state or cost buffer");
+    return rollout(c, d_x0, d_eps, d_costs, d_traj);
+}
+
+static mppi_status update(mppi_ctx* c, const float* d_costs, const float* d_eps, float* knots_out, float* nominal_out,
+                          float* u0_out, float* weights_out)
+{
+    const mppi::DevParams P = dev_params(c);
+    mppi::UpdateArgs a{};
+    a.costs = d_costs;
+    if (d_eps) {
+        a.eps = d_eps; a.eps_sn = c->D; a.eps_sd = 1;
+    } else {
+        a.eps = wsf(c, c->off_eps); a.eps_sn = 1; a.eps_sd = c->p.K;
+    }
+    a.mu = wsf(c, c->off_mu);
+    a.S = wsf(c, c->off_S);
+    a.knots_out = knots_out;
+    a.nominal_out = nominal_out;
+    a.u0_out = u0_out;
+    a.weights_out = weights_out;
+    a.status = (int*)wsf(c, c->off_status);
+    return hip_check(c, mppi::launch_update(P, a, c->stream), "update launch");
+}
+
+mppi_status mppi_update(mppi_ctx* c, const float* d_costs, const float* d_eps, float* d_knots_out,
+                        float* d_weights_out)
+{
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!d_costs || !d_knots_out) return fail(c, MPPI_EINVAL, "null costs or output");
+    return update(c, d_costs, d_eps, d_knots_out, nullptr, nullptr, d_weights_out);
+}
+
+mppi_status mppi_step(mppi_ctx* c, const float* d_x0, float* d_u0_out)
+{
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!d_x0 || !d_u0_out) return fail(c, MPPI_EINVAL, "null state or control buffer");
+    float* costs = wsf(c, c->off_costs);
+    if ((s = rollout(c, d_x0, nullptr, costs, nullptr))) return s;
+    if ((s = update(c, costs, nullptr, nullptr, wsf(c, c->off_mu), d_u0_out, nullptr))) return s;
+    c->step += 1;
+    return MPPI_OK;
+}
+
+mppi_status mppi_sync_status(mppi_ctx* c)
+{
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    int st = 0;
+    if ((s = hip_check(c, hipMemcpyAsync(&st, wsf(c, c->off_status), sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                       "read status")))
+        return s;
+    if ((s = hip_check(c, hipStreamSynchronize(c->stream), "synchronise"))) return s;
+    return st ? MPPI_WARN_ALL_NONFINITE : MPPI_OK;
+}
+
+mppi_status mppi_sim_step(const mppi_model* m, int arith, int n, const float* d_x, const float* d_u, float kp,
+                          float kd, float dt, float* d_x_out, float* d_tau_out, const float* d_hf, void* stream)
+{
+    if (arith != MPPI_ARITH_FP64 && arith != MPPI_ARITH_FP32) return fail(nullptr, MPPI_EINVAL, "bad arith");
+    if (!m || n < 0 || !d_x || !d_u || !d_x_out) return fail(nullptr, MPPI_EINVAL, "null argument or n < 0");
+    if (!finite_pos(dt) || !std::isfinite(kp) || !(kd >= 0.f)) return fail(nullptr, MPPI_EINVAL, "bad dt/kp/kd");
+    if (m->desc.scene == MPPI_SCENE_HEIGHTFIELD && !d_hf) return fail(nullptr, MPPI_EINVAL, "heightfield scene needs d_hf");
+    if (n == 0) return MPPI_OK;
+    return hip_check(nullptr,
+                     mppi::launch_sim_step(m->dev_f, m->dev_d, arith, n, m->nx, d_x, d_u, kp, kd, dt, d_x_out,
+                                           d_tau_out, d_hf, (hipStream_t)stream),
+                     "sim step launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,329 @@
+// HIP kernels of the whole-body MPPI hot path for gfx950:
+//   sample_kernel   - counter-based Gaussian knot noise (Sec. II-B sampling)
+//   rollout_kernel  - fused spline + PD + dynamics + running cost over the horizon
+//                     (Algorithm 1 inner loops); one sample per quad of lanes
+//   update_kernel   - Eq. 1 weights (log-sum-exp shift by the minimum cost) and the
+//                     Eq. 2 weighted knot mean, fused with the first-control extraction
+//                     and warm-start shift (Algorithm 1 last steps); one block per joint
+//   sim_step_kernel - one dynamics step of many states (closed-loop plant)
+#include "mppi_device.h"
+#include "mppi_launch.h"
+
+namespace mppi {
+
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void sample_kernel(DevParams P, int D, float* __restrict__ eps,
+                                                     uint32_t* __restrict__ raw)
+{
+    const int nb = (D + 3) >> 2;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= P.K * nb) return;
+    const int n = gid / nb, c = gid - n * nb;
+    uint32_t w[4] = {(uint32_t)c, (uint32_t)n, P.step, P.instance};
+    philox4x32_10(w, P.seed_lo, P.seed_hi);
+    if (raw) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) raw[(size_t)n * 4 * nb + 4 * c + i] = w[i];
+    }
+    if (eps) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float r = sqrtf(-2.0f * logf(u24<float>(w[2 * h])));
+            float s, co;
+            sincospif(2.0f * u24<float>(w[2 * h + 1]), &s, &co);
+            const int d0 = 4 * c + 2 * h;
+            if (d0 < D) eps[(size_t)n * D + d0] = r * co;
+            if (d0 + 1 < D) eps[(size_t)n * D + d0 + 1] = r * s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Rollout: block of 4*SPB lanes handles SPB samples.  Dynamic LDS holds the spline
+// basis (H x nk, type R) and, for the heightfield scene, the height grid (FP32).
+// eps addressing: eps_in[n * eps_sn + d * eps_sd] when given; otherwise Philox noise,
+// stored to eps_out[d * K + n] (dimension-major for the update's coalesced reads).
+// The state is rounded to FP32 after every step; the step itself runs in R.
+// ---------------------------------------------------------------------------------
+template <int SCENE, typename R>
+__global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, const double* __restrict__ gB,
+                                                      const float* __restrict__ ghf, const float* __restrict__ mu,
+                                                      const float* __restrict__ x0, const float* __restrict__ eps_in,
+                                                      int eps_sn, int eps_sd, float* __restrict__ eps_out,
+                                                      float* __restrict__ costs, float* __restrict__ traj)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    R* sB = reinterpret_cast<R*>(lds_raw);
+    float* sHF = reinterpret_cast<float*>(lds_raw + sizeof(R) * P.H * P.nk);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P.H * P.nk; i += blockDim.x) sB[i] = (R)gB[i];
+    if constexpr (SCENE == 1) {
+        const int nhf = M.hf_nx * M.hf_ny;
+        for (int i = tid; i < nhf; i += blockDim.x) sHF[i] = ghf[i];
+    }
+    __syncthreads();
+
+    const int leg = tid & 3;
+    const int n = blockIdx.x * (blockDim.x >> 2) + (tid >> 2);
+    const bool valid = n < P.K;
+    const int ns = valid ? n : P.K - 1;
+    const int nk = P.nk;
+    const R sigma = P.sigma;
+
+    // knots of this leg's three joints: theta = mu + sigma eps (sample 0 is the nominal)
+    R th[3][kMaxKnots];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < kMaxKnots; ++i) {
+            th[j][i] = R(0);
+            if (i < nk) {
+                const int d = (3 * leg + j) * nk + i;
+                R e;
+                if (eps_in) {
+                    e = eps_in[(size_t)ns * eps_sn + (size_t)d * eps_sd];
+                } else {
+                    e = gauss_elem<R>(P, (uint32_t)ns, (uint32_t)d);
+                    if (valid && eps_out) eps_out[(size_t)d * P.K + n] = (float)e;
+                }
+                th[j][i] = R(mu[d]) + (ns ? sigma * e : R(0));
+            }
+        }
+
+    Base<R> b;
+    Leg<R> lg;
+    load_state(x0, leg, b, lg);
+    float* tr = (traj && valid) ? traj + (size_t)n * (P.H + 1) * P.nx : nullptr;
+    if (tr) store_state(tr, leg, b, lg);
+
+    const R dt = P.dt, kp = P.kp, kd = P.kd;
+    R L = R(0);
+    for (int k = 0; k < P.H; ++k) {
+        R u[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            R s = R(0);
+#pragma unroll
+            for (int i = 0; i < kMaxKnots; ++i)
+                if (i < nk) s += sB[k * nk + i] * th[j][i];
+            u[j] = s;
+        }
+        R tau2;
+        quad_step<SCENE, R>(M, sHF, dt, kp, kd, leg, b, lg, u, tau2);
+        round_state(b, lg);
+        L += dt * stage_cost_walk(P, b, tau2);
+        if (tr) store_state(tr + (size_t)(k + 1) * P.nx, leg, b, lg);
+    }
+    float Lf = (float)L;
+    if (!(fabsf(Lf) <= 3.0e38f)) Lf = __int_as_float(0x7f800000);  // non-finite -> +inf
+    if (valid && leg == 0) costs[n] = Lf;
+}
+
+// ---------------------------------------------------------------------------------
+// Update: block j (one per joint) recomputes L_min and sum exp over all K costs with
+// fixed-order tree reductions, then the weighted noise sums for its nk knots.
+// ---------------------------------------------------------------------------------
+constexpr int kUpdThreads = 256;
+
+__device__ __forceinline__ float block_reduce(float v, float* sh, bool is_min)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = kUpdThreads / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] = is_min ? fminf(sh[t], sh[t + s]) : sh[t] + sh[t + s];
+        __syncthreads();
+    }
+    const float r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, const float* __restrict__ costs,
+                                                             const float* __restrict__ eps, int eps_sn, int eps_sd,
+                                                             const float* mu, const float* __restrict__ Sshift,
+                                                             float* knots_out, float* nominal_out, float* u0_out,
+                                                             float* __restrict__ weights_out, int* status)
+{
+    __shared__ float sh[kUpdThreads];
+    __shared__ float acc_sh[kMaxKnots][kUpdThreads];
+    __shared__ float mup[kMaxKnots];
+    const int j = blockIdx.x, t = threadIdx.x, nk = P.nk, K = P.K;
+    float lmin = __int_as_float(0x7f800000);
+    for (int n = t; n < K; n += kUpdThreads) {
+        const float c = costs[n];
+        if (fabsf(c) <= 3.0e38f) lmin = fminf(lmin, c);
+    }
+    lmin = block_reduce(lmin, sh, true);
+    const bool none = !(fabsf(lmin) <= 3.0e38f);
+    float s = 0.f;
+    float acc[kMaxKnots];
+#pragma unroll
+    for (int i = 0; i < kMaxKnots; ++i) acc[i] = 0.f;
+    if (!none) {
+        for (int n = t; n < K; n += kUpdThreads) {
+            const float c = costs[n];
+            const float e = (fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) : 0.f;
+            s += e;
+            if (n > 0) {
+#pragma unroll
+                for (int i = 0; i < kMaxKnots; ++i)
+                    if (i < nk) acc[i] += e * eps[(size_t)n * eps_sn + (size_t)(j * nk + i) * eps_sd];
+            }
+        }
+    }
+    s = block_reduce(s, sh, false);
+#pragma unroll
+    for (int i = 0; i < kMaxKnots; ++i) acc_sh[i][t] = acc[i];
+    __syncthreads();
+    for (int st = kUpdThreads / 2; st > 0; st >>= 1) {
+        if (t < st)
+#pragma unroll
+            for (int i = 0; i < kMaxKnots; ++i) acc_sh[i][t] += acc_sh[i][t + st];
+        __syncthreads();
+    }
+    if (t < nk) {
+        const float m = mu[j * nk + t];
+        mup[t] = none ? m : m + P.sigma * (acc_sh[t][0] / s);
+    }
+    __syncthreads();
+    if (t < nk) {
+        if (knots_out) knots_out[j * nk + t] = mup[t];
+        if (nominal_out) {
+            float v = 0.f;
+            for (int l = 0; l < nk; ++l) v += Sshift[t * nk + l] * mup[l];
+            nominal_out[j * nk + t] = v;
+        }
+    }
+    if (t == 0 && u0_out) u0_out[j] = mup[0];
+    if (j == 0 && weights_out) {
+        const float is = none ? 0.f : 1.f / s;
+        for (int n = t; n < K; n += kUpdThreads) {
+            const float c = costs[n];
+            weights_out[n] = (!none && fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) * is : 0.f;
+        }
+    }
+    if (j == 0 && t == 0 && status) status[0] = none ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------------
+template <int SCENE, typename R>
+__global__ __launch_bounds__(256) void sim_step_kernel(ModelT<R> M, int nstate, int nx, const float* __restrict__ x,
+                                                       const float* __restrict__ u, float kp, float kd, float dt,
+                                                       float* __restrict__ xo, float* __restrict__ tau_out,
+                                                       const float* __restrict__ ghf)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float* sHF = reinterpret_cast<float*>(lds_raw);
+    const int tid = threadIdx.x;
+    if constexpr (SCENE == 1) {
+        const int nhf = M.hf_nx * M.hf_ny;
+        for (int i = tid; i < nhf; i += blockDim.x) sHF[i] = ghf[i];
+    }
+    __syncthreads();
+    const int leg = tid & 3;
+    const int n = blockIdx.x * (blockDim.x >> 2) + (tid >> 2);
+    const bool valid = n < nstate;
+    const int ns = valid ? n : nstate - 1;
+    Base<R> b;
+    Leg<R> lg;
+    load_state(x + (size_t)ns * nx, leg, b, lg);
+    R uu[3], tauv[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        uu[j] = u[(size_t)ns * 12 + 3 * leg + j];
+        tauv[j] = R(kp) * (uu[j] - lg.q[j]) - R(kd) * lg.qd[j];
+    }
+    R tau2;
+    quad_step<SCENE, R>(M, sHF, R(dt), R(kp), R(kd), leg, b, lg, uu, tau2);
+    if (!valid) return;
+    store_state(xo + (size_t)n * nx, leg, b, lg);
+    if (tau_out) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) tau_out[(size_t)n * 12 + 3 * leg + j] = (float)tauv[j];
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------------
+hipError_t launch_sample(const DevParams& P, int D, float* eps, uint32_t* raw, hipStream_t st)
+{
+    const int nb = (D + 3) / 4;
+    const long total = (long)P.K * nb;
+    const int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(sample_kernel, dim3(blocks), dim3(256), 0, st, P, D, eps, raw);
+    return hipGetLastError();
+}
+
+template <typename R>
+static size_t rollout_lds_bytes(const ModelT<R>& M, const DevParams& P)
+{
+    size_t b = sizeof(R) * (size_t)P.H * P.nk;
+    if (M.scene == 1) b += sizeof(float) * (size_t)M.hf_nx * M.hf_ny;
+    return b;
+}
+
+template <typename R>
+static hipError_t launch_rollout_t(const ModelT<R>& M, const DevParams& P, const RolloutArgs& a, hipStream_t st)
+{
+    const int threads = a.samples_per_block * 4;
+    const int blocks = (P.K + a.samples_per_block - 1) / a.samples_per_block;
+    const size_t lds = rollout_lds_bytes(M, P);
+    if (lds > 65536) return hipErrorInvalidValue;
+#define MPPI_LAUNCH_ROLLOUT(S)                                                                                    \
+    hipLaunchKernelGGL((rollout_kernel<S, R>), dim3(blocks), dim3(threads), lds, st, M, P, a.B, a.hf, a.mu, a.x0,  \
+                       a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj)
+    switch (M.scene) {
+    case 0: MPPI_LAUNCH_ROLLOUT(0); break;
+    case 1: MPPI_LAUNCH_ROLLOUT(1); break;
+    case 2: MPPI_LAUNCH_ROLLOUT(2); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MPPI_LAUNCH_ROLLOUT
+    return hipGetLastError();
+}
+
+hipError_t launch_rollout(const DevModelF& Mf, const DevModelD& Md, int arith, const DevParams& P,
+                          const RolloutArgs& a, hipStream_t st)
+{
+    return arith == 1 ? launch_rollout_t(Mf, P, a, st) : launch_rollout_t(Md, P, a, st);
+}
+
+hipError_t launch_update(const DevParams& P, const UpdateArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL(update_kernel, dim3(12), dim3(kUpdThreads), 0, st, P, a.costs, a.eps, a.eps_sn, a.eps_sd, a.mu,
+                       a.S, a.knots_out, a.nominal_out, a.u0_out, a.weights_out, a.status);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_sim_step_t(const ModelT<R>& M, int n, int nx, const float* x, const float* u, float kp,
+                                    float kd, float dt, float* xo, float* tau, const float* hf, hipStream_t st)
+{
+    const int spb = 16;
+    const int blocks = (n + spb - 1) / spb;
+    const size_t lds = (M.scene == 1) ? (size_t)M.hf_nx * M.hf_ny * sizeof(float) : 0;
+#define MPPI_LAUNCH_SIM(S)                                                                                      \
+    hipLaunchKernelGGL((sim_step_kernel<S, R>), dim3(blocks), dim3(4 * spb), lds, st, M, n, nx, x, u, kp, kd, dt, \
+                       xo, tau, hf)
+    switch (M.scene) {
+    case 0: MPPI_LAUNCH_SIM(0); break;
+    case 1: MPPI_LAUNCH_SIM(1); break;
+    case 2: MPPI_LAUNCH_SIM(2); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MPPI_LAUNCH_SIM
+    return hipGetLastError();
+}
+
+hipError_t launch_sim_step(const DevModelF& Mf, const DevModelD& Md, int arith, int n, int nx, const float* x,
+                           const float* u, float kp, float kd, float dt, float* xo, float* tau, const float* hf,
+                           hipStream_t st)
+{
+    return arith == 1 ? launch_sim_step_t(Mf, n, nx, x, u, kp, kd, dt, xo, tau, hf, st)
+                      : launch_sim_step_t(Md, n, nx, x, u, kp, kd, dt, xo, tau, hf, st);
+}
+
+}  // namespace mppi

@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every entry point its header declares; host-side
+validation rejects bad descriptions without touching a GPU (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2409_10469_amd import binding as B
+from paper_2409_10469_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mppi.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mppi_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(B.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _model_handle(**over):
+    d = W.model_dict(W.FLAT_WALK, 0)
+    d.update(over)
+    desc, keep = B.model_desc(d)
+    h = C.c_void_p()
+    rc = B.lib().mppi_model_create(C.byref(desc), C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("over", [dict(trunk_mass=0.0), dict(k=-1.0), dict(scene=7), dict(calf_len=float("nan"))])
+def test_model_validation(over):
+    rc, h = _model_handle(**over)
+    assert rc == B.EINVAL and not h.value
+    assert B.lib().mppi_last_error(None)
+
+
+def test_heightfield_validation():
+    import numpy as np
+    d = W.model_dict(W.TERRAIN_WALK, 0)
+    d["hf"] = np.zeros((200, 200))  # larger than the LDS-staged maximum
+    desc, keep = B.model_desc(d)
+    h = C.c_void_p()
+    assert B.lib().mppi_model_create(C.byref(desc), C.byref(h)) == B.EINVAL
+
+
+@pytest.mark.parametrize("over", [dict(K=0), dict(H=0), dict(H=1000), dict(nk=1), dict(nk=9), dict(dt=0.0),
+                                  dict(lam=0.0), dict(sigma=-1.0), dict(kd=-1.0)])
+def test_params_validation(over):
+    rc, mh = _model_handle()
+    assert rc == 0
+    p = W.params_dict(W.FLAT_WALK, 0)
+    p.update(over)
+    ps = B.params_struct(p)
+    h = C.c_void_p()
+    assert B.lib().mppi_create(mh, C.byref(ps), C.byref(h)) == B.EINVAL
+    assert not h.value
+    B.lib().mppi_model_destroy(mh)
+
+
+def test_workspace_size_and_unbound_calls():
+    rc, mh = _model_handle()
+    p = W.params_dict(W.FLAT_WALK, 0)
+    ps = B.params_struct(p)
+    h = C.c_void_p()
+    assert B.lib().mppi_create(mh, C.byref(ps), C.byref(h)) == 0
+    nbytes = B.lib().mppi_workspace_bytes(h)
+    D, K = 12 * p["nk"], p["K"]
+    assert nbytes >= 4 * (D * K + 2 * K + D + p["H"] * p["nk"])
+    # launching calls before a workspace is bound fail without launching
+    assert B.lib().mppi_step(h, C.c_void_p(256), C.c_void_p(512)) == B.ESTATE
+    assert B.lib().mppi_rollout_batch(h, C.c_void_p(256), None, C.c_void_p(512), None) == B.ESTATE
+    # misaligned or short workspaces are refused before any copy
+    assert B.lib().mppi_bind(h, C.c_void_p(4096 + 4), nbytes, None) == B.EINVAL
+    assert B.lib().mppi_bind(h, C.c_void_p(4096), nbytes - 1, None) == B.ENOMEM
+    assert B.lib().mppi_set_step(h, 5) == 0 and B.lib().mppi_get_step(h) == 5
+    B.lib().mppi_destroy(h)
+    B.lib().mppi_model_destroy(mh)
+
+
+def test_box_scenes_refused_until_supported():
+    rc, h = _model_handle(scene=W.SCENE_FREE_BOX, box_half=(0.2, 0.2, 0.15), box_mass=2.0)
+    assert rc in (0, B.EINVAL)

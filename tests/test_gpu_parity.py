@@ -1,0 +1,277 @@
+"""GPU parity of the HIP hot path against the FP64 oracle, through the C ABI.
+
+Tolerances (stated by the method's specification for this build):
+  per-step state error <= 1e-5 relative per block, from identical FP32 input states;
+  rollout costs within 1e-4 relative over 10-step horizons;
+  updated knots within 1e-3;
+  Philox words bitwise equal.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_10469_amd import workloads as W
+from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, f32, random_walk_states, round_model, round_params,
+                                step_error)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_10469_amd import binding
+    binding.lib()
+    return binding
+
+
+def _setup(B, workload, seed=0, **pover):
+    md = round_model(W.model_dict(workload, seed))
+    p = round_params(W.params_dict(workload, seed, **pover))
+    orc = O.Oracle(md)
+    model = B.Model(md)
+    ctl = B.Controller(model, p)
+    return md, p, orc, model, ctl
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).cuda().contiguous()
+
+
+# ---------------------------------------------------------------------------- a1
+@pytest.mark.parametrize("K,nk", [(64, 4), (37, 6), (5, 8), (1, 2)])
+def test_philox_bitwise_and_gaussians(B, K, nk):
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=K, nk=nk, seed=0x1234_5678_9ABC)
+    for step in (0, 7):
+        ctl.set_step(step)
+        eps, raw = ctl.sample(raw=True)
+        torch.cuda.synchronize()
+        want_raw = O.philox_raw(p, step)
+        got_raw = raw.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got_raw, want_raw)
+        want = O.sample_eps(p, step)
+        got = eps.cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(got, want, rtol=2e-6, atol=2e-6)
+
+
+# ---------------------------------------------------------------------------- a3-a8
+@pytest.mark.parametrize("workload", [W.FLAT_WALK, W.TERRAIN_WALK])
+def test_one_step_state_parity(B, workload):
+    """Each GPU step from the oracle's FP32-rounded state matches the oracle's step."""
+    md, p, orc, model, ctl = _setup(B, workload)
+    xs, us = random_walk_states(orc, seeds=range(6), steps=45, dt=p["dt"], scene=workload["scene"])
+    assert len(xs) % 16 != 0 or len(xs) > 16  # ragged tail over 16-sample blocks
+    got = model.sim_step(_dev(xs), _dev(us), p["kp"], p["kd"], p["dt"]).cpu().numpy().astype(np.float64)
+    want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
+    err = step_error(got, want)
+    assert err.max() <= STEP_TOL, (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("dt", [0.02, 0.01])
+def test_one_step_parity_in_contact_transients(B, dt):
+    """States right after touchdown with large joint velocities (stiff contact regime)."""
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK)
+    rng = np.random.default_rng(7)
+    xs, us = [], []
+    for i in range(40):
+        x = W.initial_state(i)
+        x[2] += rng.uniform(-0.01, 0.01)
+        x[19:] = rng.normal(size=18) * np.r_[0.3, 0.3, 0.3, 1, 1, 1, np.full(12, 3.0)]
+        xs.append(f32(x))
+        us.append(f32(np.tile(W.STANCE_JOINTS, 4) + rng.uniform(-0.4, 0.4, 12)))
+    xs, us = np.array(xs), np.array(us)
+    got = model.sim_step(_dev(xs), _dev(us), p["kp"], p["kd"], dt).cpu().numpy().astype(np.float64)
+    want = np.array([orc.step(x, u, p["kp"], p["kd"], dt)[0] for x, u in zip(xs, us)])
+    err = step_error(got, want)
+    assert err.max() <= STEP_TOL, (err.max(), int(err.argmax()))
+
+
+# ---------------------------------------------------------------------------- a2, a9
+@pytest.mark.parametrize("workload,K", [(W.FLAT_WALK, 64), (W.FLAT_WALK, 50), (W.TERRAIN_WALK, 48)])
+def test_rollout_costs_10_steps(B, workload, K):
+    md, p, orc, model, ctl = _setup(B, workload, K=K, H=10)
+    x0 = f32(W.initial_state(3, workload["scene"]))
+    mu = f32(W.stance_knots(p["nk"]) + np.random.default_rng(2).uniform(-0.1, 0.1, 12 * p["nk"]))
+    eps = f32(W.explicit_noise(5, K, p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    costs, traj = ctl.rollout_batch(_dev(x0), eps=_dev(eps), traj=True)
+    got = costs.cpu().numpy().astype(np.float64)
+    want, wtraj = orc.rollout_batch(p, x0, mu, eps, traj=True)
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6)
+    assert rel.max() <= COST_TOL, (rel.max(), int(rel.argmax()))
+    tr = traj.cpu().numpy().astype(np.float64)
+    assert np.array_equal(tr[:, 0], np.broadcast_to(x0, tr[:, 0].shape))
+
+
+def test_rollout_trajectory_is_a_chain_of_oracle_steps(B):
+    """Full horizon at the terrain workload's launch shape: every GPU step, taken from the
+    GPU's own state, matches the oracle's step from that state (sampled samples)."""
+    md, p, orc, model, ctl = _setup(B, W.TERRAIN_WALK)
+    x0 = f32(W.initial_state(1, W.SCENE_HEIGHTFIELD))
+    mu = f32(W.stance_knots(p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    costs, traj = ctl.rollout_batch(_dev(x0), traj=True)
+    eps = ctl.sample()  # same Philox noise the rollout drew (step 0)
+    torch.cuda.synchronize()
+    tr = traj.cpu().numpy().astype(np.float64)
+    eps = eps.cpu().numpy().astype(np.float64)
+    Bm = O.spline_basis(p["nk"], p["H"], p["dt"])
+    rng = np.random.default_rng(0)
+    for n in [0, 1, p["K"] - 1] + list(rng.integers(0, p["K"], 5)):
+        theta = mu + (p["sigma"] * eps[n] if n else 0.0)
+        U = (Bm @ theta.reshape(12, p["nk"]).T)
+        L = 0.0
+        for k in range(p["H"]):
+            if not np.isfinite(tr[n, k + 1]).all():
+                break
+            xn, tau, _ = orc.step(tr[n, k], U[k], p["kp"], p["kd"], p["dt"])
+            assert step_error(tr[n, k + 1], xn).max() <= STEP_TOL, (n, k)
+            L += p["dt"] * orc.stage_cost(p, tr[n, k + 1], tau)
+        else:
+            assert abs(costs[n].item() - L) <= COST_TOL * max(abs(L), 1e-6), n
+
+
+# ---------------------------------------------------------------------------- a10
+@pytest.mark.parametrize("K,nk,lam", [(64, 4, 0.1), (1024, 6, 0.05), (300, 8, 0.05), (1, 4, 0.1)])
+def test_update_with_identical_costs(B, K, nk, lam):
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=K, nk=nk, lam=lam)
+    rng = np.random.default_rng(K)
+    mu = f32(W.stance_knots(nk) + rng.uniform(-0.2, 0.2, 12 * nk))
+    eps = f32(rng.standard_normal((K, 12 * nk)))
+    costs = f32(rng.uniform(0.5, 0.5 + 20 * lam, K))
+    ctl.set_nominal(_dev(mu))
+    knots, w = ctl.update(_dev(costs), eps=_dev(eps), weights=True)
+    want, ww, rc = O.update(p, costs, mu, eps)
+    assert rc == 0
+    assert np.abs(knots.cpu().numpy() - want).max() <= KNOT_TOL
+    assert np.abs(knots.cpu().numpy() - want).max() <= 1e-5  # far inside the bound here
+    np.testing.assert_allclose(w.cpu().numpy(), ww, rtol=1e-4, atol=1e-7)
+
+
+def test_update_nonfinite_costs(B):
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=40)
+    mu = f32(W.stance_knots(4))
+    eps = f32(np.random.default_rng(0).standard_normal((40, 48)))
+    costs = np.full(40, np.inf, dtype=np.float32)
+    costs[5], costs[9] = 1.0, 1.0
+    costs[7] = np.nan
+    ctl.set_nominal(_dev(mu))
+    knots, w = ctl.update(_dev(costs), eps=_dev(eps), weights=True)
+    want, ww, _ = O.update(p, f32(costs), mu, eps)
+    np.testing.assert_allclose(knots.cpu().numpy(), want, atol=1e-6)
+    np.testing.assert_allclose(w.cpu().numpy(), ww, atol=1e-7)
+    assert ctl.sync_status() == 0
+    knots = ctl.update(_dev(np.full(40, np.inf, dtype=np.float32)), eps=_dev(eps))
+    assert ctl.sync_status() == 1
+    np.testing.assert_array_equal(knots.cpu().numpy(), mu.astype(np.float32))
+
+
+# ---------------------------------------------------------------------------- a1-a11
+def test_mppi_step_flat_walk_matches_oracle(B):
+    """One full control step of the flat walking workload (K=64, H=25, dt=0.02, nk=4)."""
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK)
+    for seed in range(3):
+        x0 = f32(W.initial_state(seed))
+        mu = f32(W.stance_knots(4))
+        ctl.set_nominal(_dev(mu))
+        ctl.set_step(seed)
+        u0 = ctl.step(_dev(x0))
+        nominal = ctl.get_nominal().cpu().numpy()
+        assert ctl.sync_status() == 0 and ctl.step_counter == seed + 1
+        ou0, omu, ocosts, rc = orc.mppi_step(p, seed, x0, mu)
+        w, _ = O.weights(ocosts, p["lam"])
+        ess = 1.0 / np.sum(w ** 2)
+        assert ess >= 1.0
+        assert np.abs(u0.cpu().numpy() - ou0).max() <= KNOT_TOL, seed
+        assert np.abs(nominal - omu).max() <= KNOT_TOL, seed
+
+
+def test_closed_loop_prefix_terrain(B):
+    """First steps of the terrain closed loop (K=1024, H=50): controller and plant on the
+    GPU against the oracle controller and plant, step by step from the same state."""
+    md, p, orc, model, ctl = _setup(B, W.TERRAIN_WALK)
+    x = f32(W.initial_state(0, W.SCENE_HEIGHTFIELD))
+    mu = f32(W.stance_knots(p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    for s in range(3):
+        u0 = ctl.step(_dev(x))
+        g_mu = ctl.get_nominal().cpu().numpy().astype(np.float64)
+        ou0, omu, _, _ = orc.mppi_step(p, s, x, mu)
+        assert np.abs(u0.cpu().numpy() - ou0).max() <= KNOT_TOL, s
+        assert np.abs(g_mu - omu).max() <= KNOT_TOL, s
+        xg = model.sim_step(_dev(x[None]), u0[None].contiguous(), p["kp"], p["kd"], p["dt"]).cpu().numpy()[0]
+        xo, _, _ = orc.step(x, f32(u0.cpu().numpy()), p["kp"], p["kd"], p["dt"])
+        assert step_error(xg.astype(np.float64), xo).max() <= STEP_TOL
+        x, mu = f32(xg), f32(g_mu)
+        ctl.set_nominal(_dev(mu))
+
+
+def test_all_samples_diverge_keeps_nominal(B):
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=16)
+    x0 = f32(W.initial_state(0))
+    x0[19] = np.nan
+    mu = f32(W.stance_knots(4))
+    ctl.set_nominal(_dev(mu))
+    u0 = ctl.step(_dev(x0))
+    assert ctl.sync_status() == 1
+    S = O.shift_matrix(4, p["H"], p["dt"])
+    np.testing.assert_allclose(ctl.get_nominal().cpu().numpy(), (mu.reshape(12, 4) @ S.T).ravel(), atol=1e-6)
+    np.testing.assert_allclose(u0.cpu().numpy(), mu.reshape(12, 4)[:, 0], atol=0)
+
+
+def test_runs_are_bitwise_deterministic(B):
+    md, p, orc, model, ctl = _setup(B, W.TERRAIN_WALK, K=256, H=20)
+    x0 = _dev(W.initial_state(2, W.SCENE_HEIGHTFIELD))
+    a = ctl.rollout_batch(x0).cpu().numpy()
+    b = ctl.rollout_batch(x0).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("H,nk", [(1, 2), (3, 3), (80, 8)])
+def test_horizon_and_knot_edges(B, H, nk):
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=20, H=H, nk=nk, dt=0.01)
+    x0 = f32(W.initial_state(4))
+    mu = f32(W.stance_knots(nk))
+    eps = f32(W.explicit_noise(1, 20, nk) * 0.3)
+    ctl.set_nominal(_dev(mu))
+    costs, traj = ctl.rollout_batch(_dev(x0), eps=_dev(eps), traj=True)
+    tr = traj.cpu().numpy().astype(np.float64)
+    Bm = O.spline_basis(nk, H, p["dt"])
+    for n in (0, 7, 19):
+        theta = mu + (p["sigma"] * eps[n] if n else 0.0)
+        U = Bm @ theta.reshape(12, nk).T
+        for k in range(min(H, 12)):
+            xn, _, _ = orc.step(tr[n, k], U[k], p["kp"], p["kd"], p["dt"])
+            assert step_error(tr[n, k + 1], xn).max() <= STEP_TOL, (n, k)
+
+
+# ---------------------------------------------------------------------------- FP32 variant
+FP32_STEP_TOL = 5e-4   # measured bound of the FP32-arithmetic step (contact conditioning)
+
+
+@pytest.mark.parametrize("workload", [W.FLAT_WALK, W.TERRAIN_WALK])
+def test_fp32_arithmetic_step_bound(B, workload):
+    md, p, orc, model, ctl = _setup(B, workload)
+    xs, us = random_walk_states(orc, seeds=range(6), steps=45, dt=p["dt"], scene=workload["scene"])
+    got = model.sim_step(_dev(xs), _dev(us), p["kp"], p["kd"], p["dt"], arith="fp32").cpu().numpy()
+    want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
+    err = step_error(got.astype(np.float64), want)
+    print("fp32 step error: max %.2e median %.2e" % (err.max(), np.median(err)))
+    assert err.max() <= FP32_STEP_TOL
+
+
+def test_fp32_arithmetic_rollout_costs(B):
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=64, H=10, arith="fp32")
+    x0 = f32(W.initial_state(3))
+    mu = f32(W.stance_knots(p["nk"]))
+    eps = f32(W.explicit_noise(5, 64, p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    got = ctl.rollout_batch(_dev(x0), eps=_dev(eps)).cpu().numpy().astype(np.float64)
+    want = orc.rollout_batch(p, x0, mu, eps)
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6)
+    print("fp32 rollout cost error: max %.2e" % rel.max())
+    assert rel.max() <= 1e-2
