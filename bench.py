@@ -1,0 +1,193 @@
+"""Benchmark of the whole-body MPPI hot path on one MI355X.
+
+One step = one closed-loop control step of the heightfield walking workload
+(K = 1024 samples, horizon H = 50 at dt = 0.01 s, 6 knots per joint): Philox sampling,
+the fused rollout of all samples, the Eq. 1 / Eq. 2 update with first-control
+extraction and shift, and one plant step with the chosen control -- all on the GPU,
+inputs resident in HBM.  Prints one JSON line.
+
+Metric: rollout-steps/s (K * H per control step) and the p50/p99 control-step latency
+(HIP events around each step on the library's stream).  The roofline object reports
+the fused rollout kernel's algorithmic FLOP rate (flops per rollout-step counted from
+the kernel's formulation, times K * H, over its event-timed duration) against the
+MI355X vector peak of the arithmetic type.  cpu_baseline times the FP64 CPU oracle on
+a bounded sample of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic flops per rollout-step of the heightfield scene, counted from the step's
+# formulation (adds, multiplies, divisions, square roots and transcendental calls each
+# count 1) with two feet in ground contact: dynamics 7216, spline 24 * nk, cost 17.
+FLOPS_DYN_PER_STEP = {0: 6832, 1: 7216, 2: 6904}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector peaks (fp32 counts packed issue)
+
+
+def flops_per_rollout_step(scene: int, nk: int) -> int:
+    return FLOPS_DYN_PER_STEP[scene] + 24 * nk + 17
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("mppi_device.h", "mppi_kernels.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2409_10469_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload: str, arith: str):
+    """Counter-measured HBM bytes per rollout launch, if the committed counter summary
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"rollout_{workload}_{arith}_hbm.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(workload, seed, seconds):
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2409_10469_amd import workloads as W
+    md = W.model_dict(workload, seed)
+    p = W.params_dict(workload, seed)
+    orc = O.Oracle(md)
+    x = W.initial_state(seed, workload["scene"])
+    mu = W.stance_knots(p["nk"])
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        u0, mu, _, _ = orc.mppi_step(p, steps, x, mu, nthreads=threads)
+        x, _, _ = orc.step(x, u0, p["kp"], p["kd"], p["dt"])
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    rs = steps * p["K"] * p["H"]
+    return {"value": rs / el, "unit": "rollout-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} closed-loop control steps of {workload['name']} (K={p['K']}, H={p['H']}) "
+                      f"in {el:.1f} s, FP64 oracle, OpenMP over samples"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="heightfield_walk")
+    ap.add_argument("--arith", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU sharding is a design only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2409_10469_amd import binding as B
+    from paper_2409_10469_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wl = W.WORKLOADS[args.workload]
+    md = W.model_dict(wl, args.seed)
+    p = W.params_dict(wl, args.seed, arith=args.arith)
+    model = B.Model(md)
+    ctl = B.Controller(model, p)
+    K, H, nk = p["K"], p["H"], p["nk"]
+    stream = torch.cuda.current_stream()
+
+    x = [torch.tensor(W.initial_state(args.seed, wl["scene"]), dtype=torch.float32, device="cuda"),
+         torch.empty(model.nx, dtype=torch.float32, device="cuda")]
+    ctl.set_nominal(torch.tensor(W.stance_knots(nk), dtype=torch.float32, device="cuda"))
+    costs = torch.empty(K, dtype=torch.float32, device="cuda")
+    u0 = torch.empty(12, dtype=torch.float32, device="cuda")
+
+    def control_step(i, ev=None):
+        xi, xo = x[i % 2], x[(i + 1) % 2]
+        if ev:
+            ev[0].record(stream)
+        ctl.rollout_batch(xi, costs=costs)
+        if ev:
+            ev[1].record(stream)
+        ctl.update_shift(costs, u0)
+        model.sim_step_into(xi.view(1, -1), u0.view(1, -1), p["kp"], p["kd"], p["dt"], xo.view(1, -1),
+                            arith=args.arith)
+        if ev:
+            ev[2].record(stream)
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for i in range(args.warmup):
+        control_step(i)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        control_step(args.warmup + i, evs[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
+    roll_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    status = ctl.sync_status()
+    xf = x[(args.warmup + args.steps) % 2].cpu().numpy()
+
+    value = K * H * args.steps / elapsed
+    flops = flops_per_rollout_step(wl["scene"], nk) * K * H
+    achieved = flops / (roll_ms.mean() * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.arith]
+    out = {
+        "metric": "rollout-steps/sec + p99 MPPI step latency",
+        "value": value,
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.arith == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "K": K, "H": H, "dt": p["dt"], "n_knots": nk, "scene": "heightfield 64x64"
+                   if wl["scene"] == 1 else wl["name"], "closed_loop": True, "state": "f32",
+                   "step_arithmetic": args.arith},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "mean": float(step_ms.mean())},
+        "rollout_kernel_ms": float(roll_ms.mean()),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic_from_profile(wl["name"], args.arith),
+                     "flops_per_rollout_step": flops_per_rollout_step(wl["scene"], nk)},
+        "final_state_finite": bool(np.isfinite(xf).all()),
+        "update_status": int(status),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.seed, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,6 +152,13 @@ mppi_status mppi_update(mppi_ctx *ctx, const float *d_costs, const float *d_eps,
  * and mppi_sync_status reports MPPI_WARN_ALL_NONFINITE. */
 mppi_status mppi_step(mppi_ctx *ctx, const float *d_x0, float *d_u0_out);
 
+/* The second half of mppi_step, for callers that time or overlap the two kernels:
+ * after mppi_rollout_batch(ctx, d_x0, NULL, d_costs, ...) of the current step, computes
+ * the Eq. 1 weights (optionally written to d_weights_out, K floats), the Eq. 2 update,
+ * the first control into d_u0_out, shifts the nominal and advances the step counter.
+ * mppi_step(ctx, x, u) is exactly rollout_batch(x, NULL, costs) + update_shift(costs, u). */
+mppi_status mppi_update_shift(mppi_ctx *ctx, const float *d_costs, float *d_u0_out, float *d_weights_out);
+
 /* Synchronises the bound stream and returns the status of the last update. */
 mppi_status mppi_sync_status(mppi_ctx *ctx);
 

@@ -79,6 +79,7 @@ def lib():
             "mppi_rollout_batch": (C.c_int, [vp, fp, fp, fp, fp]),
             "mppi_update": (C.c_int, [vp, fp, fp, fp, fp]),
             "mppi_step": (C.c_int, [vp, fp, fp]),
+            "mppi_update_shift": (C.c_int, [vp, fp, fp, fp]),
             "mppi_sync_status": (C.c_int, [vp]),
             "mppi_sim_step": (C.c_int, [vp, C.c_int, C.c_int, fp, fp, C.c_float, C.c_float, C.c_float, fp, fp, fp,
                                         vp]),
@@ -180,6 +181,12 @@ class Model:
                                    _ptr(self.hf_device()), _stream(stream)))
         return xo
 
+    def sim_step_into(self, x, u, kp, kd, dt, out, tau_out=None, stream=None, arith="fp64"):
+        """As sim_step, writing into the preallocated `out` (n x nx)."""
+        _check(lib().mppi_sim_step(self.h, ARITH[arith], x.shape[0], _ptr(x), _ptr(u), kp, kd, dt, _ptr(out),
+                                   _ptr(tau_out), _ptr(self.hf_device()), _stream(stream)))
+        return out
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.mppi_model_destroy(self.h)
@@ -251,6 +258,12 @@ class Controller:
         import torch
         u0 = u0 if u0 is not None else torch.empty(12, dtype=torch.float32, device="cuda")
         self._s(lib().mppi_step(self.h, _ptr(x0), _ptr(u0)))
+        return u0
+
+    def update_shift(self, costs, u0=None, weights=None):
+        import torch
+        u0 = u0 if u0 is not None else torch.empty(12, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_update_shift(self.h, _ptr(costs), _ptr(u0), _ptr(weights)))
         return u0
 
     def sync_status(self):

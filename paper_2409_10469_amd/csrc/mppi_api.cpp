@@ -425,6 +425,16 @@ mppi_status mppi_step(mppi_ctx* c, const float* d_x0, float* d_u0_out)
     return MPPI_OK;
 }
 
+mppi_status mppi_update_shift(mppi_ctx* c, const float* d_costs, float* d_u0_out, float* d_weights_out)
+{
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!d_costs || !d_u0_out) return fail(c, MPPI_EINVAL, "null costs or control buffer");
+    if ((s = update(c, d_costs, nullptr, nullptr, wsf(c, c->off_mu), d_u0_out, d_weights_out))) return s;
+    c->step += 1;
+    return MPPI_OK;
+}
+
 mppi_status mppi_sync_status(mppi_ctx* c)
 {
     mppi_status s;
