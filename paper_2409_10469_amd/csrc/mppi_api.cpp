@@ -221,7 +221,11 @@ mppi_status mppi_model_create(const mppi_model_desc* d, mppi_model** out)
         return fail(nullptr, MPPI_EINVAL, "contact damping and friction must be >= 0");
     if (d->scene < MPPI_SCENE_FLAT || d->scene > MPPI_SCENE_FREE_BOX)
         return fail(nullptr, MPPI_EINVAL, "unknown scene");
-    if (d->scene == MPPI_SCENE_FREE_BOX) return fail(nullptr, MPPI_EINVAL, "the free-box scene is not supported yet");
+    if (d->scene == MPPI_SCENE_FREE_BOX) {
+        for (int i = 0; i < 3; ++i)
+            if (!finite_pos(d->box_half[i])) return fail(nullptr, MPPI_EINVAL, "free box needs positive half sizes");
+        if (!finite_pos(d->box_mass)) return fail(nullptr, MPPI_EINVAL, "free box needs a positive mass");
+    }
     if (d->scene == MPPI_SCENE_STATIC_BOX) {
         for (int i = 0; i < 3; ++i)
             if (!finite_pos(d->sbox_half[i]) || !std::isfinite(d->sbox_center[i]))

@@ -492,17 +492,17 @@ struct LegSys {
     R rl[3];                         // dt (tau + J^T F - b), joints
 };
 
-// a contact on this leg's calf at trunk-frame point r
+// a contact on this leg's calf at trunk-frame point r; vo is the velocity of the other
+// body's material point there (trunk coordinates, zero for static geometry) and n points
+// toward the robot.  Returns the force on the robot and the friction secant.
 template <typename R>
 __device__ __forceinline__ void leg_contact(const ModelT<R>& M, const LegGeo<R>& G, V3<R> vb, V3<R> w,
-                                            const R qd[3], R delta, V3<R> n, V3<R> r, R dt, R* Q, R* rb,
-                                            LegSys<R>& S)
+                                            const R qd[3], R delta, V3<R> n, V3<R> r, V3<R> vo, R dt, R* Q, R* rb,
+                                            LegSys<R>& S, V3<R>& F, R& eta)
 {
     const V3<R> ex = v3(R(1), R(0), R(0));
     const V3<R> ja = cross(ex, r - G.h), jf = cross(G.ey, r - G.h), jk = cross(G.ey, r - G.pk);
-    const V3<R> vc = vb + cross(w, r) + qd[0] * ja + qd[1] * jf + qd[2] * jk;
-    V3<R> F;
-    R eta;
+    const V3<R> vc = vb + cross(w, r) + qd[0] * ja + qd[1] * jf + qd[2] * jk - vo;
     contact_law(M, delta, n, vc, F, eta);
     const R ce = M.cc - eta;
     base_contact(eta, M.cc, r, n, F, dt, Q, rb);
@@ -526,16 +526,83 @@ __device__ __forceinline__ void leg_contact(const ModelT<R>& M, const LegGeo<R>&
     S.A22 += dt * (eta * dot(jk, jk) + ce * gj[2] * gj[2]);
 }
 
-// a contact on the trunk at trunk-frame point r
+// a contact on the trunk at trunk-frame point r (vo, n as for leg_contact)
 template <typename R>
 __device__ __forceinline__ void trunk_contact(const ModelT<R>& M, V3<R> vb, V3<R> w, R delta, V3<R> n, V3<R> r,
-                                              R dt, R* Q, R* rb)
+                                              V3<R> vo, R dt, R* Q, R* rb, V3<R>& F, R& eta)
 {
-    const V3<R> vc = vb + cross(w, r);
-    V3<R> F;
-    R eta;
+    const V3<R> vc = vb + cross(w, r) - vo;
     contact_law(M, delta, n, vc, F, eta);
     base_contact(eta, M.cc, r, n, F, dt, Q, rb);
+}
+
+// ------------------------------------------------------------------------------
+// free box (pushing scene): rigid body with generalized velocity [w_b, v_l] in its own
+// body coordinates (v_l = R_b^T v_world), solved like the trunk's base block
+// ------------------------------------------------------------------------------
+template <typename R>
+struct BoxS {
+    V3<R> p;
+    R qw, qx, qy, qz;
+    V3<R> vw, w;
+};
+template <typename R>
+struct BoxFrame {
+    M33<R> Rb;
+    V3<R> vl;  // body-frame linear velocity
+};
+template <typename R>
+__device__ __forceinline__ void load_box(const float* __restrict__ x, BoxS<R>& bx)
+{
+    bx.p = v3<R>(x[37], x[38], x[39]);
+    bx.qw = x[40]; bx.qx = x[41]; bx.qy = x[42]; bx.qz = x[43];
+    bx.vw = v3<R>(x[44], x[45], x[46]);
+    bx.w = v3<R>(x[47], x[48], x[49]);
+}
+template <typename R>
+__device__ __forceinline__ void store_box(float* __restrict__ o, const BoxS<R>& bx)
+{
+    o[37] = (float)bx.p.x; o[38] = (float)bx.p.y; o[39] = (float)bx.p.z;
+    o[40] = (float)bx.qw; o[41] = (float)bx.qx; o[42] = (float)bx.qy; o[43] = (float)bx.qz;
+    o[44] = (float)bx.vw.x; o[45] = (float)bx.vw.y; o[46] = (float)bx.vw.z;
+    o[47] = (float)bx.w.x; o[48] = (float)bx.w.y; o[49] = (float)bx.w.z;
+}
+template <typename R>
+__device__ __forceinline__ void round_box(BoxS<R>& bx)
+{
+    bx.p = v3(to_f32(bx.p.x), to_f32(bx.p.y), to_f32(bx.p.z));
+    bx.qw = to_f32(bx.qw); bx.qx = to_f32(bx.qx); bx.qy = to_f32(bx.qy); bx.qz = to_f32(bx.qz);
+    bx.vw = v3(to_f32(bx.vw.x), to_f32(bx.vw.y), to_f32(bx.vw.z));
+    bx.w = v3(to_f32(bx.w.x), to_f32(bx.w.y), to_f32(bx.w.z));
+}
+// world velocity of the box's material point at world position x
+template <typename R>
+__device__ __forceinline__ V3<R> box_point_vel(const BoxS<R>& bx, const BoxFrame<R>& bf, V3<R> x)
+{
+    return bx.vw + mul(bf.Rb, cross(bx.w, mulT(bf.Rb, x - bx.p)));
+}
+// the box's share of a contact: force Fw (world) on the box at world point x, damping
+// secant eta along normal nw (sign irrelevant), into the box's 6x6 system
+template <typename R>
+__device__ __forceinline__ void box_share(const ModelT<R>& M, const BoxS<R>& bx, const BoxFrame<R>& bf, V3<R> x,
+                                          V3<R> nw, V3<R> Fw, R eta, R dt, R* Qb, R* rbx)
+{
+    base_contact(eta, M.cc, mulT(bf.Rb, x - bx.p), mulT(bf.Rb, nw), mulT(bf.Rb, Fw), dt, Qb, rbx);
+}
+// quaternion update q <- normalize(q (x) exp(dt w / 2)) (body-frame angular velocity)
+template <typename R>
+__device__ __forceinline__ void quat_step(R& qw, R& qx, R& qy, R& qz, V3<R> w, R dt)
+{
+    const V3<R> ph = (R(0.5) * dt) * w;
+    const R a = m_sqrt(dot(ph, ph));
+    const R sc = sinc_q(a);
+    const R dw = m_cos(a), dx = sc * ph.x, dy = sc * ph.y, dz = sc * ph.z;
+    const R nw = qw * dw - qx * dx - qy * dy - qz * dz;
+    const R nx = qw * dx + qx * dw + qy * dz - qz * dy;
+    const R ny = qw * dy - qx * dz + qy * dw + qz * dx;
+    const R nz = qw * dz + qx * dy - qy * dx + qz * dw;
+    const R inv = R(1) / m_sqrt(nw * nw + nx * nx + ny * ny + nz * nz);
+    qw = nw * inv; qx = nx * inv; qy = ny * inv; qz = nz * inv;
 }
 
 // ------------------------------------------------------------------------------
@@ -545,7 +612,7 @@ __device__ __forceinline__ void trunk_contact(const ModelT<R>& M, V3<R> vb, V3<R
 // ------------------------------------------------------------------------------
 template <int SCENE, typename R>
 __device__ __forceinline__ void quad_step(const ModelT<R>& M, const float* __restrict__ hf, R dt, R kp, R kd,
-                                          int leg, Base<R>& b, Leg<R>& lg, const R u[3], R& tau2)
+                                          int leg, Base<R>& b, Leg<R>& lg, BoxS<R>& bx, const R u[3], R& tau2)
 {
     R tau[3];
 #pragma unroll
@@ -652,20 +719,45 @@ __device__ __forceinline__ void quad_step(const ModelT<R>& M, const float* __res
     }
     S.A00 += dt * kd; S.A11 += dt * kd; S.A22 += dt * kd;  // joint damping (implicit)
 
-    // ---- foot (sphere on the calf) against terrain and, in the climbing scene, the box
+    // ---- free box frame and its implicit-system accumulators (pushing scene)
+    [[maybe_unused]] BoxFrame<R> bf;
+    [[maybe_unused]] R Qb[21], rbx[6];
+    const V3<R> zero = v3(R(0), R(0), R(0));
+    V3<R> F;
+    R eta;
+    if constexpr (SCENE == 3) {
+        bf.Rb = quat_R(bx.qw, bx.qx, bx.qy, bx.qz);
+#pragma unroll
+        for (int i = 0; i < 21; ++i) Qb[i] = R(0);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) rbx[i] = R(0);
+    }
+
+    // ---- foot (sphere on the calf) against terrain and the static or free box
     {
         const V3<R> pfw = b.p + mul(Rm, G.pf);
         R delta;
         V3<R> nw;
         if (terrain<SCENE>(M, hf, pfw, M.foot_r, delta, nw)) {
             const V3<R> n = mulT(Rm, nw);
-            leg_contact(M, G, vb, w, lg.qd, delta, n, G.pf - M.foot_r * n, dt, Q, rb, S);
+            leg_contact(M, G, vb, w, lg.qd, delta, n, G.pf - M.foot_r * n, zero, dt, Q, rb, S, F, eta);
         }
         if constexpr (SCENE == 2) {
             const V3<R> l = pfw - v3(M.sb_cx, M.sb_cy, M.sb_cz);
             if (sphere_aabox(l, M.foot_r, v3(M.sb_hx, M.sb_hy, M.sb_hz), delta, nw)) {
                 const V3<R> n = mulT(Rm, nw);
-                leg_contact(M, G, vb, w, lg.qd, delta, n, G.pf - M.foot_r * n, dt, Q, rb, S);
+                leg_contact(M, G, vb, w, lg.qd, delta, n, G.pf - M.foot_r * n, zero, dt, Q, rb, S, F, eta);
+            }
+        }
+        if constexpr (SCENE == 3) {
+            V3<R> nl;
+            if (sphere_aabox(mulT(bf.Rb, pfw - bx.p), M.foot_r, v3(M.bx_hx, M.bx_hy, M.bx_hz), delta, nl)) {
+                const V3<R> nb = mul(bf.Rb, nl);  // box -> foot (world)
+                const V3<R> pcw = pfw - M.foot_r * nb;
+                const V3<R> n = mulT(Rm, nb);
+                const V3<R> vo = mulT(Rm, box_point_vel(bx, bf, pcw));
+                leg_contact(M, G, vb, w, lg.qd, delta, n, G.pf - M.foot_r * n, vo, dt, Q, rb, S, F, eta);
+                box_share(M, bx, bf, pcw, nb, R(-1) * mul(Rm, F), eta, dt, Qb, rbx);
             }
         }
     }
@@ -678,10 +770,43 @@ __device__ __forceinline__ void quad_step(const ModelT<R>& M, const float* __res
         const V3<R> pw = b.p + mul(Rm, rloc);
         R delta;
         V3<R> nw;
-        if (terrain<SCENE>(M, hf, pw, R(0), delta, nw)) trunk_contact(M, vb, w, delta, mulT(Rm, nw), rloc, dt, Q, rb);
+        if (terrain<SCENE>(M, hf, pw, R(0), delta, nw))
+            trunk_contact(M, vb, w, delta, mulT(Rm, nw), rloc, zero, dt, Q, rb, F, eta);
         if constexpr (SCENE == 2) {
             if (point_aabox(pw - v3(M.sb_cx, M.sb_cy, M.sb_cz), v3(M.sb_hx, M.sb_hy, M.sb_hz), delta, nw))
-                trunk_contact(M, vb, w, delta, mulT(Rm, nw), rloc, dt, Q, rb);
+                trunk_contact(M, vb, w, delta, mulT(Rm, nw), rloc, zero, dt, Q, rb, F, eta);
+        }
+        if constexpr (SCENE == 3) {
+            V3<R> nl;
+            if (point_aabox(mulT(bf.Rb, pw - bx.p), v3(M.bx_hx, M.bx_hy, M.bx_hz), delta, nl)) {
+                const V3<R> nb = mul(bf.Rb, nl);  // box face normal, toward the corner
+                const V3<R> vo = mulT(Rm, box_point_vel(bx, bf, pw));
+                trunk_contact(M, vb, w, delta, mulT(Rm, nb), rloc, vo, dt, Q, rb, F, eta);
+                box_share(M, bx, bf, pw, nb, R(-1) * mul(Rm, F), eta, dt, Qb, rbx);
+            }
+        }
+    }
+    // ---- two box corners per lane: against the trunk and the ground
+    if constexpr (SCENE == 3) {
+        const V3<R> th = v3(R(0.5) * M.tsx, R(0.5) * M.tsy, R(0.5) * M.tsz);
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int ci = 2 * leg + cc;
+            const V3<R> cl = v3(ci & 1 ? M.bx_hx : -M.bx_hx, ci & 2 ? M.bx_hy : -M.bx_hy, ci & 4 ? M.bx_hz : -M.bx_hz);
+            const V3<R> xw = bx.p + mul(bf.Rb, cl);
+            R delta;
+            V3<R> nt;
+            const V3<R> lt = mulT(Rm, xw - b.p);
+            if (point_aabox(lt, th, delta, nt)) {  // nt: trunk face normal, toward the box corner
+                const V3<R> vo = mulT(Rm, box_point_vel(bx, bf, xw));
+                trunk_contact(M, vb, w, delta, R(-1) * nt, lt, vo, dt, Q, rb, F, eta);
+                box_share(M, bx, bf, xw, mul(Rm, nt), R(-1) * mul(Rm, F), eta, dt, Qb, rbx);
+            }
+            V3<R> nw;
+            if (terrain<SCENE>(M, hf, xw, R(0), delta, nw)) {
+                contact_law(M, delta, nw, box_point_vel(bx, bf, xw), F, eta);
+                box_share(M, bx, bf, xw, nw, F, eta, dt, Qb, rbx);
+            }
         }
     }
 
@@ -709,6 +834,12 @@ __device__ __forceinline__ void quad_step(const ModelT<R>& M, const float* __res
 #pragma unroll
     for (int i = 0; i < 6; ++i) rb[i] = quad_sum(rb[i]);
     tau2 = quad_sum(t2);
+    if constexpr (SCENE == 3) {
+#pragma unroll
+        for (int i = 0; i < 21; ++i) Qb[i] = quad_sum(Qb[i]);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) rbx[i] = quad_sum(rbx[i]);
+    }
 
     // ---- trunk's own terms: inertia, total mass, gyroscopic and gravity bias
     Q[s6(0, 0)] += M.I0x; Q[s6(1, 1)] += M.I0y; Q[s6(2, 2)] += M.I0z;
@@ -735,27 +866,43 @@ __device__ __forceinline__ void quad_step(const ModelT<R>& M, const float* __res
     b.w = b.w + v3(rb[0], rb[1], rb[2]);
     b.vw = b.vw + mul(Rm, v3(rb[3], rb[4], rb[5]));
     b.p = b.p + dt * b.vw;
-    {
-        const V3<R> ph = (R(0.5) * dt) * b.w;
-        const R a = m_sqrt(dot(ph, ph));
-        const R sc = sinc_q(a);
-        const R dw = m_cos(a), dx = sc * ph.x, dy = sc * ph.y, dz = sc * ph.z;
-        const R nw = b.qw * dw - b.qx * dx - b.qy * dy - b.qz * dz;
-        const R nx = b.qw * dx + b.qx * dw + b.qy * dz - b.qz * dy;
-        const R ny = b.qw * dy - b.qx * dz + b.qy * dw + b.qz * dx;
-        const R nz = b.qw * dz + b.qx * dy - b.qy * dx + b.qz * dw;
-        const R inv = R(1) / m_sqrt(nw * nw + nx * nx + ny * ny + nz * nz);
-        b.qw = nw * inv; b.qx = nx * inv; b.qy = ny * inv; b.qz = nz * inv;
+    quat_step(b.qw, b.qx, b.qy, b.qz, b.w, dt);
+
+    // ---- free box: own 6x6 system (inertia, gyroscopic and gravity terms), then integrate
+    if constexpr (SCENE == 3) {
+        Qb[s6(0, 0)] += M.bx_Ix; Qb[s6(1, 1)] += M.bx_Iy; Qb[s6(2, 2)] += M.bx_Iz;
+        Qb[s6(3, 3)] += M.bx_m; Qb[s6(4, 4)] += M.bx_m; Qb[s6(5, 5)] += M.bx_m;
+        const V3<R> wbx = bx.w;
+        const V3<R> gy = cross(wbx, v3(M.bx_Ix * wbx.x, M.bx_Iy * wbx.y, M.bx_Iz * wbx.z));
+        const V3<R> gl = (-M.g) * v3(bf.Rb.m[6], bf.Rb.m[7], bf.Rb.m[8]);
+        rbx[0] -= dt * gy.x; rbx[1] -= dt * gy.y; rbx[2] -= dt * gy.z;
+        rbx[3] += dt * M.bx_m * gl.x; rbx[4] += dt * M.bx_m * gl.y; rbx[5] += dt * M.bx_m * gl.z;
+        chol6_solve(Qb, rbx);
+        bx.w = bx.w + v3(rbx[0], rbx[1], rbx[2]);
+        bx.vw = bx.vw + mul(bf.Rb, v3(rbx[3], rbx[4], rbx[5]));
+        bx.p = bx.p + dt * bx.vw;
+        quat_step(bx.qw, bx.qx, bx.qy, bx.qz, bx.w, dt);
     }
 }
 
-// running cost at the post-step state (all lanes compute the same value)
-template <typename R>
-__device__ __forceinline__ R stage_cost_walk(const DevParams& P, const Base<R>& b, R tau2)
+// running cost at the post-step state (all lanes compute the same value): height,
+// uprightness, torque, and forward velocity -- or, in the pushing scene, the distance
+// of the trunk to the box and of the box to its goal (xy)
+template <int SCENE, typename R>
+__device__ __forceinline__ R stage_cost(const DevParams& P, const Base<R>& b, const BoxS<R>& bx, R tau2)
 {
     const R Rzz = R(1) - R(2) * (b.qx * b.qx + b.qy * b.qy);
-    const R dz = b.p.z - R(P.h_ref), dv = b.vw.x - R(P.v_ref);
-    return R(P.w_h) * dz * dz + R(P.w_o) * (R(1) - Rzz * Rzz) + R(P.w_v) * dv * dv + R(P.w_tau) * tau2;
+    const R dz = b.p.z - R(P.h_ref);
+    R l = R(P.w_h) * dz * dz + R(P.w_o) * (R(1) - Rzz * Rzz) + R(P.w_tau) * tau2;
+    if constexpr (SCENE == 3) {
+        const R ex = b.p.x - bx.p.x, ey = b.p.y - bx.p.y;
+        const R gx = bx.p.x - R(P.goal_x), gy = bx.p.y - R(P.goal_y);
+        l += R(P.w_reach) * (ex * ex + ey * ey) + R(P.w_box) * (gx * gx + gy * gy);
+    } else {
+        const R dv = b.vw.x - R(P.v_ref);
+        l += R(P.w_v) * dv * dv;
+    }
+    return l;
 }
 
 }  // namespace mppi

@@ -92,9 +92,14 @@ __global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, 
 
     Base<R> b;
     Leg<R> lg;
+    BoxS<R> bx{};
     load_state(x0, leg, b, lg);
+    if constexpr (SCENE == 3) load_box(x0, bx);
     float* tr = (traj && valid) ? traj + (size_t)n * (P.H + 1) * P.nx : nullptr;
-    if (tr) store_state(tr, leg, b, lg);
+    if (tr) {
+        store_state(tr, leg, b, lg);
+        if (SCENE == 3 && leg == 0) store_box(tr, bx);
+    }
 
     const R dt = P.dt, kp = P.kp, kd = P.kd;
     R L = R(0);
@@ -109,10 +114,14 @@ __global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, 
             u[j] = s;
         }
         R tau2;
-        quad_step<SCENE, R>(M, sHF, dt, kp, kd, leg, b, lg, u, tau2);
+        quad_step<SCENE, R>(M, sHF, dt, kp, kd, leg, b, lg, bx, u, tau2);
         round_state(b, lg);
-        L += dt * stage_cost_walk(P, b, tau2);
-        if (tr) store_state(tr + (size_t)(k + 1) * P.nx, leg, b, lg);
+        if constexpr (SCENE == 3) round_box(bx);
+        L += dt * stage_cost<SCENE>(P, b, bx, tau2);
+        if (tr) {
+            store_state(tr + (size_t)(k + 1) * P.nx, leg, b, lg);
+            if (SCENE == 3 && leg == 0) store_box(tr + (size_t)(k + 1) * P.nx, bx);
+        }
     }
     float Lf = (float)L;
     if (!(fabsf(Lf) <= 3.0e38f)) Lf = __int_as_float(0x7f800000);  // non-finite -> +inf
@@ -228,7 +237,9 @@ __global__ __launch_bounds__(256) void sim_step_kernel(ModelT<R> M, int nstate, 
     const int ns = valid ? n : nstate - 1;
     Base<R> b;
     Leg<R> lg;
+    BoxS<R> bx{};
     load_state(x + (size_t)ns * nx, leg, b, lg);
+    if constexpr (SCENE == 3) load_box(x + (size_t)ns * nx, bx);
     R uu[3], tauv[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -236,9 +247,10 @@ __global__ __launch_bounds__(256) void sim_step_kernel(ModelT<R> M, int nstate, 
         tauv[j] = R(kp) * (uu[j] - lg.q[j]) - R(kd) * lg.qd[j];
     }
     R tau2;
-    quad_step<SCENE, R>(M, sHF, R(dt), R(kp), R(kd), leg, b, lg, uu, tau2);
+    quad_step<SCENE, R>(M, sHF, R(dt), R(kp), R(kd), leg, b, lg, bx, uu, tau2);
     if (!valid) return;
     store_state(xo + (size_t)n * nx, leg, b, lg);
+    if (SCENE == 3 && leg == 0) store_box(xo + (size_t)n * nx, bx);
     if (tau_out) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) tau_out[(size_t)n * 12 + 3 * leg + j] = (float)tauv[j];
@@ -279,6 +291,7 @@ static hipError_t launch_rollout_t(const ModelT<R>& M, const DevParams& P, const
     case 0: MPPI_LAUNCH_ROLLOUT(0); break;
     case 1: MPPI_LAUNCH_ROLLOUT(1); break;
     case 2: MPPI_LAUNCH_ROLLOUT(2); break;
+    case 3: MPPI_LAUNCH_ROLLOUT(3); break;
     default: return hipErrorInvalidValue;
     }
 #undef MPPI_LAUNCH_ROLLOUT
@@ -312,6 +325,7 @@ static hipError_t launch_sim_step_t(const ModelT<R>& M, int n, int nx, const flo
     case 0: MPPI_LAUNCH_SIM(0); break;
     case 1: MPPI_LAUNCH_SIM(1); break;
     case 2: MPPI_LAUNCH_SIM(2); break;
+    case 3: MPPI_LAUNCH_SIM(3); break;
     default: return hipErrorInvalidValue;
     }
 #undef MPPI_LAUNCH_SIM

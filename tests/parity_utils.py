@@ -71,3 +71,19 @@ def random_walk_states(orc, seeds, steps, dt, kp=40.0, kd=1.0, scale=0.3, scene=
                 break
             x = f32(xn)
     return np.array(states), np.array(targets)
+
+
+def box_contact_states(n, seed=0):
+    """Robot at stance with random velocities and a free box pressed against its front:
+    trunk corners inside the box, feet against its faces, box corners into the trunk."""
+    rng = np.random.default_rng(seed)
+    xs = []
+    for i in range(n):
+        x = W.initial_state(seed * 1000 + i, W.SCENE_FREE_BOX)
+        x[19:37] = rng.normal(size=18) * np.r_[0.3, 0.3, 0.2, 1, 1, 1, np.full(12, 2.0)]
+        yaw = rng.uniform(-0.9, 0.9)
+        x[37:40] = (rng.uniform(0.33, 0.42), rng.uniform(-0.12, 0.12), W.FREE_BOX_HALF[2] + rng.uniform(-0.004, 0.02))
+        x[40:44] = (np.cos(yaw / 2), 0.0, 0.0, np.sin(yaw / 2))
+        x[44:50] = rng.normal(size=6) * np.r_[0.3, 0.3, 0.1, 0.5, 0.5, 0.5]
+        xs.append(f32(x))
+    return np.array(xs)

@@ -86,6 +86,14 @@ def test_workspace_size_and_unbound_calls():
     B.lib().mppi_model_destroy(mh)
 
 
-def test_box_scenes_refused_until_supported():
+def test_box_scene_validation():
     rc, h = _model_handle(scene=W.SCENE_FREE_BOX, box_half=(0.2, 0.2, 0.15), box_mass=2.0)
-    assert rc in (0, B.EINVAL)
+    assert rc == 0 and B.lib().mppi_model_nx(h) == 50
+    B.lib().mppi_model_destroy(h)
+    rc, h = _model_handle(scene=W.SCENE_FREE_BOX, box_half=(0.2, 0.2, 0.15), box_mass=0.0)
+    assert rc == B.EINVAL
+    rc, h = _model_handle(scene=W.SCENE_STATIC_BOX, sbox_center=(1.1, 0, 0.15), sbox_half=(0.5, 0.5, 0.15))
+    assert rc == 0 and B.lib().mppi_model_nx(h) == 37
+    B.lib().mppi_model_destroy(h)
+    rc, h = _model_handle(scene=W.SCENE_STATIC_BOX, sbox_center=(1.1, 0, 0.15), sbox_half=(0.5, -0.5, 0.15))
+    assert rc == B.EINVAL

@@ -13,8 +13,8 @@ import pytest
 
 from oracle import oracle as O
 from paper_2409_10469_amd import workloads as W
-from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, f32, random_walk_states, round_model, round_params,
-                                step_error)
+from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, box_contact_states, f32, random_walk_states, round_model,
+                                round_params, step_error)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -275,3 +275,87 @@ def test_fp32_arithmetic_rollout_costs(B):
     rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6)
     print("fp32 rollout cost error: max %.2e" % rel.max())
     assert rel.max() <= 1e-2
+
+
+# ---------------------------------------------------------------------------- box scenes
+def test_free_box_contacts_one_step(B):
+    md, p, orc, model, ctl = _setup(B, W.BOX_PUSH)
+    xs = box_contact_states(120, seed=1)
+    rng = np.random.default_rng(3)
+    us = f32(np.tile(W.STANCE_JOINTS, 4) + rng.uniform(-0.3, 0.3, (len(xs), 12)))
+    active = np.array([orc.contact_total(x)[2] for x in xs])
+    assert (active > 4).mean() > 0.5  # most states touch the box
+    got = model.sim_step(_dev(xs), _dev(us), p["kp"], p["kd"], p["dt"]).cpu().numpy().astype(np.float64)
+    want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
+    err = step_error(got, want, box=True)
+    assert err.max() <= STEP_TOL, (err.max(), int(err.argmax()))
+
+
+def test_free_box_resting_and_pushed_rollout(B):
+    """10-step costs with the box against the trunk (contact every step)."""
+    md, p, orc, model, ctl = _setup(B, W.BOX_PUSH, K=48, H=10)
+    x0 = box_contact_states(1, seed=5)[0]
+    x0[19:37] = 0.0
+    x0[44:50] = 0.0
+    mu = f32(W.stance_knots(p["nk"]))
+    eps = f32(W.explicit_noise(2, 48, p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    costs, traj = ctl.rollout_batch(_dev(x0), eps=_dev(eps), traj=True)
+    got = costs.cpu().numpy().astype(np.float64)
+    want = orc.rollout_batch(p, x0, mu, eps)
+    assert np.isfinite(want).all() and np.isfinite(got).all()
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6)
+    assert rel.max() <= COST_TOL, (rel.max(), int(rel.argmax()))
+    tr = traj.cpu().numpy().astype(np.float64)
+    Bm = O.spline_basis(p["nk"], p["H"], p["dt"])
+    for n in (0, 9, 47):
+        theta = mu + (p["sigma"] * eps[n] if n else 0.0)
+        U = Bm @ theta.reshape(12, p["nk"]).T
+        for k in range(p["H"]):
+            xn, _, _ = orc.step(tr[n, k], U[k], p["kp"], p["kd"], p["dt"])
+            assert step_error(tr[n, k + 1], xn, box=True).max() <= STEP_TOL, (n, k)
+
+
+def test_box_push_full_size_chain(B):
+    """The pushing workload at its launch shape (K=4096, H=60): sampled samples are
+    chains of oracle steps."""
+    md, p, orc, model, ctl = _setup(B, W.BOX_PUSH)
+    x0 = f32(W.initial_state(0, W.SCENE_FREE_BOX))
+    x0[37] = 0.45  # box close enough to be reached inside the horizon
+    mu = f32(W.stance_knots(p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    costs, traj = ctl.rollout_batch(_dev(x0), traj=True)
+    eps = ctl.sample().cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    tr = traj.cpu().numpy().astype(np.float64)
+    Bm = O.spline_basis(p["nk"], p["H"], p["dt"])
+    c = costs.cpu().numpy()
+    assert np.isfinite(c).mean() > 0.9
+    for n in [0, 1, p["K"] - 1, int(np.argmin(c))] + list(np.random.default_rng(1).integers(0, p["K"], 3)):
+        theta = mu + (p["sigma"] * eps[n] if n else 0.0)
+        U = Bm @ theta.reshape(12, p["nk"]).T
+        for k in range(0, p["H"], 3):
+            if not np.isfinite(tr[n, k + 1]).all():
+                break
+            xn, _, _ = orc.step(tr[n, k], U[k], p["kp"], p["kd"], p["dt"])
+            assert step_error(tr[n, k + 1], xn, box=True).max() <= STEP_TOL, (n, k)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_static_box_climb_one_step(B, seed):
+    md, p, orc, model, ctl = _setup(B, W.BOX_CLIMB)
+    rng = np.random.default_rng(seed)
+    xs, us = [], []
+    for i in range(60):
+        x = W.initial_state(i)
+        x[0] = rng.uniform(0.2, 0.45)  # front feet and corners near the box face (x = 0.6)
+        x[2] += rng.uniform(-0.005, 0.05)
+        x[19:] = rng.normal(size=18) * np.r_[0.3, 0.3, 0.3, 1, 1, 1, np.full(12, 2.0)]
+        x[7:19] += rng.uniform(-0.5, 0.5, 12)
+        xs.append(f32(x))
+        us.append(f32(np.tile(W.STANCE_JOINTS, 4) + rng.uniform(-0.4, 0.4, 12)))
+    xs, us = np.array(xs), np.array(us)
+    got = model.sim_step(_dev(xs), _dev(us), p["kp"], p["kd"], p["dt"]).cpu().numpy().astype(np.float64)
+    want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
+    err = step_error(got, want)
+    assert err.max() <= STEP_TOL, (err.max(), int(err.argmax()))
