@@ -42,6 +42,7 @@ typedef enum mppi_status {
     MPPI_EINVAL = -1,            /* bad argument; see mppi_last_error */
     MPPI_ENOMEM = -2,            /* workspace too small */
     MPPI_EHIP = -3,              /* a HIP runtime call failed */
+    MPPI_EBUDGET = -5,           /* batched serving: the instance does not fit in the HBM budget */
     MPPI_ESTATE = -6             /* call out of order (e.g. no workspace bound) */
 } mppi_status;
 
@@ -171,6 +172,53 @@ mppi_status mppi_sim_step(const mppi_model *model, int arith, int n, const float
 
 const char *mppi_status_str(mppi_status s);
 const char *mppi_last_error(const mppi_ctx *ctx);
+
+/* ---------------------------------------------------------------------------------
+ * Batched serving: many independent MPPI instances (own model, K, H, knots, state)
+ * advanced together, one graph launch per control step.  Each step every live
+ * instance samples, rolls out, updates and shifts its nominal exactly as mppi_step
+ * does (same Philox counters: step counter per instance, instance id from its params),
+ * then advances its own state by one plant step with the new first control and adds
+ * dt * running cost to its accumulated cost (closed loop on the GPU).
+ *
+ * Work is split into tiles of 16 samples popped from a device queue by a persistent
+ * kernel; the workgroup finishing an instance's last tile runs its update.  The
+ * caller's workspace is the HBM budget: a control region (mppi_batch_control_bytes)
+ * followed by a pool from which instances are allocated first-fit.
+ * --------------------------------------------------------------------------------- */
+#define MPPI_BATCH_MAX_MODELS 8
+typedef struct mppi_batch mppi_batch;
+
+/* max_horizon and max_hf_cells size the LDS stage (8 B x max_horizon x 8 knots + 4 B x
+ * max_hf_cells <= 64 KiB in FP64 arithmetic).  EINVAL on out-of-range limits. */
+mppi_status mppi_batch_create(int max_instances, int max_horizon, int max_hf_cells, int arith, mppi_batch **out);
+void mppi_batch_destroy(mppi_batch *b);
+size_t mppi_batch_control_bytes(int max_instances, int arith);
+/* binds the workspace (256-byte aligned) and stream; forgets all models and instances */
+mppi_status mppi_batch_bind(mppi_batch *b, void *d_workspace, size_t bytes, void *hip_stream);
+/* registers a model (copies its heightfield into the pool); up to MPPI_BATCH_MAX_MODELS */
+mppi_status mppi_batch_add_model(mppi_batch *b, const mppi_model *model, int *slot_out);
+/* admits an instance with HOST initial state x0 (nx) and nominal mu (12 * n_knots);
+ * MPPI_EBUDGET if it does not fit in the remaining pool or the table is full
+ * (nothing is changed then; the caller may queue the request).  K <= 4096,
+ * H <= max_horizon. */
+mppi_status mppi_batch_admit(mppi_batch *b, int model_slot, const mppi_params *params, const float *x0,
+                             const float *mu, int *id_out);
+/* releases an instance; its memory is reused only by later stream-ordered admissions */
+mppi_status mppi_batch_remove(mppi_batch *b, int id);
+/* one control step of every live instance: one graph launch on the bound stream */
+mppi_status mppi_batch_step(mppi_batch *b);
+/* persistent grid = blocks_per_cu x compute units; order 1 = longest horizon first */
+mppi_status mppi_batch_set_tuning(mppi_batch *b, int blocks_per_cu, int order);
+/* times `steps` control steps for each candidate tuning on the current instances and
+ * keeps the fastest (advances every instance by the steps it runs) */
+mppi_status mppi_batch_autotune(mppi_batch *b, int steps, int *best_blocks_per_cu, int *best_order, float *best_ms);
+/* synchronises and copies one instance's state, first control, nominal, accumulated
+ * cost and step counter to HOST memory (NULL to skip) */
+mppi_status mppi_batch_read(mppi_batch *b, int id, float *x, float *u0, float *mu, float *cost_acc, uint32_t *step);
+mppi_status mppi_batch_stats(const mppi_batch *b, int *n_live, int *total_tiles, size_t *bytes_used,
+                             size_t *bytes_pool);
+const char *mppi_batch_last_error(const mppi_batch *b);
 
 #ifdef __cplusplus
 }

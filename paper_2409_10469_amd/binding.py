@@ -273,3 +273,101 @@ class Controller:
         if getattr(self, "h", None) and _lib is not None:
             _lib.mppi_destroy(self.h)
             self.h = None
+
+
+class Batch:
+    """Batched serving of many MPPI instances (one graph launch per control step)."""
+
+    def __init__(self, max_instances, budget_bytes, max_horizon=80, max_hf_cells=4096, arith="fp64", stream=None):
+        import torch
+        L = lib()
+        if not hasattr(L, "_batch_sigs"):
+            vp = C.c_void_p
+            sig = {
+                "mppi_batch_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+                "mppi_batch_destroy": (None, [vp]),
+                "mppi_batch_control_bytes": (C.c_size_t, [C.c_int, C.c_int]),
+                "mppi_batch_bind": (C.c_int, [vp, vp, C.c_size_t, vp]),
+                "mppi_batch_add_model": (C.c_int, [vp, vp, C.POINTER(C.c_int)]),
+                "mppi_batch_admit": (C.c_int, [vp, C.c_int, C.POINTER(Params), vp, vp, C.POINTER(C.c_int)]),
+                "mppi_batch_remove": (C.c_int, [vp, C.c_int]),
+                "mppi_batch_step": (C.c_int, [vp]),
+                "mppi_batch_set_tuning": (C.c_int, [vp, C.c_int, C.c_int]),
+                "mppi_batch_autotune": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                                  C.POINTER(C.c_float)]),
+                "mppi_batch_read": (C.c_int, [vp, C.c_int, vp, vp, vp, vp, vp]),
+                "mppi_batch_stats": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_size_t),
+                                               C.POINTER(C.c_size_t)]),
+                "mppi_batch_last_error": (C.c_char_p, [vp]),
+            }
+            for name, (res, args) in sig.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            L._batch_sigs = True
+        self.L = L
+        h = C.c_void_p()
+        self._chk(L.mppi_batch_create(max_instances, max_horizon, max_hf_cells, ARITH[arith], C.byref(h)))
+        self.h = h
+        ctrl = L.mppi_batch_control_bytes(max_instances, ARITH[arith])
+        total = ctrl + int(budget_bytes)
+        self.ws = torch.empty(total + 256, dtype=torch.uint8, device="cuda")
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off:off + total]
+        self.models = []
+        self._chk(L.mppi_batch_bind(h, C.c_void_p(self.ws_view.data_ptr()), total, _stream(stream)))
+
+    def _chk(self, status):
+        if status < 0:
+            raise MppiError(status, self.L.mppi_batch_last_error(getattr(self, "h", None)).decode())
+        return status
+
+    def add_model(self, model: "Model") -> int:
+        slot = C.c_int()
+        self._chk(self.L.mppi_batch_add_model(self.h, model.h, C.byref(slot)))
+        self.models.append(model)
+        return slot.value
+
+    def admit(self, slot: int, p: dict, x0, mu):
+        """Returns the instance id, or None if it does not fit in the budget."""
+        ps = params_struct(p)
+        x0 = np.ascontiguousarray(x0, dtype=np.float32)
+        mu = np.ascontiguousarray(mu, dtype=np.float32)
+        i = C.c_int()
+        rc = self.L.mppi_batch_admit(self.h, slot, C.byref(ps), x0.ctypes.data_as(C.c_void_p),
+                                     mu.ctypes.data_as(C.c_void_p), C.byref(i))
+        if rc == -5:
+            return None
+        self._chk(rc)
+        return i.value
+
+    def remove(self, i):
+        self._chk(self.L.mppi_batch_remove(self.h, int(i)))
+
+    def step(self):
+        self._chk(self.L.mppi_batch_step(self.h))
+
+    def set_tuning(self, blocks_per_cu, order):
+        self._chk(self.L.mppi_batch_set_tuning(self.h, blocks_per_cu, order))
+
+    def autotune(self, steps=3):
+        bb, bo, ms = C.c_int(), C.c_int(), C.c_float()
+        self._chk(self.L.mppi_batch_autotune(self.h, steps, C.byref(bb), C.byref(bo), C.byref(ms)))
+        return bb.value, bo.value, ms.value
+
+    def read(self, i, nx, nk):
+        x, u0, mu = np.zeros(nx, np.float32), np.zeros(12, np.float32), np.zeros(12 * nk, np.float32)
+        acc, step = np.zeros(1, np.float32), np.zeros(1, np.uint32)
+        vp = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._chk(self.L.mppi_batch_read(self.h, int(i), vp(x), vp(u0), vp(mu), vp(acc), vp(step)))
+        return x, u0, mu, float(acc[0]), int(step[0])
+
+    def stats(self):
+        n, t, u, pool = C.c_int(), C.c_int(), C.c_size_t(), C.c_size_t()
+        self._chk(self.L.mppi_batch_stats(self.h, C.byref(n), C.byref(t), C.byref(u), C.byref(pool)))
+        return dict(live=n.value, tiles=t.value, bytes_used=u.value, bytes_pool=pool.value)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mppi_batch_destroy(self.h)
+            self.h = None

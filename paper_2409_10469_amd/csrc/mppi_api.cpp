@@ -191,6 +191,24 @@ mppi_status need_bound(mppi_ctx* c)
 
 }  // namespace
 
+namespace mppi_host {
+bool model_info(const mppi_model* m, int* scene, int* nx, const float** hf, int* hf_cells, const void** dev_f,
+                const void** dev_d)
+{
+    *scene = m->desc.scene;
+    *nx = m->nx;
+    *hf = m->hf.empty() ? nullptr : m->hf.data();
+    *hf_cells = (int)m->hf.size();
+    *dev_f = &m->dev_f;
+    *dev_d = &m->dev_d;
+    return true;
+}
+void spline_matrices(int nk, int H, double dt, std::vector<double>& B, std::vector<float>& S)
+{
+    build_spline(nk, H, dt, B, S);
+}
+}  // namespace mppi_host
+
 extern "C" {
 
 const char* mppi_status_str(mppi_status s)
@@ -202,6 +220,7 @@ const char* mppi_status_str(mppi_status s)
     case MPPI_ENOMEM: return "workspace too small";
     case MPPI_EHIP: return "HIP runtime error";
     case MPPI_ESTATE: return "call out of order";
+    case MPPI_EBUDGET: return "does not fit in the HBM budget";
     }
     return "unknown status";
 }

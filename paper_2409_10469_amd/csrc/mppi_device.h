@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mppi_launch.h"
+
 namespace mppi {
 
 constexpr int kMaxKnots = 8;
@@ -49,12 +51,6 @@ struct ModelT {
 using DevModelF = ModelT<float>;
 using DevModelD = ModelT<double>;
 
-struct DevParams {
-    int K, H, nk, nx;
-    float dt, sigma, inv_lambda, kp, kd;
-    float w_h, h_ref, w_o, w_v, v_ref, w_tau, w_reach, w_box, goal_x, goal_y;
-    uint32_t seed_lo, seed_hi, instance, step;
-};
 
 // ------------------------------------------------------------------------------
 // math wrappers for both arithmetic types

@@ -39,44 +39,35 @@ __global__ __launch_bounds__(256) void sample_kernel(DevParams P, int D, float* 
 }
 
 // ---------------------------------------------------------------------------------
-// Rollout: block of 4*SPB lanes handles SPB samples.  Dynamic LDS holds the spline
-// basis (H x nk, type R) and, for the heightfield scene, the height grid (FP32).
+// Rollout of the samples of one workgroup: quad q of the block handles sample
+// n = n_base + q.  sB (spline basis, type R) and sHF (heightfield) are in LDS.
 // eps addressing: eps_in[n * eps_sn + d * eps_sd] when given; otherwise Philox noise,
 // stored to eps_out[d * K + n] (dimension-major for the update's coalesced reads).
 // The state is rounded to FP32 after every step; the step itself runs in R.
 // ---------------------------------------------------------------------------------
 template <int SCENE, typename R>
-__global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, const double* __restrict__ gB,
-                                                      const float* __restrict__ ghf, const float* __restrict__ mu,
-                                                      const float* __restrict__ x0, const float* __restrict__ eps_in,
-                                                      int eps_sn, int eps_sd, float* __restrict__ eps_out,
-                                                      float* __restrict__ costs, float* __restrict__ traj)
+__device__ __forceinline__ void rollout_samples(const ModelT<R>& M, const DevParams& P, const R* sB, const float* sHF,
+                                                R* sTh,
+                                                const float* __restrict__ mu, const float* __restrict__ x0,
+                                                const float* __restrict__ eps_in, int eps_sn, int eps_sd,
+                                                float* __restrict__ eps_out, float* __restrict__ costs,
+                                                float* __restrict__ traj, int n_base)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    R* sB = reinterpret_cast<R*>(lds_raw);
-    float* sHF = reinterpret_cast<float*>(lds_raw + sizeof(R) * P.H * P.nk);
     const int tid = threadIdx.x;
-    for (int i = tid; i < P.H * P.nk; i += blockDim.x) sB[i] = (R)gB[i];
-    if constexpr (SCENE == 1) {
-        const int nhf = M.hf_nx * M.hf_ny;
-        for (int i = tid; i < nhf; i += blockDim.x) sHF[i] = ghf[i];
-    }
-    __syncthreads();
-
     const int leg = tid & 3;
-    const int n = blockIdx.x * (blockDim.x >> 2) + (tid >> 2);
+    const int n = n_base + (tid >> 2);
     const bool valid = n < P.K;
     const int ns = valid ? n : P.K - 1;
     const int nk = P.nk;
     const R sigma = P.sigma;
 
-    // knots of this leg's three joints: theta = mu + sigma eps (sample 0 is the nominal)
-    R th[3][kMaxKnots];
+    // knots of this leg's three joints, theta = mu + sigma eps (sample 0 is the nominal),
+    // kept in LDS (sTh: 3 * kMaxKnots values per lane) to spare registers
+    R* th = sTh + (size_t)tid * 3 * kMaxKnots;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int i = 0; i < kMaxKnots; ++i) {
-            th[j][i] = R(0);
             if (i < nk) {
                 const int d = (3 * leg + j) * nk + i;
                 R e;
@@ -86,7 +77,7 @@ __global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, 
                     e = gauss_elem<R>(P, (uint32_t)ns, (uint32_t)d);
                     if (valid && eps_out) eps_out[(size_t)d * P.K + n] = (float)e;
                 }
-                th[j][i] = R(mu[d]) + (ns ? sigma * e : R(0));
+                th[j * kMaxKnots + i] = R(mu[d]) + (ns ? sigma * e : R(0));
             }
         }
 
@@ -110,7 +101,7 @@ __global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, 
             R s = R(0);
 #pragma unroll
             for (int i = 0; i < kMaxKnots; ++i)
-                if (i < nk) s += sB[k * nk + i] * th[j][i];
+                if (i < nk) s += sB[k * nk + i] * th[j * kMaxKnots + i];
             u[j] = s;
         }
         R tau2;
@@ -126,6 +117,33 @@ __global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, 
     float Lf = (float)L;
     if (!(fabsf(Lf) <= 3.0e38f)) Lf = __int_as_float(0x7f800000);  // non-finite -> +inf
     if (valid && leg == 0) costs[n] = Lf;
+}
+
+template <typename R>
+__device__ __forceinline__ void stage_lds(const DevParams& P, int scene, int hf_cells, const double* __restrict__ gB,
+                                          const float* __restrict__ ghf, R* sB, float* sHF)
+{
+    for (int i = threadIdx.x; i < P.H * P.nk; i += blockDim.x) sB[i] = (R)gB[i];
+    if (scene == 1)
+        for (int i = threadIdx.x; i < hf_cells; i += blockDim.x) sHF[i] = ghf[i];
+}
+
+// standalone rollout: block of 4*SPB lanes handles SPB consecutive samples
+template <int SCENE, typename R>
+__global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, const double* __restrict__ gB,
+                                                      const float* __restrict__ ghf, const float* __restrict__ mu,
+                                                      const float* __restrict__ x0, const float* __restrict__ eps_in,
+                                                      int eps_sn, int eps_sd, float* __restrict__ eps_out,
+                                                      float* __restrict__ costs, float* __restrict__ traj)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    R* sB = reinterpret_cast<R*>(lds_raw);
+    R* sTh = sB + P.H * P.nk;
+    float* sHF = reinterpret_cast<float*>(sTh + blockDim.x * 3 * kMaxKnots);
+    stage_lds(P, SCENE, M.hf_nx * M.hf_ny, gB, ghf, sB, sHF);
+    __syncthreads();
+    rollout_samples<SCENE, R>(M, P, sB, sHF, sTh, mu, x0, eps_in, eps_sn, eps_sd, eps_out, costs, traj,
+                              blockIdx.x * (blockDim.x >> 2));
 }
 
 // ---------------------------------------------------------------------------------
@@ -258,6 +276,140 @@ __global__ __launch_bounds__(256) void sim_step_kernel(ModelT<R> M, int nstate, 
 }
 
 // ---------------------------------------------------------------------------------
+// Batched serving: a persistent kernel of one-wave workgroups pops (instance, tile)
+// items from an atomic queue; a tile is 16 samples of one instance.  The workgroup that
+// completes an instance's last tile runs that instance's tail: Eq. 1 weights, the Eq. 2
+// update, first control, shift, one plant step of the instance's state with that control
+// and its running cost.  No workgroup ever waits on another; the last workgroup to find
+// the queue empty resets it for the next launch, so the same graph can be replayed.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int SCENE, typename R>
+__device__ __forceinline__ void plant_step(const ModelT<R>& M, const DevParams& P, const float* sHF, float* x,
+                                           const float* u0, float* cost_acc)
+{
+    const int leg = threadIdx.x & 3;
+    Base<R> b;
+    Leg<R> lg;
+    BoxS<R> bx{};
+    load_state(x, leg, b, lg);
+    if constexpr (SCENE == 3) load_box(x, bx);
+    R u[3] = {R(u0[3 * leg]), R(u0[3 * leg + 1]), R(u0[3 * leg + 2])};
+    R tau2;
+    quad_step<SCENE, R>(M, sHF, R(P.dt), R(P.kp), R(P.kd), leg, b, lg, bx, u, tau2);
+    const R l = stage_cost<SCENE>(P, b, bx, tau2);
+    __syncthreads();  // every lane has read x
+    if (threadIdx.x < 4) {
+        store_state(x, leg, b, lg);
+        if (SCENE == 3 && leg == 0) store_box(x, bx);
+        if (leg == 0) cost_acc[0] += (float)(R(P.dt) * l);
+    }
+}
+
+template <int SCENE, typename R>
+__device__ __forceinline__ void instance_tail(const InstDesc& I, const DevParams& P, const ModelT<R>& M, const float* sHF,
+                              float* sMup)
+{
+    const int t = threadIdx.x, K = P.K, nk = P.nk, D = 12 * nk;
+    float lmin = __int_as_float(0x7f800000);
+    for (int n = t; n < K; n += 64) {
+        const float c = I.costs[n];
+        if (fabsf(c) <= 3.0e38f) lmin = fminf(lmin, c);
+    }
+    lmin = wave_min(lmin);
+    const bool none = !(fabsf(lmin) <= 3.0e38f);
+    float s = 0.f;
+    for (int n = t; n < K; n += 64) {
+        const float c = I.costs[n];
+        const float e = (!none && fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) : 0.f;
+        I.w[n] = e;
+        s += e;
+    }
+    s = wave_sum(s);
+    __syncthreads();  // weights visible to the whole workgroup (one wave)
+    for (int d = 0; d < D; ++d) {
+        float acc = 0.f;
+        for (int n = t; n < K; n += 64)
+            if (n > 0) acc += I.w[n] * I.eps[(size_t)d * K + n];
+        acc = wave_sum(acc);
+        if (t == 0) sMup[d] = none ? I.mu[d] : I.mu[d] + P.sigma * (acc / s);
+    }
+    __syncthreads();
+    if (t < 12) I.u0[t] = sMup[t * nk];
+    for (int q = t; q < D; q += 64) {
+        const int j = q / nk, i = q - j * nk;
+        float v = 0.f;
+        for (int l = 0; l < nk; ++l) v += I.S[i * nk + l] * sMup[j * nk + l];
+        I.mu[q] = v;
+    }
+    __syncthreads();
+    plant_step<SCENE, R>(M, P, sHF, I.x, I.u0, I.cost_acc);
+    if (t == 0) {
+        I.step[0] += 1u;
+        I.done[0] = 0;
+    }
+}
+
+// one persistent kernel per scene: its own queue of that scene's tiles
+template <int SCENE, typename R>
+__global__ __launch_bounds__(64) void batch_kernel(BatchArgs<R> a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int s_tile, s_last;
+    __shared__ float sMup[12 * kMaxKnots];
+    const int total = *a.total_tiles;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(a.head, 1);
+        __syncthreads();
+        // wave-uniform from here on: table rows and models are read with scalar loads
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (t >= total) break;
+        const int i = __builtin_amdgcn_readfirstlane(a.tile_map[t]);
+        const InstDesc& I = a.inst[i];
+        DevParams P = I.P;
+        P.step = I.step[0];
+        const ModelT<R>& M = a.models[__builtin_amdgcn_readfirstlane(I.model)];
+        R* sB = reinterpret_cast<R*>(lds_raw);
+        R* sTh = sB + P.H * P.nk;
+        float* sHF = reinterpret_cast<float*>(sTh + 64 * 3 * kMaxKnots);
+        stage_lds(P, SCENE, I.hf_cells, I.B, I.hf, sB, sHF);
+        __syncthreads();
+        const int n_base = (t - I.tile0) * kTileSamples;
+        rollout_samples<SCENE, R>(M, P, sB, sHF, sTh, I.mu, I.x, nullptr, 0, 0, I.eps, I.costs, nullptr, n_base);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = (atomicAdd(I.done, 1) == I.ntiles - 1);
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            instance_tail<SCENE, R>(I, P, M, sHF, sMup);
+            __threadfence();
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (atomicAdd(a.exited, 1) == (int)gridDim.x - 1) {
+            *a.head = 0;
+            *a.exited = 0;
+            __threadfence();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------------
 hipError_t launch_sample(const DevParams& P, int D, float* eps, uint32_t* raw, hipStream_t st)
@@ -270,9 +422,9 @@ hipError_t launch_sample(const DevParams& P, int D, float* eps, uint32_t* raw, h
 }
 
 template <typename R>
-static size_t rollout_lds_bytes(const ModelT<R>& M, const DevParams& P)
+static size_t rollout_lds_bytes(const ModelT<R>& M, const DevParams& P, int threads)
 {
-    size_t b = sizeof(R) * (size_t)P.H * P.nk;
+    size_t b = sizeof(R) * ((size_t)P.H * P.nk + (size_t)threads * 3 * kMaxKnots);
     if (M.scene == 1) b += sizeof(float) * (size_t)M.hf_nx * M.hf_ny;
     return b;
 }
@@ -282,7 +434,7 @@ static hipError_t launch_rollout_t(const ModelT<R>& M, const DevParams& P, const
 {
     const int threads = a.samples_per_block * 4;
     const int blocks = (P.K + a.samples_per_block - 1) / a.samples_per_block;
-    const size_t lds = rollout_lds_bytes(M, P);
+    const size_t lds = rollout_lds_bytes(M, P, threads);
     if (lds > 65536) return hipErrorInvalidValue;
 #define MPPI_LAUNCH_ROLLOUT(S)                                                                                    \
     hipLaunchKernelGGL((rollout_kernel<S, R>), dim3(blocks), dim3(threads), lds, st, M, P, a.B, a.hf, a.mu, a.x0,  \
@@ -338,6 +490,25 @@ hipError_t launch_sim_step(const DevModelF& Mf, const DevModelD& Md, int arith, 
 {
     return arith == 1 ? launch_sim_step_t(Mf, n, nx, x, u, kp, kd, dt, xo, tau, hf, st)
                       : launch_sim_step_t(Md, n, nx, x, u, kp, kd, dt, xo, tau, hf, st);
+}
+
+template <typename R>
+static hipError_t launch_batch_t(int scene, const BatchArgs<R>& a, int grid, size_t lds, hipStream_t st)
+{
+    switch (scene) {
+    case 0: hipLaunchKernelGGL((batch_kernel<0, R>), dim3(grid), dim3(64), lds, st, a); break;
+    case 1: hipLaunchKernelGGL((batch_kernel<1, R>), dim3(grid), dim3(64), lds, st, a); break;
+    case 2: hipLaunchKernelGGL((batch_kernel<2, R>), dim3(grid), dim3(64), lds, st, a); break;
+    case 3: hipLaunchKernelGGL((batch_kernel<3, R>), dim3(grid), dim3(64), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int arith, int scene, const void* args, int grid, size_t lds, hipStream_t st)
+{
+    if (arith == 1) return launch_batch_t(scene, *static_cast<const BatchArgs<float>*>(args), grid, lds, st);
+    return launch_batch_t(scene, *static_cast<const BatchArgs<double>*>(args), grid, lds, st);
 }
 
 }  // namespace mppi

@@ -9,7 +9,14 @@ template <typename R>
 struct ModelT;
 using DevModelF = ModelT<float>;
 using DevModelD = ModelT<double>;
-struct DevParams;
+
+// per-instance controller parameters as the kernels read them
+struct DevParams {
+    int K, H, nk, nx;
+    float dt, sigma, inv_lambda, kp, kd;
+    float w_h, h_ref, w_o, w_v, v_ref, w_tau, w_reach, w_box, goal_x, goal_y;
+    uint32_t seed_lo, seed_hi, instance, step;
+};
 
 struct RolloutArgs {
     const double* B;       // spline basis H x nk (FP64)
@@ -45,5 +52,45 @@ hipError_t launch_update(const DevParams& P, const UpdateArgs& a, hipStream_t st
 hipError_t launch_sim_step(const DevModelF& Mf, const DevModelD& Md, int arith, int n, int nx, const float* x,
                            const float* u, float kp, float kd, float dt, float* xo, float* tau, const float* hf,
                            hipStream_t st);
+
+}  // namespace mppi
+
+namespace mppi {
+
+// ---------------------------------------------------------------------------------
+// batched serving: one row of the device instance table
+// ---------------------------------------------------------------------------------
+constexpr int kTileSamples = 16;  // samples per 64-lane tile (one sample per quad)
+
+struct InstDesc {
+    DevParams P;                // K, H, nk, nx, dt, sigma, 1/lambda, gains, cost weights, seed, instance
+    int scene, model, ntiles, tile0;
+    int hf_cells, pad0;
+    const double* B;            // spline basis H x nk
+    const float* S;             // shift matrix nk x nk
+    const float* hf;            // heightfield of the model (scene 1)
+    float* x;                   // current state (nx)
+    float* mu;                  // nominal knots (12 nk)
+    float* eps;                 // noise, D x K
+    float* costs;               // K
+    float* w;                   // K unnormalised weights
+    float* u0;                  // last first control (12)
+    float* cost_acc;            // running cost of the closed loop
+    int* done;                  // finished tiles of the current step
+    uint32_t* step;             // control-step counter (Philox counter word)
+};
+
+template <typename R>
+struct BatchArgs {
+    const InstDesc* inst;
+    const ModelT<R>* models;
+    const int* tile_map;        // this scene's tiles -> instance row
+    const int* total_tiles;     // number of this scene's tiles
+    int* head;                  // this scene's work-queue head
+    int* exited;                // blocks that found this scene's queue empty
+};
+
+hipError_t launch_batch(int arith, int scene, const void* args /* BatchArgs<R> */, int grid, size_t lds,
+                        hipStream_t st);
 
 }  // namespace mppi

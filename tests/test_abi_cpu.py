@@ -97,3 +97,17 @@ def test_box_scene_validation():
     B.lib().mppi_model_destroy(h)
     rc, h = _model_handle(scene=W.SCENE_STATIC_BOX, sbox_center=(1.1, 0, 0.15), sbox_half=(0.5, -0.5, 0.15))
     assert rc == B.EINVAL
+
+
+def test_batch_create_validation():
+    L = B.lib()
+    vp = C.c_void_p
+    L.mppi_batch_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]
+    L.mppi_batch_control_bytes.restype = C.c_size_t
+    L.mppi_batch_control_bytes.argtypes = [C.c_int, C.c_int]
+    h = vp()
+    assert L.mppi_batch_create(0, 80, 4096, 0, C.byref(h)) == B.EINVAL
+    assert L.mppi_batch_create(16, 0, 4096, 0, C.byref(h)) == B.EINVAL
+    assert L.mppi_batch_create(16, 80, 4096, 5, C.byref(h)) == B.EINVAL
+    assert L.mppi_batch_create(16, 256, 14336, 0, C.byref(h)) == B.EINVAL  # LDS stage over 64 KiB
+    assert L.mppi_batch_control_bytes(16, 0) > 16 * 256

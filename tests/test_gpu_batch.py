@@ -1,0 +1,158 @@
+"""Batched serving (many MPPI instances per graph launch) against the single-instance
+C-ABI path and the oracle, on the GPU."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_10469_amd import workloads as W
+from tests.parity_utils import KNOT_TOL, STEP_TOL, f32, round_model, round_params, step_error
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_10469_amd import binding
+    binding.lib()
+    return binding
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).cuda().contiguous()
+
+
+SPECS = [  # (workload, K, H, nk, seed, instance id)
+    (W.FLAT_WALK, 64, 25, 4, 0, 3),
+    (W.TERRAIN_WALK, 300, 40, 6, 1, 7),
+    (W.BOX_CLIMB, 100, 30, 6, 2, 11),
+    (W.BOX_PUSH, 257, 20, 8, 3, 12),
+    (W.FLAT_WALK, 17, 10, 2, 4, 40),
+    (W.TERRAIN_WALK, 33, 80, 5, 5, 41),
+]
+
+
+def _init_state(wl, seed):
+    x = W.initial_state(seed, wl["scene"])
+    if wl["scene"] == W.SCENE_FREE_BOX:
+        x[37] = 0.45  # box within reach, so contacts occur
+    return f32(x)
+
+
+def _setup(B, budget=64 << 20, arith="fp64"):
+    batch = B.Batch(max_instances=16, budget_bytes=budget, max_horizon=80, max_hf_cells=4096, arith=arith)
+    slots, models, mds = {}, {}, {}
+    for wl in (W.FLAT_WALK, W.TERRAIN_WALK, W.BOX_CLIMB, W.BOX_PUSH):
+        md = round_model(W.model_dict(wl, 0))
+        m = B.Model(md)
+        slots[wl["name"]] = batch.add_model(m)
+        models[wl["name"]] = m
+        mds[wl["name"]] = md
+    return batch, slots, models, mds
+
+
+def _params(wl, K, H, nk, seed, inst, arith="fp64"):
+    return round_params(W.params_dict(wl, seed, K=K, H=H, nk=nk, instance=inst, arith=arith))
+
+
+def test_batch_matches_single_instance_path(B):
+    batch, slots, models, mds = _setup(B)
+    ids, refs = [], []
+    for wl, K, H, nk, seed, inst in SPECS:
+        p = _params(wl, K, H, nk, seed, inst)
+        x0 = _init_state(wl, seed)
+        mu = f32(W.stance_knots(nk) + np.random.default_rng(seed).uniform(-0.05, 0.05, 12 * nk))
+        ids.append(batch.admit(slots[wl["name"]], p, x0, mu))
+        refs.append((wl, p, x0, mu))
+    assert None not in ids
+    for step in range(2):
+        batch.step()
+        torch.cuda.synchronize()
+        for i, (wl, p, x0, mu) in zip(ids, refs):
+            model = models[wl["name"]]
+            ctl = B.Controller(model, p)
+            ctl.set_nominal(_dev(mu))
+            ctl.set_step(step)
+            u0 = ctl.step(_dev(x0))
+            nominal = ctl.get_nominal().cpu().numpy()
+            x1 = model.sim_step(_dev(x0[None]), u0[None].contiguous(), p["kp"], p["kd"], p["dt"]).cpu().numpy()[0]
+            bx, bu0, bmu, acc, bstep = batch.read(i, model.nx, p["nk"])
+            assert bstep == step + 1
+            assert np.abs(bu0 - u0.cpu().numpy()).max() <= 1e-5, (wl["name"], step)
+            assert np.abs(bmu - nominal).max() <= 1e-5, (wl["name"], step)
+            err = step_error(bx.astype(np.float64), x1.astype(np.float64), box=wl["scene"] == W.SCENE_FREE_BOX)
+            assert err.max() <= STEP_TOL, (wl["name"], step, err.max())
+            assert np.isfinite(acc) and acc > 0
+        # continue both paths from the batch's state and nominal
+        refs = [(wl, p, f32(batch.read(i, models[wl["name"]].nx, p["nk"])[0]),
+                 f32(batch.read(i, models[wl["name"]].nx, p["nk"])[2])) for i, (wl, p, _, _) in zip(ids, refs)]
+
+
+def test_batch_first_step_against_oracle(B):
+    batch, slots, models, mds = _setup(B)
+    wl, K, H, nk, seed, inst = W.TERRAIN_WALK, 200, 30, 6, 9, 2
+    p = _params(wl, K, H, nk, seed, inst)
+    x0 = _init_state(wl, seed)
+    mu = f32(W.stance_knots(nk))
+    i = batch.admit(slots[wl["name"]], p, x0, mu)
+    batch.step()
+    bx, bu0, bmu, acc, _ = batch.read(i, models[wl["name"]].nx, nk)
+    orc = O.Oracle(mds[wl["name"]])
+    ou0, omu, _, _ = orc.mppi_step(p, 0, x0, mu)
+    assert np.abs(bu0 - ou0).max() <= KNOT_TOL
+    assert np.abs(bmu - omu).max() <= KNOT_TOL
+    ox, tau, _ = orc.step(x0, f32(bu0), p["kp"], p["kd"], p["dt"])
+    assert step_error(bx.astype(np.float64), ox).max() <= STEP_TOL
+    assert abs(acc - p["dt"] * orc.stage_cost(p, ox, tau)) <= 1e-4 * abs(acc)
+
+
+def test_admission_budget_and_reuse(B):
+    batch, slots, models, mds = _setup(B, budget=2 << 20)
+    wl = W.TERRAIN_WALK
+    nk = 6
+    admitted = []
+    for n in range(16):
+        p = _params(wl, 1024, 50, nk, n, n)
+        i = batch.admit(slots[wl["name"]], p, _init_state(wl, n), W.stance_knots(nk))
+        if i is None:
+            break
+        admitted.append(i)
+    # 1024 samples x 72 dims of noise is ~0.3 MB: the 2 MB pool holds a handful
+    assert 1 <= len(admitted) < 16
+    st = batch.stats()
+    assert st["live"] == len(admitted) and st["bytes_used"] <= st["bytes_pool"]
+    batch.step()
+    batch.remove(admitted[0])
+    p = _params(wl, 1024, 50, nk, 99, 99)
+    again = batch.admit(slots[wl["name"]], p, _init_state(wl, 99), W.stance_knots(nk))
+    assert again is not None
+    batch.step()
+    batch.step()
+    x, u0, mu, acc, step = batch.read(again, models[wl["name"]].nx, nk)
+    assert step == 2 and np.isfinite(x).all() and np.isfinite(u0).all()
+    x1, _, _, _, step1 = batch.read(admitted[1], models[wl["name"]].nx, nk)
+    assert step1 == 3
+
+
+def test_autotune_and_replay_determinism(B):
+    outs = []
+    for trial in range(2):
+        batch, slots, models, mds = _setup(B)
+        ids = []
+        for wl, K, H, nk, seed, inst in SPECS:
+            p = _params(wl, K, H, nk, seed, inst)
+            ids.append(batch.admit(slots[wl["name"]], p, _init_state(wl, seed), W.stance_knots(nk)))
+        if trial == 0:
+            bb, bo, ms = batch.autotune(steps=1)
+            assert bb in (2, 4, 8, 16) and bo in (0, 1) and ms > 0
+        else:
+            for _ in range(16):  # autotune ran 8 candidates x (1 warm-up + 1 timed) steps
+                batch.step()
+        out = [batch.read(i, models[s[0]["name"]].nx, s[3]) for i, s in zip(ids, SPECS)]
+        outs.append(out)
+    for a, b in zip(*outs):
+        assert a[4] == b[4]
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[2], b[2])
