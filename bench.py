@@ -25,15 +25,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic flops per rollout-step of the heightfield scene, counted from the step's
-# formulation (adds, multiplies, divisions, square roots and transcendental calls each
-# count 1) with two feet in ground contact: dynamics 7216, spline 24 * nk, cost 17.
-FLOPS_DYN_PER_STEP = {0: 6832, 1: 7216, 2: 6904}
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector peaks (fp32 counts packed issue)
-
-
-def flops_per_rollout_step(scene: int, nk: int) -> int:
-    return FLOPS_DYN_PER_STEP[scene] + 24 * nk + 17
+from paper_2409_10469_amd.roofline import PEAK_TFLOPS, flops_per_rollout_step  # noqa: E402
 
 
 def kernel_source_hash() -> str:
@@ -84,7 +76,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="heightfield_walk")
+    ap.add_argument("--workload", default="heightfield_walk",
+                    help="heightfield_walk (default), flat_walk, box_push, box_climb or batched_serving")
     ap.add_argument("--arith", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -106,6 +99,8 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "batched_serving":
+        return bench_serving(args)
     wl = W.WORKLOADS[args.workload]
     md = W.model_dict(wl, args.seed)
     p = W.params_dict(wl, args.seed, arith=args.arith)
@@ -186,6 +181,44 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.seed, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """256 MPPI instances (mixed tasks, K log-uniform in [256, 4096], H uniform in
+    [20, 80]) under a seeded Poisson stream admitted by a 64 MiB HBM budget."""
+    import numpy as np
+    from paper_2409_10469_amd.serving import ServingSim
+    sim = ServingSim(seed=args.seed, arith=args.arith)
+    sim.prefill(256)
+    r = sim.run(args.steps, warmup=args.warmup, autotune=True)
+    lat = r["latency_ms"]
+    value = r["rollout_steps"] / r["elapsed"]
+    achieved = r["flops"] / (lat.sum() * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.arith]
+    qd = r["queue_delay"]
+    out = {
+        "metric": "rollout-steps/sec + p99 MPPI step latency",
+        "value": value, "unit": "rollout-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["elapsed"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.arith == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": "batched_serving", "target_instances": 256, "K": "log-uniform [256, 4096]",
+                   "H": "uniform [20, 80]", "tasks": "flat, heightfield, box climb, box push",
+                   "arrivals": "Poisson, lifetime 200 steps", "hbm_budget_mib": 64, "state": "f32",
+                   "step_arithmetic": args.arith},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean())},
+        "host_admission_ms": {"p50": float(np.percentile(r["host_ms"], 50)),
+                              "p99": float(np.percentile(r["host_ms"], 99))},
+        "live_instances": {"mean": float(r["live"].mean()), "min": int(r["live"].min()), "max": int(r["live"].max())},
+        "queueing_delay_steps": {"mean": float(qd.mean()) if qd.size else 0.0,
+                                 "p99": float(np.percentile(qd, 99)) if qd.size else 0.0},
+        "autotune": {"blocks_per_cu": r["tune"][0], "order": "longest_first" if r["tune"][1] else "admission",
+                     "ms": r["tune"][2]} if r["tune"] else None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None},
+        "budget": r["stats"],
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,117 @@
+#include <cstdio>
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+static long n_add = 0, n_mul = 0, n_div = 0, n_sqrt = 0, n_trans = 0;
+struct CountD {
+    double v;
+    CountD() : v(0) {}
+    CountD(double x) : v(x) {}
+    CountD(float x) : v(x) {}
+    CountD(int x) : v(x) {}
+    explicit operator float() const { return (float)v; }
+    explicit operator double() const { return v; }
+    explicit operator int() const { return (int)v; }
+};
+inline CountD operator+(CountD a, CountD b) { ++n_add; return a.v + b.v; }
+inline CountD operator-(CountD a, CountD b) { ++n_add; return a.v - b.v; }
+inline CountD operator*(CountD a, CountD b) { ++n_mul; return a.v * b.v; }
+inline CountD operator/(CountD a, CountD b) { ++n_div; return a.v / b.v; }
+inline CountD operator-(CountD a) { return -a.v; }
+inline CountD& operator+=(CountD& a, CountD b) { a = a + b; return a; }
+inline CountD& operator-=(CountD& a, CountD b) { a = a - b; return a; }
+inline bool operator<(CountD a, CountD b) { return a.v < b.v; }
+inline bool operator>(CountD a, CountD b) { return a.v > b.v; }
+inline bool operator<=(CountD a, CountD b) { return a.v <= b.v; }
+inline bool operator>=(CountD a, CountD b) { return a.v >= b.v; }
+inline CountD m_sqrt(CountD x) { ++n_sqrt; return std::sqrt(x.v); }
+inline CountD m_abs(CountD x) { return std::fabs(x.v); }
+inline CountD m_min(CountD a, CountD b) { return std::fmin(a.v, b.v); }
+inline CountD m_max(CountD a, CountD b) { return std::fmax(a.v, b.v); }
+inline CountD m_floor(CountD x) { return std::floor(x.v); }
+inline CountD m_tanh(CountD x) { ++n_trans; return std::tanh(x.v); }
+inline CountD m_sin(CountD x) { ++n_trans; return std::sin(x.v); }
+inline CountD m_cos(CountD x) { ++n_trans; return std::cos(x.v); }
+inline void m_sincos(CountD x, CountD* s, CountD* c) { n_trans += 2; *s = std::sin(x.v); *c = std::cos(x.v); }
+inline CountD m_log(CountD x) { ++n_trans; return std::log(x.v); }
+inline CountD sinc_q(CountD a) { ++n_trans; ++n_div; return a.v > 0 ? std::sin(a.v) / a.v : 1.0; }
+template <int C> inline CountD dpp(CountD v) { return v; }
+#include "mppi_device.h"
+using namespace mppi;
+typedef CountD R;
+
+static long total() { return n_add + n_mul + n_div + n_sqrt + n_trans; }
+static void reset() { n_add = n_mul = n_div = n_sqrt = n_trans = 0; }
+
+int main(int argc, char** argv)
+{
+    int scene = argc > 1 ? atoi(argv[1]) : 0;
+    ModelT<R> M{};
+    M.tsx = 0.38; M.tsy = 0.094; M.tsz = 0.114; M.m0 = 5.2;
+    M.I0x = 5.2 * (0.094 * 0.094 + 0.114 * 0.114) / 12; M.I0y = 0.068; M.I0z = 0.066;
+    M.hip_x = 0.188; M.hip_y = 0.047; M.l1 = 0.213; M.m1 = 1.0; M.k1 = 1.0 * 0.213 * 0.213 / 12;
+    M.l2 = 0.213; M.m2 = 0.2; M.k2 = 0.2 * 0.213 * 0.213 / 12; M.mtot = 10; M.foot_r = 0.02; M.g = 9.81;
+    M.ck = 2e4; M.cc = 500; M.cmu = 0.8; M.inv_vs = 100; M.scene = scene;
+    float hf[64 * 64] = {0};
+    M.hf_nx = 64; M.hf_ny = 64; M.hf_inv_cell = 20; M.hf_x0 = -1.575; M.hf_y0 = -1.575;
+    M.bx_hx = 0.2; M.bx_hy = 0.2; M.bx_hz = 0.15; M.bx_m = 2.0; M.bx_Ix = 2.0 * (0.16 + 0.09) / 12;
+    M.bx_Iy = 2.0 * (0.16 + 0.09) / 12; M.bx_Iz = 2.0 * 0.32 / 12;
+    M.sb_cx = 1.1; M.sb_cy = 0; M.sb_cz = 0.15; M.sb_hx = 0.5; M.sb_hy = 0.5; M.sb_hz = 0.15;
+    long lane_sum = 0;
+    for (int leg = 0; leg < 4; ++leg) {
+        Base<R> b;
+        b.p = v3<R>(0.01, 0.02, argc > 2 ? atof(argv[2]) : 0.2806);
+        b.qw = 0.999; b.qx = 0.02; b.qy = -0.03; b.qz = 0.01;
+        b.vw = v3<R>(0.3, -0.1, -0.05);
+        b.w = v3<R>(0.2, -0.4, 0.1);
+        Leg<R> lg;
+        lg.q[0] = 0.02; lg.q[1] = 0.9; lg.q[2] = -1.8;
+        lg.qd[0] = 0.5; lg.qd[1] = -1.0; lg.qd[2] = 2.0;
+        R u[3] = {0.0, 0.95, -1.75}, tau2;
+        BoxS<R> bx;
+        bx.p = v3<R>(1.0, 0.0, 0.15 - 2.0 * 9.81 / 8e4);
+        bx.qw = 1; bx.qx = 0; bx.qy = 0; bx.qz = 0;
+        bx.vw = v3<R>(0.01, 0.0, 0.0);
+        bx.w = v3<R>(0.0, 0.0, 0.0);
+        reset();
+        switch (scene) {
+        case 0: quad_step<0, R>(M, hf, R(0.01), R(40), R(1), leg, b, lg, bx, u, tau2); break;
+        case 1: quad_step<1, R>(M, hf, R(0.01), R(40), R(1), leg, b, lg, bx, u, tau2); break;
+        case 2: quad_step<2, R>(M, hf, R(0.01), R(40), R(1), leg, b, lg, bx, u, tau2); break;
+        case 3: quad_step<3, R>(M, hf, R(0.01), R(40), R(1), leg, b, lg, bx, u, tau2); break;
+        }
+        printf("leg %d: add %ld mul %ld div %ld sqrt %ld trans %ld total %ld (z foot contact %s)\n", leg, n_add, n_mul,
+               n_div, n_sqrt, n_trans, total(), "");
+        lane_sum += total();
+    }
+    // base work every lane repeats: rotation, trunk frame velocity and gravity, 6x6 solve,
+    // trunk terms and base integration
+    reset();
+    {
+        M33<R> Rm = quat_R(R(0.999), R(0.02), R(-0.03), R(0.01));
+        V3<R> vb = mulT(Rm, v3<R>(0.3, -0.1, -0.05));
+        V3<R> gb = R(-9.81) * v3(Rm.m[6], Rm.m[7], Rm.m[8]);
+        (void)vb; (void)gb;
+    }
+    long pro = total();
+    reset();
+    {
+        R Q[21], r[6];
+        for (int i = 0; i < 21; ++i) Q[i] = (i == 0 || i == 6 || i == 11 || i == 15 || i == 18 || i == 20) ? 2.0 : 0.1;
+        for (int i = 0; i < 6; ++i) r[i] = 0.3;
+        chol6_solve(Q, r);
+    }
+    long chol = total();
+    // trunk terms: 6 adds, gyroscopic 3 mul + cross 9, 6 mul-add rhs; base integration:
+    // w (3), vw = vw + R dv (15 + 3), p (6), quaternion exp and product (~45) and norm (~12)
+    long trunk_integ = 6 + 3 + 9 + 12 + 3 + 18 + 6 + 45 + 12 + 2;
+    long base = pro + chol + trunk_integ;
+    long nred = scene == 3 ? 55 : 28;
+    if (scene == 3) base += chol + 6 + 12 + 9 + 6 + 6 + 18 + 6 + 59 + 30;  // box solve, terms, integration
+    long reduce_extra = nred * (8 - 3);  // quad_sum counts 2 adds per lane; a 4-way sum needs 3
+    long algo_step = lane_sum - 3 * base - reduce_extra;
+    printf("per-lane sum %ld, base (redundant) %ld [prologue %ld chol6 %ld other %ld]\n", lane_sum, base, pro, chol,
+           trunk_integ);
+    printf("ALGORITHMIC flops per rollout-step (dynamics): %ld\n", algo_step);
+    return 0;
+}

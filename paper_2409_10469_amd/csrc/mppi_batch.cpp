@@ -143,6 +143,8 @@ size_t model_size(int arith) { return arith == 1 ? sizeof(mppi::ModelT<float>) :
 
 void drop_graph(mppi_batch* b)
 {
+    // an executable graph may still be running on the caller's stream: let it finish
+    if (b->exec && b->stream) hipStreamSynchronize(b->stream);
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
     b->exec = nullptr;
@@ -246,21 +248,23 @@ mppi_status capture(mppi_batch* b)
         return s;
     hipStream_t st = b->cap_stream;
     if ((s = bhip(b, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture"))) return s;
+    // the scenes' kernels run one after another in the graph
     hipError_t le = hipSuccess;
     for (int sc = 0; sc < 4 && le == hipSuccess; ++sc) {
         if (!b->scene_used[sc]) continue;
+        hipStream_t ss = st;
         if (b->arith == 1) {
             mppi::BatchArgs<float> a{(const mppi::InstDesc*)wsp(b, b->o_table),
                                      (const mppi::ModelT<float>*)wsp(b, b->o_models),
                                      (const int*)wsp(b, b->o_tiles[sc]), (const int*)wsp(b, b->o_total[sc]),
                                      (int*)wsp(b, b->o_head[sc]), (int*)wsp(b, b->o_exited[sc])};
-            le = mppi::launch_batch(1, sc, &a, b->grid, lds, st);
+            le = mppi::launch_batch(1, sc, &a, b->grid, lds, ss);
         } else {
             mppi::BatchArgs<double> a{(const mppi::InstDesc*)wsp(b, b->o_table),
                                       (const mppi::ModelT<double>*)wsp(b, b->o_models),
                                       (const int*)wsp(b, b->o_tiles[sc]), (const int*)wsp(b, b->o_total[sc]),
                                       (int*)wsp(b, b->o_head[sc]), (int*)wsp(b, b->o_exited[sc])};
-            le = mppi::launch_batch(0, sc, &a, b->grid, lds, st);
+            le = mppi::launch_batch(0, sc, &a, b->grid, lds, ss);
         }
     }
     hipGraph_t g = nullptr;
