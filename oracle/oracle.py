@@ -23,7 +23,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-shared", "-fPIC", "-o", tmp, SRC,
-                               "-lm"])
+                               os.path.join(HERE, "mlp_oracle.c"), "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -96,6 +96,11 @@ def lib():
             "orc_update": (C.c_int, [pp, dp, dp, dp, dp, dp]),
             "orc_shift": (None, [pp, dp, dp, dp]),
             "orc_mppi_step": (C.c_int, [mp, pp, C.c_uint32, dp, dp, dp, dp, C.c_int]),
+            "orc_mlp_n_params": (C.c_int, []),
+            "orc_mlp_forward": (None, [dp, C.c_int, dp, dp, C.c_int]),
+            "orc_mlp_loss": (C.c_double, [dp, C.c_int, dp, dp, C.c_int]),
+            "orc_mlp_grad": (C.c_double, [dp, C.c_int, dp, dp, dp, C.c_int]),
+            "orc_adam": (None, [dp, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -326,3 +331,48 @@ def shift(p: dict, mu_prime):
     mu, u0 = np.zeros(D), np.zeros(12)
     lib().orc_shift(C.byref(ps), _dp(_f64(mu_prime, D)), _dp(mu), _dp(u0))
     return mu, u0
+
+
+# ---- learned proposal (MLP) ----------------------------------------------------
+MLP_DIMS = (40, 512, 512, 512, 512, 144)
+
+
+def mlp_n_params():
+    return lib().orc_mlp_n_params()
+
+
+def mlp_forward(P, X, bf16=False):
+    X = _f64(X)
+    B = X.shape[0]
+    out = np.zeros((B, 144))
+    lib().orc_mlp_forward(_dp(_f64(P)), B, _dp(X), _dp(out), int(bf16))
+    return out
+
+
+def mlp_loss(P, X, Y, bf16=False):
+    X, Y = _f64(X), _f64(Y)
+    return lib().orc_mlp_loss(_dp(_f64(P)), X.shape[0], _dp(X), _dp(Y), int(bf16))
+
+
+def mlp_grad(P, X, Y, bf16=False):
+    X, Y = _f64(X), _f64(Y)
+    G = np.zeros(mlp_n_params())
+    L = lib().orc_mlp_grad(_dp(_f64(P)), X.shape[0], _dp(X), _dp(Y), _dp(G), int(bf16))
+    return L, G
+
+
+def adam(P, m, v, G, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    P, m, v = _f64(P).copy(), _f64(m).copy(), _f64(v).copy()
+    lib().orc_adam(_dp(P), _dp(m), _dp(v), _dp(_f64(G)), P.size, int(t), lr, b1, b2, eps)
+    return P, m, v
+
+
+def mlp_layer_views(P):
+    """(W, b) views of each layer of a flat parameter vector."""
+    out, off = [], 0
+    for fi, fo in zip(MLP_DIMS[:-1], MLP_DIMS[1:]):
+        W = P[off:off + fi * fo].reshape(fi, fo)
+        b = P[off + fi * fo:off + fi * fo + fo]
+        out.append((W, b))
+        off += fi * fo + fo
+    return out
