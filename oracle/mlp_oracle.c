@@ -18,6 +18,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include "mppi_oracle.h"
+
 #define NL 5
 static const int DIMS[NL + 1] = {40, 512, 512, 512, 512, 144};
 
@@ -181,5 +183,53 @@ void orc_adam(double *P, double *m, double *v, const double *G, int n, int t, do
         m[i] = b1 * m[i] + (1 - b1) * G[i];
         v[i] = b2 * v[i] + (1 - b2) * G[i] * G[i];
         P[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* Network input: the robot state with the base xy taken relative to the episode origin,
+   followed by the 3-dim command (forward, lateral, yaw-rate references), standardised
+   with the dataset statistics. */
+void orc_policy_features(const double *x, const double *cmd, const double *origin, const double *in_mean,
+                         const double *in_std, double *feat)
+{
+    double f[40];
+    for (int i = 0; i < 37; ++i) f[i] = x[i];
+    f[0] -= origin[0];
+    f[1] -= origin[1];
+    for (int i = 0; i < 3; ++i) f[37 + i] = cmd[i];
+    for (int i = 0; i < 40; ++i) feat[i] = (f[i] - in_mean[i]) / in_std[i];
+}
+
+/* Network output -> sampling distribution of a controller with nk knots per joint.
+   out = [standardised means (12 x 6, joint-major), standardised log-stds (12 x 6)].
+   Means are de-standardised (m = y sigma_y + mean_y) and log-stds shifted by log sigma_y;
+   both are resampled from the 6-knot spline to nk knots evenly spaced over the same
+   horizon (the knot times are at the same fractions of the horizon, so the map does not
+   depend on H dt); the log-std is clamped to [log 0.02, log sigma_max]. */
+void orc_policy_head(const double *out, const double *out_mean, const double *out_std, int nk, double sigma_max,
+                     double *center, double *sd)
+{
+    const double lo = log(0.02), hi = log(sigma_max);
+    for (int j = 0; j < 12; ++j) {
+        double m6[6], s6[6];
+        for (int k = 0; k < 6; ++k) {
+            int d = j * 6 + k;
+            m6[k] = out[d] * out_std[d] + out_mean[d];
+            s6[k] = out[72 + d] + log(out_std[d]);
+        }
+        for (int i = 0; i < nk; ++i) {
+            double t = (double)i / (nk - 1), m, s;
+            if (nk == 6) {
+                m = m6[i];
+                s = s6[i];
+            } else {
+                orc_spline_eval(6, 1.0, m6, t, &m);
+                orc_spline_eval(6, 1.0, s6, t, &s);
+            }
+            if (s < lo) s = lo;
+            if (s > hi) s = hi;
+            center[j * nk + i] = m;
+            sd[j * nk + i] = exp(s);
+        }
     }
 }

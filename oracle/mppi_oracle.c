@@ -1191,3 +1191,55 @@ int orc_mppi_step(const orc_model *m, const orc_params *p, uint32_t step, const 
     if (!costs) free(L);
     return rc;
 }
+
+/* Learned-proposal step (Sec. V-B names richer sampling distributions as future work; the
+   network-given proposal is the reading of this library).  With Kp samples around the
+   proposal: theta_0 = c (proposal mean), theta_1 = mu (shifted nominal), and
+   theta_n = c + sd * eps_n for 2 <= n < Kp, eps from the same counters as a plain step.
+   When L(c) is finite and L(c) <= L(mu) the Eq. 1-2 update runs over these Kp samples;
+   otherwise the step falls back to a plain step with K samples around mu.
+   *accepted reports which branch ran; costs_p (Kp) and costs (K, fallback only) are
+   optional outputs. */
+int orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t step, const double *x0, double *mu,
+                           const double *center, const double *sd, int Kp, double *u0, double *costs_p,
+                           double *costs, int *accepted, int nthreads)
+{
+    int D = 12 * p->nk, nx = orc_nx(m);
+    orc_params q = *p;
+    q.K = Kp;
+    double *eps = malloc(sizeof(double) * (size_t)Kp * D);
+    double *L = malloc(sizeof(double) * Kp);
+    double *theta = malloc(sizeof(double) * (size_t)Kp * D);
+    double *B = malloc(sizeof(double) * p->H * p->nk);
+    orc_sample_eps(&q, step, eps);
+    orc_spline_basis(p->nk, p->H, p->dt, B);
+    for (int n = 0; n < Kp; ++n)
+        for (int d = 0; d < D; ++d)
+            theta[(size_t)n * D + d] = n == 0 ? center[d] : n == 1 ? mu[d] : center[d] + sd[d] * eps[(size_t)n * D + d];
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (int n = 0; n < Kp; ++n) L[n] = rollout_with_basis(m, p, B, x0, theta + (size_t)n * D, NULL);
+    (void)nthreads;
+    (void)nx;
+    if (costs_p) memcpy(costs_p, L, sizeof(double) * Kp);
+    int acc = Kp >= 2 && isfinite(L[0]) && L[0] <= L[1];
+    if (accepted) *accepted = acc;
+    int rc;
+    if (acc) {
+        double *w = malloc(sizeof(double) * Kp), mup[96];
+        rc = orc_weights(Kp, p->lambda, L, w);
+        for (int d = 0; d < D; ++d) {
+            double s = 0;
+            for (int n = 0; n < Kp; ++n) s += w[n] * theta[(size_t)n * D + d];
+            mup[d] = s;
+        }
+        orc_shift(p, mup, mu, u0);
+        free(w);
+    } else {
+        rc = orc_mppi_step(m, p, step, x0, mu, u0, costs, nthreads);
+    }
+    free(eps); free(L); free(theta); free(B);
+    return rc;
+}

@@ -95,5 +95,16 @@ int  orc_update(const orc_params *p, const double *costs, const double *mu, cons
 void orc_shift(const orc_params *p, const double *mu_prime, double *mu_out, double *u0);
 int  orc_mppi_step(const orc_model *m, const orc_params *p, uint32_t step, const double *x0, double *mu,
                    double *u0, double *costs, int nthreads);
+int  orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t step, const double *x0, double *mu,
+                            const double *center, const double *sd, int Kp, double *u0, double *costs_p,
+                            double *costs, int *accepted, int nthreads);
+
+/* Learned proposal network (mlp_oracle.c). */
+int  orc_mlp_n_params(void);
+void orc_mlp_forward(const double *P, int B, const double *X, double *out, int bf);
+void orc_policy_features(const double *x, const double *cmd, const double *origin, const double *in_mean,
+                         const double *in_std, double *feat);
+void orc_policy_head(const double *out, const double *out_mean, const double *out_std, int nk, double sigma_max,
+                     double *center, double *sd);
 
 #endif

@@ -96,6 +96,10 @@ def lib():
             "orc_update": (C.c_int, [pp, dp, dp, dp, dp, dp]),
             "orc_shift": (None, [pp, dp, dp, dp]),
             "orc_mppi_step": (C.c_int, [mp, pp, C.c_uint32, dp, dp, dp, dp, C.c_int]),
+            "orc_mppi_step_proposal": (C.c_int, [mp, pp, C.c_uint32, dp, dp, dp, dp, C.c_int, dp, dp, dp,
+                                                 C.POINTER(C.c_int), C.c_int]),
+            "orc_policy_features": (None, [dp, dp, dp, dp, dp, dp]),
+            "orc_policy_head": (None, [dp, dp, dp, C.c_int, C.c_double, dp, dp]),
             "orc_mlp_n_params": (C.c_int, []),
             "orc_mlp_forward": (None, [dp, C.c_int, dp, dp, C.c_int]),
             "orc_mlp_loss": (C.c_double, [dp, C.c_int, dp, dp, C.c_int]),
@@ -264,6 +268,19 @@ class Oracle:
                                   _dp(costs), int(nthreads))
         return u0, mu, costs, rc
 
+    def mppi_step_proposal(self, p: dict, step: int, x0, mu, center, sd, Kp, nthreads=0):
+        """Learned-proposal step; returns (u0, shifted nominal, proposal costs (Kp),
+        fallback costs (K, zeros when accepted), accepted, status)."""
+        ps = self.params(p)
+        D = 12 * p["nk"]
+        mu = _f64(mu, D).copy()
+        u0, cp, cf = np.zeros(12), np.zeros(Kp), np.zeros(p["K"])
+        acc = C.c_int(0)
+        rc = self.L.orc_mppi_step_proposal(C.byref(self.m), C.byref(ps), int(step), _dp(_f64(x0, self.nx)), _dp(mu),
+                                           _dp(_f64(center, D)), _dp(_f64(sd, D)), int(Kp), _dp(u0), _dp(cp),
+                                           _dp(cf), C.byref(acc), int(nthreads))
+        return u0, mu, cp, cf, bool(acc.value), rc
+
 
 # ---- model-free pieces ---------------------------------------------------
 def philox(ctr, key):
@@ -365,6 +382,20 @@ def adam(P, m, v, G, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     P, m, v = _f64(P).copy(), _f64(m).copy(), _f64(v).copy()
     lib().orc_adam(_dp(P), _dp(m), _dp(v), _dp(_f64(G)), P.size, int(t), lr, b1, b2, eps)
     return P, m, v
+
+
+def policy_features(x, cmd, origin, in_mean, in_std):
+    f = np.zeros(40)
+    lib().orc_policy_features(_dp(_f64(x, 37)), _dp(_f64(cmd, 3)), _dp(_f64(origin, 2)), _dp(_f64(in_mean, 40)),
+                              _dp(_f64(in_std, 40)), _dp(f))
+    return f
+
+
+def policy_head(out, out_mean, out_std, nk, sigma_max):
+    c, sd = np.zeros(12 * nk), np.zeros(12 * nk)
+    lib().orc_policy_head(_dp(_f64(out, 144)), _dp(_f64(out_mean, 72)), _dp(_f64(out_std, 72)), int(nk),
+                          float(sigma_max), _dp(c), _dp(sd))
+    return c, sd
 
 
 def mlp_layer_views(P):
