@@ -1,0 +1,129 @@
+/*
+ * mppi_policy.h -- C ABI of the learned sampling proposal.
+ *
+ * The paper leaves sampling from richer distributions to future work (Sec. V-B) and
+ * cites offline-learned sampling distributions as related work (Sec. II-B).  This
+ * library's proposal is a multilayer perceptron
+ *     40 -> 512 -> 512 -> 512 -> 512 -> 144, SiLU between layers,
+ * mapping (state, command) to a mean and a log standard deviation for each of the
+ * 12 joints x 6 knots of the next plan.  It runs on the gfx950 matrix cores with BF16
+ * operands and FP32 accumulation; FP32 master weights and Adam moments are kept beside
+ * the BF16 copies the products read.
+ *
+ * Conventions (as in mppi.h):
+ *  - d_* pointers are DEVICE pointers owned by the caller; others are host pointers.
+ *  - The library never allocates device memory: the caller binds a workspace of
+ *    mppi_policy_workspace_bytes() bytes (256-byte aligned).
+ *  - Calls that launch work are asynchronous on the bound stream; a negative status
+ *    means nothing was launched (mppi_policy_last_error describes why).
+ *
+ * Input features (40 floats per row, "raw"): the 37-float robot state of mppi.h with the
+ * base x, y taken relative to the episode origin, then the command
+ * (v_x reference, v_y reference, yaw-rate reference).  The network sees them standardised
+ * with the policy's normalisation: (f - in_mean) / in_std.
+ * Network output (144 floats per row, standardised): 72 means then 72 log-stds, both
+ * joint-major (index j * 6 + k for knot k of joint j).  Training targets (72 floats per
+ * row, raw knots) are standardised with (y - out_mean) / out_std; the loss is the
+ * Gaussian negative log-likelihood averaged over rows and outputs,
+ *     L = mean( (y_std - m)^2 exp(-2 s) / 2 + s ).
+ *
+ * Parameter layout (flat FP32, 882832 values): per layer l, W_l (fan_in x fan_out,
+ * row-major, W[i][o]) then b_l (fan_out).
+ */
+#ifndef MPPI_POLICY_H
+#define MPPI_POLICY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mppi.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPPI_POLICY_IN 40
+#define MPPI_POLICY_OUT 144
+#define MPPI_POLICY_KNOTS 6
+#define MPPI_POLICY_TARGET 72
+
+typedef struct mppi_policy mppi_policy;
+
+/* Number of parameters (882832). */
+int mppi_policy_n_params(void);
+
+/* Creates a policy able to process up to max_batch rows per call (1..65536).  With
+ * ckpt_path NULL the weights are drawn from a seeded uniform(-1/sqrt(fan_in),
+ * 1/sqrt(fan_in)) (biases likewise), Adam moments are zero and the normalisation is the
+ * identity; otherwise all of these are read from a file written by mppi_policy_save
+ * (EINVAL if it is missing or malformed). */
+mppi_status mppi_policy_create(const char *ckpt_path, uint64_t seed, int max_batch, mppi_policy **out);
+void mppi_policy_destroy(mppi_policy *pol);
+size_t mppi_policy_workspace_bytes(const mppi_policy *pol);
+/* Binds workspace and stream and uploads weights, moments and normalisation. */
+mppi_status mppi_policy_bind(mppi_policy *pol, void *d_workspace, size_t bytes, void *hip_stream);
+/* Host arrays in_mean[40], in_std[40], out_mean[72], out_std[72]; stds must be > 0. */
+mppi_status mppi_policy_set_normalization(mppi_policy *pol, const float *in_mean, const float *in_std,
+                                          const float *out_mean, const float *out_std);
+/* FP32 master parameters (n_params floats, device) out / in.  set_params also refreshes
+ * the BF16 copies; it leaves the Adam moments and step count unchanged. */
+mppi_status mppi_policy_get_params(mppi_policy *pol, float *d_params);
+mppi_status mppi_policy_set_params(mppi_policy *pol, const float *d_params);
+/* Forward pass of B rows of raw features d_in (B x 40) into d_out (B x 144,
+ * standardised network output); 1 <= B <= max_batch. */
+mppi_status mppi_policy_forward(mppi_policy *pol, const float *d_in, int B, float *d_out);
+/* Loss and gradient over the B rows d_index[0..B) (or rows 0..B-1 if d_index is NULL)
+ * of d_in (x 40) and d_target (x 72): d_grad receives n_params floats in the parameter
+ * layout, d_loss one float (either may be NULL). */
+mppi_status mppi_policy_grad(mppi_policy *pol, const float *d_in, const float *d_target, const int *d_index, int B,
+                             float *d_grad, float *d_loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; Kingma and Ba) with
+ * the given gradient (n_params floats, device) and learning rate. */
+mppi_status mppi_policy_adam(mppi_policy *pol, const float *d_grad, float lr);
+/* mppi_policy_grad followed by mppi_policy_adam on its gradient. */
+mppi_status mppi_policy_train_step(mppi_policy *pol, const float *d_in, const float *d_target, const int *d_index,
+                                   int B, float lr, float *d_loss);
+/* Adam steps taken so far. */
+int mppi_policy_steps(const mppi_policy *pol);
+/* Synchronises the stream and writes weights, moments, step count and normalisation
+ * to a binary file ("MPPIPOL1" header, then little-endian int32 n_params and step,
+ * 224 normalisation floats, and the parameters, first and second moments as FP32). */
+mppi_status mppi_policy_save(mppi_policy *pol, const char *path);
+/* Proposal of a controller with n_knots knots per joint from one row of network output
+ * d_out (144 floats, device): means and log-stds de-standardised, resampled from the 6
+ * knots to n_knots knots at the same fractions of the horizon (not-a-knot cubic spline),
+ * log-std clamped to [log 0.02, log sigma_max]; d_center and d_sd receive 12 * n_knots
+ * floats (joint-major). */
+mppi_status mppi_policy_head(mppi_policy *pol, const float *d_out, int n_knots, float sigma_max, float *d_center,
+                             float *d_sd);
+const char *mppi_policy_last_error(const mppi_policy *pol);
+
+/* ---- controller side -------------------------------------------------------------
+ * DISABLED IN THIS BUILD: the three calls below validate nothing and return MPPI_EINVAL
+ * ("disabled"); their first GPU run ended in a memory fault whose cause has not been
+ * identified.  The intended behaviour, which the CPU oracle implements, is:
+ *
+ * One control step with an explicit proposal (mean d_center, std d_sd; 12 * n_knots
+ * floats each, device): k_prop samples theta_0 = center, theta_1 = the current (shifted)
+ * nominal, theta_n = center + sd * eps_n for 2 <= n < k_prop, with eps_n the same Philox
+ * noise a plain step draws for sample n.  If the rollout cost of the centre is finite and
+ * not above the nominal's, Eq. 1 and Eq. 2 run over these k_prop samples; otherwise the
+ * step falls back to a plain step with K samples (the fallback launch is always queued
+ * and exits at once when the proposal was accepted).  Then, as in mppi_step, the first
+ * control goes to d_u0_out, the nominal is shifted and the step counter advances.
+ * 2 <= k_prop <= K. */
+mppi_status mppi_step_proposal(mppi_ctx *ctx, const float *d_x0, const float *d_center, const float *d_sd,
+                               int k_prop, float *d_u0_out);
+/* Makes every later mppi_step of ctx use the policy: features of the current state and
+ * command (host cmd[3]) relative to the host origin_xy[2], a forward pass, the head, and
+ * mppi_step_proposal with k_prop samples.  The policy's kernels then run on ctx's
+ * stream; the policy must not be used on another stream meanwhile.  pol NULL switches
+ * the proposal off.  Requires a 37-float state model. */
+mppi_status mppi_set_proposal(mppi_ctx *ctx, mppi_policy *pol, int k_prop, const float *cmd, const float *origin_xy);
+/* Synchronises and reports how many proposal steps ran and how many were accepted. */
+mppi_status mppi_proposal_stats(mppi_ctx *ctx, int *accepted, int *steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

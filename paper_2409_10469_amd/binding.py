@@ -85,6 +85,25 @@ def lib():
                                         vp]),
             "mppi_status_str": (C.c_char_p, [C.c_int]),
             "mppi_last_error": (C.c_char_p, [vp]),
+            "mppi_step_proposal": (C.c_int, [vp, fp, fp, fp, C.c_int, fp]),
+            "mppi_set_proposal": (C.c_int, [vp, vp, C.c_int, vp, vp]),
+            "mppi_proposal_stats": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+            "mppi_policy_n_params": (C.c_int, []),
+            "mppi_policy_create": (C.c_int, [C.c_char_p, C.c_uint64, C.c_int, C.POINTER(C.c_void_p)]),
+            "mppi_policy_destroy": (None, [vp]),
+            "mppi_policy_workspace_bytes": (C.c_size_t, [vp]),
+            "mppi_policy_bind": (C.c_int, [vp, vp, C.c_size_t, vp]),
+            "mppi_policy_set_normalization": (C.c_int, [vp, vp, vp, vp, vp]),
+            "mppi_policy_get_params": (C.c_int, [vp, fp]),
+            "mppi_policy_set_params": (C.c_int, [vp, fp]),
+            "mppi_policy_forward": (C.c_int, [vp, fp, C.c_int, fp]),
+            "mppi_policy_grad": (C.c_int, [vp, fp, fp, vp, C.c_int, fp, fp]),
+            "mppi_policy_adam": (C.c_int, [vp, fp, C.c_float]),
+            "mppi_policy_train_step": (C.c_int, [vp, fp, fp, vp, C.c_int, C.c_float, fp]),
+            "mppi_policy_steps": (C.c_int, [vp]),
+            "mppi_policy_save": (C.c_int, [vp, C.c_char_p]),
+            "mppi_policy_head": (C.c_int, [vp, fp, C.c_int, C.c_float, fp, fp]),
+            "mppi_policy_last_error": (C.c_char_p, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -269,9 +288,115 @@ class Controller:
     def sync_status(self):
         return self._s(lib().mppi_sync_status(self.h))
 
+    def step_proposal(self, x0, center, sd, k_prop, u0=None):
+        """One control step sampling k_prop knots around an explicit proposal (mean, std)."""
+        import torch
+        u0 = u0 if u0 is not None else torch.empty(12, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_step_proposal(self.h, _ptr(x0), _ptr(center), _ptr(sd), int(k_prop), _ptr(u0)))
+        return u0
+
+    def set_proposal(self, policy, k_prop=0, cmd=(0.0, 0.0, 0.0), origin=(0.0, 0.0)):
+        """Route later step() calls through the learned proposal (policy None: plain MPPI)."""
+        c = np.ascontiguousarray(cmd, dtype=np.float32)
+        o = np.ascontiguousarray(origin, dtype=np.float32)
+        self._s(lib().mppi_set_proposal(self.h, policy.h if policy is not None else None, int(k_prop),
+                                        c.ctypes.data_as(C.c_void_p), o.ctypes.data_as(C.c_void_p)))
+        self._policy = policy  # keep alive while in use
+
+    def proposal_stats(self):
+        a, n = C.c_int(), C.c_int()
+        self._s(lib().mppi_proposal_stats(self.h, C.byref(a), C.byref(n)))
+        return a.value, n.value
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.mppi_destroy(self.h)
+            self.h = None
+
+
+N_POLICY_PARAMS = 882832
+
+
+class Policy:
+    """Learned proposal network (include/mppi_policy.h) on a torch-allocated workspace."""
+
+    def __init__(self, max_batch=4096, seed=0, ckpt=None, stream=None):
+        import torch
+        L = lib()
+        h = C.c_void_p()
+        rc = L.mppi_policy_create(ckpt.encode() if ckpt else None, int(seed) & 0xFFFFFFFFFFFFFFFF, int(max_batch),
+                                  C.byref(h))
+        if rc < 0:
+            raise MppiError(rc, L.mppi_policy_last_error(None).decode())
+        self.h = h
+        self.max_batch = int(max_batch)
+        nbytes = L.mppi_policy_workspace_bytes(h)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off:off + nbytes]
+        self.stream = stream
+        self._s(L.mppi_policy_bind(h, C.c_void_p(self.ws_view.data_ptr()), nbytes, _stream(stream)))
+
+    def _s(self, status):
+        if status < 0:
+            raise MppiError(status, lib().mppi_policy_last_error(self.h).decode())
+        return status
+
+    def set_normalization(self, in_mean, in_std, out_mean, out_std):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (in_mean, in_std, out_mean, out_std)]
+        assert [a.size for a in arrs] == [40, 40, 72, 72]
+        self._s(lib().mppi_policy_set_normalization(self.h, *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
+
+    def get_params(self):
+        import torch
+        out = torch.empty(N_POLICY_PARAMS, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_policy_get_params(self.h, _ptr(out)))
+        return out
+
+    def set_params(self, P):
+        self._s(lib().mppi_policy_set_params(self.h, _ptr(P)))
+
+    def forward(self, X):
+        import torch
+        out = torch.empty((X.shape[0], 144), dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_policy_forward(self.h, _ptr(X), int(X.shape[0]), _ptr(out)))
+        return out
+
+    def grad(self, X, Y, index=None, B=None):
+        import torch
+        B = int(B if B is not None else (index.shape[0] if index is not None else X.shape[0]))
+        G = torch.empty(N_POLICY_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_policy_grad(self.h, _ptr(X), _ptr(Y), _ptr(index), B, _ptr(G), _ptr(loss)))
+        return loss, G
+
+    def adam(self, G, lr):
+        self._s(lib().mppi_policy_adam(self.h, _ptr(G), float(lr)))
+
+    def train_step(self, X, Y, index=None, B=None, lr=1e-3, loss=None):
+        import torch
+        B = int(B if B is not None else (index.shape[0] if index is not None else X.shape[0]))
+        loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_policy_train_step(self.h, _ptr(X), _ptr(Y), _ptr(index), B, float(lr), _ptr(loss)))
+        return loss
+
+    @property
+    def steps(self):
+        return lib().mppi_policy_steps(self.h)
+
+    def save(self, path):
+        self._s(lib().mppi_policy_save(self.h, str(path).encode()))
+
+    def head(self, out_row, nk, sigma_max):
+        import torch
+        c = torch.empty(12 * nk, dtype=torch.float32, device="cuda")
+        sd = torch.empty(12 * nk, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_policy_head(self.h, _ptr(out_row), int(nk), float(sigma_max), _ptr(c), _ptr(sd)))
+        return c, sd
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mppi_policy_destroy(self.h)
             self.h = None
 
 

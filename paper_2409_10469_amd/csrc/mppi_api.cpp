@@ -2,6 +2,7 @@
 // and kernel launches on the caller's stream.  No device allocation happens here: the
 // caller provides the workspace.
 #include "mppi.h"
+#include "mppi_policy.h"
 
 #include <hip/hip_runtime.h>
 
@@ -206,6 +207,14 @@ bool model_info(const mppi_model* m, int* scene, int* nx, const float** hf, int*
 void spline_matrices(int nk, int H, double dt, std::vector<double>& B, std::vector<float>& S)
 {
     build_spline(nk, H, dt, B, S);
+}
+double spline_basis_at(int nk, double T, int k, double t)
+{
+    std::vector<double> y(nk, 0.0), m(nk);
+    y[k] = 1.0;
+    const double h = T / (nk - 1);
+    second_derivatives(nk, h, y.data(), m.data());
+    return spline_value(nk, h, y.data(), m.data(), t);
 }
 }  // namespace mppi_host
 
@@ -468,6 +477,23 @@ mppi_status mppi_sync_status(mppi_ctx* c)
         return s;
     if ((s = hip_check(c, hipStreamSynchronize(c->stream), "synchronise"))) return s;
     return st ? MPPI_WARN_ALL_NONFINITE : MPPI_OK;
+}
+
+// The proposal control step is switched off: its first GPU run ended in a memory
+// fault whose cause has not been identified; these entry points refuse until it is.
+mppi_status mppi_step_proposal(mppi_ctx* c, const float*, const float*, const float*, int, float*)
+{
+    return fail(c, MPPI_EINVAL, "the learned-proposal control step is disabled in this build");
+}
+
+mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy*, int, const float*, const float*)
+{
+    return fail(c, MPPI_EINVAL, "the learned-proposal control step is disabled in this build");
+}
+
+mppi_status mppi_proposal_stats(mppi_ctx* c, int*, int*)
+{
+    return fail(c, MPPI_EINVAL, "the learned-proposal control step is disabled in this build");
 }
 
 mppi_status mppi_sim_step(const mppi_model* m, int arith, int n, const float* d_x, const float* d_u, float kp,

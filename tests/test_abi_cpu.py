@@ -10,21 +10,46 @@ from paper_2409_10469_amd import binding as B
 from paper_2409_10469_amd import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "mppi.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mppi_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(mppi_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     L = C.CDLL(B.LIB_PATH)
     names = _declared()
-    assert len(names) >= 18
+    assert len(names) >= 50
     for n in names:
         assert hasattr(L, n), n
+
+
+def test_policy_host_validation_and_checkpoint_errors(tmp_path):
+    L = B.lib()
+    assert L.mppi_policy_n_params() == B.N_POLICY_PARAMS
+    h = C.c_void_p()
+    assert L.mppi_policy_create(None, 0, 0, C.byref(h)) == B.EINVAL and not h.value
+    assert L.mppi_policy_create(None, 0, 70000, C.byref(h)) == B.EINVAL
+    assert L.mppi_policy_create(str(tmp_path / "missing").encode(), 0, 16, C.byref(h)) == B.EINVAL
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"MPPIPOL1" + b"\0" * 64)
+    assert L.mppi_policy_create(str(bad).encode(), 0, 16, C.byref(h)) == B.EINVAL
+    assert L.mppi_policy_create(None, 7, 256, C.byref(h)) == B.OK and h.value
+    # calls that need a bound workspace refuse without one
+    assert L.mppi_policy_forward(h, None, 1, None) == B.ESTATE
+    assert L.mppi_policy_save(h, b"x") == B.ESTATE
+    one = (C.c_float * 72)(*([1.0] * 72))
+    zero = (C.c_float * 72)()
+    assert L.mppi_policy_set_normalization(h, one, zero, one, one) == B.EINVAL  # zero input std
+    assert L.mppi_policy_set_normalization(h, zero, one, zero, one) == B.OK
+    assert L.mppi_policy_workspace_bytes(h) > 4 * 4 * B.N_POLICY_PARAMS
+    L.mppi_policy_destroy(h)
 
 
 def _model_handle(**over):
@@ -111,3 +136,11 @@ def test_batch_create_validation():
     assert L.mppi_batch_create(16, 80, 4096, 5, C.byref(h)) == B.EINVAL
     assert L.mppi_batch_create(16, 256, 14336, 0, C.byref(h)) == B.EINVAL  # LDS stage over 64 KiB
     assert L.mppi_batch_control_bytes(16, 0) > 16 * 256
+
+
+def test_proposal_step_is_switched_off():
+    L = B.lib()
+    assert L.mppi_step_proposal(None, None, None, None, 16, None) == B.EINVAL
+    assert L.mppi_set_proposal(None, None, 16, None, None) == B.EINVAL
+    assert L.mppi_proposal_stats(None, None, None) == B.EINVAL
+    assert b"disabled" in L.mppi_last_error(None)
