@@ -206,6 +206,12 @@ mppi_status mppi_batch_admit(mppi_batch *b, int model_slot, const mppi_params *p
                              const float *mu, int *id_out);
 /* releases an instance; its memory is reused only by later stream-ordered admissions */
 mppi_status mppi_batch_remove(mppi_batch *b, int id);
+/* From the next step on, each control step s of instance id writes row (s mod cap) of
+ * d_rec: the state the step started from (nx floats) followed by that step's updated,
+ * unshifted knots mu' (12 * n_knots floats).  d_rec is a caller-owned DEVICE buffer of
+ * cap * (nx + 12 * n_knots) floats that must stay allocated while recording; NULL stops
+ * recording.  (Training data for the learned proposal: pairs of state and weighted plan.) */
+mppi_status mppi_batch_record(mppi_batch *b, int id, float *d_rec, int cap);
 /* one control step of every live instance: one graph launch on the bound stream */
 mppi_status mppi_batch_step(mppi_batch *b);
 /* persistent grid = blocks_per_cu x compute units; order 1 = longest horizon first */

@@ -65,6 +65,9 @@ mppi_status mppi_policy_bind(mppi_policy *pol, void *d_workspace, size_t bytes, 
 /* Host arrays in_mean[40], in_std[40], out_mean[72], out_std[72]; stds must be > 0. */
 mppi_status mppi_policy_set_normalization(mppi_policy *pol, const float *in_mean, const float *in_std,
                                           const float *out_mean, const float *out_std);
+/* Copies the normalisation to host arrays (same order and sizes; NULL to skip one). */
+mppi_status mppi_policy_get_normalization(const mppi_policy *pol, float *in_mean, float *in_std, float *out_mean,
+                                          float *out_std);
 /* FP32 master parameters (n_params floats, device) out / in.  set_params also refreshes
  * the BF16 copies; it leaves the Adam moments and step count unchanged. */
 mppi_status mppi_policy_get_params(mppi_policy *pol, float *d_params);

@@ -95,6 +95,7 @@ def lib():
             "mppi_policy_bind": (C.c_int, [vp, vp, C.c_size_t, vp]),
             "mppi_policy_set_normalization": (C.c_int, [vp, vp, vp, vp, vp]),
             "mppi_policy_get_params": (C.c_int, [vp, fp]),
+            "mppi_policy_get_normalization": (C.c_int, [vp, vp, vp, vp, vp]),
             "mppi_policy_set_params": (C.c_int, [vp, fp]),
             "mppi_policy_forward": (C.c_int, [vp, fp, C.c_int, fp]),
             "mppi_policy_grad": (C.c_int, [vp, fp, fp, vp, C.c_int, fp, fp]),
@@ -336,6 +337,7 @@ class Policy:
         self.ws_view = self.ws[off:off + nbytes]
         self.stream = stream
         self._s(L.mppi_policy_bind(h, C.c_void_p(self.ws_view.data_ptr()), nbytes, _stream(stream)))
+        self._norm = self.get_normalization()
 
     def _s(self, status):
         if status < 0:
@@ -346,6 +348,12 @@ class Policy:
         arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (in_mean, in_std, out_mean, out_std)]
         assert [a.size for a in arrs] == [40, 40, 72, 72]
         self._s(lib().mppi_policy_set_normalization(self.h, *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
+        self._norm = tuple(a.astype(np.float64) for a in arrs)
+
+    def get_normalization(self):
+        arrs = [np.zeros(n, np.float32) for n in (40, 40, 72, 72)]
+        self._s(lib().mppi_policy_get_normalization(self.h, *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
+        return tuple(a.astype(np.float64) for a in arrs)
 
     def get_params(self):
         import torch
@@ -364,6 +372,7 @@ class Policy:
 
     def grad(self, X, Y, index=None, B=None):
         import torch
+        assert index is None or index.dtype == torch.int32
         B = int(B if B is not None else (index.shape[0] if index is not None else X.shape[0]))
         G = torch.empty(N_POLICY_PARAMS, dtype=torch.float32, device="cuda")
         loss = torch.empty(1, dtype=torch.float32, device="cuda")
@@ -375,6 +384,7 @@ class Policy:
 
     def train_step(self, X, Y, index=None, B=None, lr=1e-3, loss=None):
         import torch
+        assert index is None or index.dtype == torch.int32
         B = int(B if B is not None else (index.shape[0] if index is not None else X.shape[0]))
         loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device="cuda")
         self._s(lib().mppi_policy_train_step(self.h, _ptr(X), _ptr(Y), _ptr(index), B, float(lr), _ptr(loss)))
@@ -417,6 +427,7 @@ class Batch:
                 "mppi_batch_admit": (C.c_int, [vp, C.c_int, C.POINTER(Params), vp, vp, C.POINTER(C.c_int)]),
                 "mppi_batch_remove": (C.c_int, [vp, C.c_int]),
                 "mppi_batch_step": (C.c_int, [vp]),
+                "mppi_batch_record": (C.c_int, [vp, C.c_int, vp, C.c_int]),
                 "mppi_batch_set_tuning": (C.c_int, [vp, C.c_int, C.c_int]),
                 "mppi_batch_autotune": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                                   C.POINTER(C.c_float)]),
@@ -468,9 +479,22 @@ class Batch:
 
     def remove(self, i):
         self._chk(self.L.mppi_batch_remove(self.h, int(i)))
+        getattr(self, "_records", {}).pop(i, None)
 
     def step(self):
         self._chk(self.L.mppi_batch_step(self.h))
+
+    def record(self, i, rec=None):
+        """Record [x_s, mu'_s] of instance i into the device tensor rec (cap x (nx + 12 nk),
+        float32) from the next step on; rec None stops.  The tensor is kept alive here."""
+        if rec is not None:
+            assert rec.dtype.is_floating_point and rec.element_size() == 4 and rec.dim() == 2
+        self._chk(self.L.mppi_batch_record(self.h, int(i), _ptr(rec), int(rec.shape[0]) if rec is not None else 0))
+        self._records = getattr(self, "_records", {})
+        if rec is None:
+            self._records.pop(i, None)
+        else:
+            self._records[i] = rec
 
     def set_tuning(self, blocks_per_cu, order):
         self._chk(self.L.mppi_batch_set_tuning(self.h, blocks_per_cu, order))

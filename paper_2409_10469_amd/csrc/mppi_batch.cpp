@@ -92,6 +92,8 @@ struct Instance {
     int model = 0;
     mppi_params p{};
     size_t off = 0, bytes = 0;
+    float* rec = nullptr;  // caller's record buffer
+    int rec_cap = 0;
     // offsets inside the allocation
     size_t o_B, o_S, o_x, o_mu, o_eps, o_costs, o_w, o_u0, o_acc, o_done, o_step;
 };
@@ -202,6 +204,8 @@ mppi_status upload_table(mppi_batch* b)
             d.cost_acc = (float*)(base + in.o_acc);
             d.done = (int*)(base + in.o_done);
             d.step = (uint32_t*)(base + in.o_step);
+            d.rec = in.rec;
+            d.rec_cap = in.rec_cap;
             for (int k = 0; k < d.ntiles; ++k) map[tile + k] = row;
             tile += d.ntiles;
             ++row;
@@ -465,6 +469,16 @@ mppi_status mppi_batch_remove(mppi_batch* b, int id)
     // later admissions reuse the memory only through stream-ordered copies
     b->arena.release(b->inst[id].off, b->inst[id].bytes);
     b->inst[id].live = false;
+    b->dirty = true;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_record(mppi_batch* b, int id, float* d_rec, int cap)
+{
+    if (!b || id < 0 || id >= b->max_inst || !b->inst[id].live) return bfail(b, MPPI_EINVAL, "unknown instance");
+    if (d_rec && cap < 1) return bfail(b, MPPI_EINVAL, "record capacity must be >= 1");
+    b->inst[id].rec = d_rec;
+    b->inst[id].rec_cap = d_rec ? cap : 0;
     b->dirty = true;
     return MPPI_OK;
 }

@@ -354,6 +354,11 @@ __device__ __forceinline__ void instance_tail(const InstDesc& I, const DevParams
         for (int l = 0; l < nk; ++l) v += I.S[i * nk + l] * sMup[j * nk + l];
         I.mu[q] = v;
     }
+    if (I.rec) {  // the state this step started from and its updated knots
+        float* row = I.rec + (size_t)(I.step[0] % (uint32_t)I.rec_cap) * (P.nx + D);
+        for (int q = t; q < P.nx; q += 64) row[q] = I.x[q];
+        for (int q = t; q < D; q += 64) row[P.nx + q] = sMup[q];
+    }
     __syncthreads();
     plant_step<SCENE, R>(M, P, sHF, I.x, I.u0, I.cost_acc);
     if (t == 0) {

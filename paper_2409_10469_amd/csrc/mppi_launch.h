@@ -78,6 +78,8 @@ struct InstDesc {
     float* cost_acc;            // running cost of the closed loop
     int* done;                  // finished tiles of the current step
     uint32_t* step;             // control-step counter (Philox counter word)
+    float* rec;                 // record rows [x, mu'] (nx + 12 nk floats) or null
+    int rec_cap, pad1;          // rows in rec; step s writes row s mod rec_cap
 };
 
 template <typename R>

@@ -413,6 +413,17 @@ mppi_status mppi_policy_set_normalization(mppi_policy* p, const float* in_mean, 
     return phip(p, hipStreamSynchronize(p->stream), "normalisation synchronise");
 }
 
+mppi_status mppi_policy_get_normalization(const mppi_policy* p, float* in_mean, float* in_std, float* out_mean,
+                                          float* out_std)
+{
+    if (!p) return pfail(nullptr, MPPI_EINVAL, "null policy");
+    if (in_mean) std::memcpy(in_mean, p->norm, 160);
+    if (in_std) std::memcpy(in_std, p->norm + 40, 160);
+    if (out_mean) std::memcpy(out_mean, p->norm + 80, 288);
+    if (out_std) std::memcpy(out_std, p->norm + 152, 288);
+    return MPPI_OK;
+}
+
 mppi_status mppi_policy_get_params(mppi_policy* p, float* d_params)
 {
     mppi_status s;

@@ -1,0 +1,191 @@
+"""Learned sampling proposal: training data from GPU closed loops and training.
+
+Data.  Closed loops of the flat-ground walk (64 samples, 25 steps of 0.02 s, 4 knots)
+and the heightfield walk (1024 samples, 50 steps of 0.01 s, 6 knots) run as instances
+of a Batch; each instance draws its forward-velocity command from U[0, 0.8] m/s (the
+lateral and yaw-rate commands are 0) and records, every control step, the state the step
+started from and the step's updated, unshifted knots.  Each record becomes one pair
+  input  = state with base x, y relative to the episode origin, then the command (40)
+  target = updated knots at 6 knots per joint (72); the 4-knot plans are resampled to 6
+           knots at the same fractions of their 0.5 s horizon (both horizons are 0.5 s).
+Rows from the step at which an episode's base drops below 0.12 m (a fall) or turns
+non-finite, onwards, are dropped.  Episodes are split into training and held-out sets
+by episode.
+
+Training.  Gaussian negative log-likelihood with Adam (lr 1e-3, batch 4096), inputs and
+targets standardised with the training set's per-feature mean and std.  Every product,
+loss, gradient and update runs in the library's kernels; this module generates the
+index permutations and evaluates held-out loss.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import workloads as W
+
+CONFIGS = (W.FLAT_WALK, W.TERRAIN_WALK)
+V_RANGE = (0.0, 0.8)
+FALL_Z = 0.12
+
+
+def resample_matrix(nk_from: int, nk_to: int = 6) -> np.ndarray:
+    """Knots of a plan at nk_to evenly spaced fractions of the horizon from its nk_from
+    knots.  For 4 knots the not-a-knot cubic spline is the interpolating cubic, so the
+    map is the Lagrange basis; 6 -> 6 is the identity."""
+    if nk_from == nk_to:
+        return np.eye(nk_to)
+    if nk_from != 4:
+        raise ValueError("training data comes from 4- and 6-knot plans")
+    src = np.linspace(0.0, 1.0, nk_from)
+    dst = np.linspace(0.0, 1.0, nk_to)
+    R = np.ones((nk_to, nk_from))
+    for j in range(nk_from):
+        for m in range(nk_from):
+            if m != j:
+                R[:, j] *= (dst - src[m]) / (src[j] - src[m])
+    return R
+
+
+def generate(n_pairs=1_000_000, episode_steps=200, instances=256, seed=0, arith="fp64", budget=1 << 30,
+             log=print):
+    """Closed-loop pairs from both configs, half each.  Returns dict of float32 device
+    tensors X (N x 40), Y (N x 72) and int32 episode ids, plus bookkeeping."""
+    import torch
+    rng = np.random.default_rng([seed, 77])
+    Xs, Ys, Es = [], [], []
+    ep_id = 0
+    stats = dict(episodes=0, falls=0, control_steps=0, rollout_steps=0, seconds=0.0)
+    stream = torch.cuda.current_stream()
+    for ci, wl in enumerate(CONFIGS):
+        target = n_pairs // len(CONFIGS) + (n_pairs % len(CONFIGS) if ci == 0 else 0)
+        got = 0
+        nk, K, H = wl["nk"], wl["K"], wl["H"]
+        nx, D = 37, 12 * nk
+        R = torch.as_tensor(resample_matrix(nk), dtype=torch.float32, device="cuda")
+        batch = B.Batch(max_instances=instances, budget_bytes=budget, max_horizon=H,
+                        max_hf_cells=W.HF_N * W.HF_N, arith=arith)
+        model = B.Model(W.model_dict(wl, 0))
+        slot = batch.add_model(model)
+        while got < target:
+            n_inst = min(instances, math.ceil((target - got) / episode_steps))
+            recs, meta = [], []
+            for k in range(n_inst):
+                s = int(rng.integers(1 << 30))
+                v = float(rng.uniform(*V_RANGE))
+                origin = tuple(rng.uniform(-0.5, 0.5, 2)) if wl["scene"] == W.SCENE_HEIGHTFIELD else (0.0, 0.0)
+                p = W.params_dict(wl, s, v_ref=v, instance=ep_id + k, arith=arith)
+                x0 = W.initial_state(s, wl["scene"], origin=origin)
+                i = batch.admit(slot, p, x0, W.stance_knots(nk))
+                if i is None:
+                    raise RuntimeError("instance does not fit in the generation budget")
+                rec = torch.empty((episode_steps, nx + D), dtype=torch.float32, device="cuda")
+                batch.record(i, rec)
+                recs.append((i, rec))
+                meta.append((v, origin))
+            t0 = time.perf_counter()
+            for _ in range(episode_steps):
+                batch.step()
+            stream.synchronize()
+            stats["seconds"] += time.perf_counter() - t0
+            stats["control_steps"] += n_inst * episode_steps
+            stats["rollout_steps"] += n_inst * episode_steps * K * H
+            for (i, rec), (v, origin) in zip(recs, meta):
+                batch.record(i, None)
+                batch.remove(i)
+                x, mup = rec[:, :nx], rec[:, nx:]
+                ok = torch.isfinite(rec).all(1) & (x[:, 2] > FALL_Z)
+                bad = (~ok).nonzero()
+                n_ok = int(bad[0, 0]) if bad.numel() else episode_steps
+                if n_ok < episode_steps:
+                    stats["falls"] += 1
+                if n_ok == 0:
+                    continue
+                feat = torch.empty((n_ok, 40), dtype=torch.float32, device="cuda")
+                feat[:, :nx] = x[:n_ok]
+                feat[:, 0] -= origin[0]
+                feat[:, 1] -= origin[1]
+                feat[:, 37] = v
+                feat[:, 38:] = 0.0
+                tgt = (mup[:n_ok].reshape(n_ok, 12, nk) @ R.T).reshape(n_ok, 72)
+                Xs.append(feat)
+                Ys.append(tgt)
+                Es.append(torch.full((n_ok,), ep_id, dtype=torch.int32, device="cuda"))
+                got += n_ok
+                ep_id += 1
+                stats["episodes"] += 1
+            log(f"  {wl['name']}: {got}/{target} pairs, {stats['episodes']} episodes, {stats['falls']} falls")
+        del batch
+    X = torch.cat(Xs)[:n_pairs].contiguous()
+    Y = torch.cat(Ys)[:n_pairs].contiguous()
+    E = torch.cat(Es)[:n_pairs].contiguous()
+    return dict(X=X, Y=Y, episode=E, stats=stats)
+
+
+def split(data, holdout=0.05, seed=0):
+    """Training / held-out row indices by episode."""
+    import torch
+    E = data["episode"].cpu().numpy()
+    eps = np.unique(E)
+    rng = np.random.default_rng([seed, 78])
+    held = set(rng.choice(eps, max(1, int(len(eps) * holdout)), replace=False).tolist())
+    mask = np.array([e in held for e in E])
+    tr = torch.as_tensor(np.nonzero(~mask)[0].astype(np.int32), device="cuda")
+    ho = torch.as_tensor(np.nonzero(mask)[0].astype(np.int32), device="cuda")
+    return tr, ho
+
+
+def normalization(data, rows, floor=1e-3):
+    X, Y = data["X"][rows.long()], data["Y"][rows.long()]
+    im, isd = X.mean(0), X.std(0).clamp_min(floor)
+    om, osd = Y.mean(0), Y.std(0).clamp_min(floor)
+    return [t.double().cpu().numpy() for t in (im, isd, om, osd)]
+
+
+def nll(policy, data, rows, chunk=4096):
+    """Held-out Gaussian NLL (mean over rows and outputs) from forward passes."""
+    import torch
+    X, Y = data["X"], data["Y"]
+    om, osd = policy._norm[2], policy._norm[3]
+    om = torch.as_tensor(om, dtype=torch.float32, device="cuda")
+    osd = torch.as_tensor(osd, dtype=torch.float32, device="cuda")
+    tot, n = 0.0, 0
+    chunk = min(chunk, policy.max_batch)
+    for a in range(0, rows.numel(), chunk):
+        r = rows[a:a + chunk].long()
+        out = policy.forward(X[r].contiguous())
+        y = (Y[r] - om) / osd
+        m, s = out[:, :72], out[:, 72:]
+        tot += float((0.5 * (y - m) ** 2 * torch.exp(-2 * s) + s).sum())
+        n += r.numel() * 72
+    return tot / n
+
+
+def train(policy, data, rows, epochs=10, batch=4096, lr=1e-3, seed=0, held=None, log=print):
+    """Adam on the Gaussian NLL.  Returns per-epoch (train loss, held-out NLL, seconds)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    n = rows.numel()
+    for ep in range(epochs):
+        perm = rows[torch.randperm(n, generator=g, device="cuda")].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = torch.zeros(1, dtype=torch.float32, device="cuda")
+        steps = 0
+        for a in range(0, n - batch + 1, batch):
+            policy.train_step(data["X"], data["Y"], index=perm[a:a + batch], B=batch, lr=lr, loss=loss)
+            acc += loss
+            steps += 1
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tl = float(acc.item()) / max(steps, 1)
+        hl = nll(policy, data, held) if held is not None else float("nan")
+        hist.append((tl, hl, dt, steps))
+        log(f"  epoch {ep}: train NLL {tl:.4f}  held-out NLL {hl:.4f}  {dt:.2f} s ({steps} steps)")
+    return hist

@@ -156,3 +156,44 @@ def test_autotune_and_replay_determinism(B):
         assert a[4] == b[4]
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_record_rows_are_step_states_and_unshifted_updates(B):
+    """Recorded row s holds the state control step s started from and that step's
+    updated knots mu'_s: S mu'_s is the nominal after the step, mu'_s at knot 0 the
+    applied control, and the single-instance update of the same step gives mu'_s."""
+    batch, slots, models, mds = _setup(B)
+    wl, K, H, nk, seed, inst = W.TERRAIN_WALK, 300, 40, 6, 1, 7
+    p = _params(wl, K, H, nk, seed, inst)
+    x0 = _init_state(wl, seed)
+    mu = f32(W.stance_knots(nk))
+    i = batch.admit(slots[wl["name"]], p, x0, mu)
+    other = batch.admit(slots["flat_walk"], _params(W.FLAT_WALK, 64, 25, 4, 0, 3), _init_state(W.FLAT_WALK, 0),
+                        f32(W.stance_knots(4)))
+    nx, D, cap = 37, 12 * nk, 3
+    rec = torch.full((cap, nx + D), float("nan"), device="cuda")
+    batch.record(i, rec)
+    S = O.shift_matrix(nk, H, p["dt"])
+    xs, mus, u0s = [x0], [], []
+    for s in range(5):
+        batch.step()
+        x, u0, nom, _, step = batch.read(i, nx, nk)
+        r = rec[s % cap].cpu().numpy()
+        np.testing.assert_array_equal(r[:nx], xs[-1].astype(np.float32))
+        mup = r[nx:].astype(np.float64)
+        np.testing.assert_array_equal(mup.reshape(12, nk)[:, 0], u0)
+        assert np.abs((mup.reshape(12, nk) @ S.T).reshape(-1) - nom).max() <= 1e-5
+        if s == 0:  # the same step through the single-instance kernels
+            ctl = B.Controller(models[wl["name"]], p)
+            ctl.set_nominal(_dev(mu))
+            costs = ctl.rollout_batch(_dev(x0))
+            knots = ctl.update(costs).cpu().numpy()
+            assert np.abs(knots - mup).max() <= 1e-5
+        xs.append(f32(x))
+        assert step == s + 1
+    batch.record(i, None)
+    snap = rec.clone()
+    batch.step()
+    torch.cuda.synchronize()
+    assert torch.equal(snap, rec)  # recording stopped
+    batch.remove(other)

@@ -139,6 +139,8 @@ def test_adam_two_steps_match_oracle_and_refresh_bf16_weights(B):
 def test_train_step_reduces_loss_and_checkpoint_round_trip(B, tmp_path):
     pol = B.Policy(max_batch=128, seed=8)
     rng = np.random.default_rng(1)
+    norm = (rng.normal(size=40), rng.uniform(0.5, 2, 40), rng.normal(size=72), rng.uniform(0.5, 2, 72))
+    pol.set_normalization(*norm)
     X = _dev(rng.normal(size=(128, 40)))
     W0 = rng.normal(size=(40, 72)) * 0.3
     Y = _dev(np.tanh(rng.normal(size=(128, 40)) @ W0))
@@ -148,6 +150,8 @@ def test_train_step_reduces_loss_and_checkpoint_round_trip(B, tmp_path):
     pol.save(path)
     pol2 = B.Policy(max_batch=128, ckpt=str(path))
     assert pol2.steps == pol.steps == 30
+    for a, b in zip(pol2.get_normalization(), norm):
+        np.testing.assert_array_equal(a, np.float32(b))
     assert torch.equal(pol2.get_params(), pol.get_params())
     # identical next step from the restored moments
     l1 = pol.train_step(X, Y, lr=1e-3)
@@ -237,3 +241,24 @@ def test_learned_step_matches_oracle_chain(B):
     ctl.set_proposal(None)
     ctl.step(_dev(x0))
     assert ctl.proposal_stats()[1] == 1  # plain steps are not counted
+
+
+def test_training_pipeline_on_closed_loop_data(B):
+    """Pairs from GPU closed loops of both walking configs, then a few Adam epochs: the
+    held-out NLL falls well below the untrained network's."""
+    from paper_2409_10469_amd import proposal as PR
+    data = PR.generate(n_pairs=16000, episode_steps=40, instances=64, seed=3, log=lambda *a: None)
+    X, Y = data["X"], data["Y"]
+    assert X.shape == (16000, 40) and Y.shape == (16000, 72)
+    assert torch.isfinite(X).all() and torch.isfinite(Y).all()
+    assert (X[:, 2] > PR.FALL_Z).all()
+    v = X[:, 37].cpu().numpy()
+    assert v.min() >= 0.0 and v.max() <= 0.8 and (X[:, 38:] == 0).all()
+    tr, ho = PR.split(data, holdout=0.1, seed=0)
+    assert tr.numel() + ho.numel() == 16000 and ho.numel() > 0
+    pol = B.Policy(max_batch=1024, seed=1)
+    pol.set_normalization(*PR.normalization(data, tr))
+    before = PR.nll(pol, data, ho)
+    hist = PR.train(pol, data, tr, epochs=4, batch=1024, lr=1e-3, seed=0, held=ho, log=lambda *a: None)
+    after = hist[-1][1]
+    assert np.isfinite(after) and after < before - 0.5, (before, after)
