@@ -77,11 +77,14 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="heightfield_walk",
-                    help="heightfield_walk (default), flat_walk, box_push, box_climb or batched_serving")
+                    help="heightfield_walk (default), flat_walk, box_push, box_climb, batched_serving or "
+                         "proposal_training")
     ap.add_argument("--arith", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pairs", type=int, default=1_000_000, help="proposal_training: closed-loop pairs")
+    ap.add_argument("--epochs", type=int, default=8, help="proposal_training: Adam epochs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -101,6 +104,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched_serving":
         return bench_serving(args)
+    if args.workload == "proposal_training":
+        return bench_proposal(args)
     wl = W.WORKLOADS[args.workload]
     md = W.model_dict(wl, args.seed)
     p = W.params_dict(wl, args.seed, arith=args.arith)
@@ -218,6 +223,72 @@ def bench_serving(args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None},
         "budget": r["stats"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def mlp_train_flops_per_pair():
+    """Algorithmic flops of one training pair: forward and weight-gradient products over
+    every layer, input-gradient products over layers 1..4 (2 flops per multiply-add)."""
+    dims = (40, 512, 512, 512, 512, 144)
+    layers = list(zip(dims[:-1], dims[1:]))
+    fwd = sum(2 * a * b for a, b in layers)
+    return 2 * fwd + sum(2 * a * b for a, b in layers[1:])
+
+
+def bench_proposal(args):
+    """Learned-proposal training: closed-loop pairs from the flat and heightfield walks
+    generated on the GPU, then Adam epochs on the Gaussian NLL (batch 4096)."""
+    import numpy as np
+    import torch
+    from paper_2409_10469_amd import binding as B
+    from paper_2409_10469_amd import proposal as PR
+    log = lambda m: print(m, flush=True)
+    t0 = time.perf_counter()
+    data = PR.generate(n_pairs=args.pairs, episode_steps=200, instances=256, seed=args.seed, arith=args.arith, log=log)
+    gen_s = time.perf_counter() - t0
+    tr, ho = PR.split(data, holdout=0.05, seed=args.seed)
+    pol = B.Policy(max_batch=4096, seed=args.seed)
+    pol.set_normalization(*PR.normalization(data, tr))
+    nll0 = PR.nll(pol, data, ho)
+    hist = PR.train(pol, data, tr, epochs=args.epochs, batch=4096, lr=1e-3, seed=args.seed, held=ho, log=log)
+    # timed train steps for the roofline (events on the policy's stream)
+    stream = torch.cuda.current_stream()
+    idx = tr[:4096].contiguous()
+    loss = torch.empty(1, device="cuda")
+    for _ in range(5):
+        pol.train_step(data["X"], data["Y"], index=idx, B=4096, lr=0.0, loss=loss)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_t = 50
+    e0.record(stream)
+    for _ in range(n_t):
+        pol.train_step(data["X"], data["Y"], index=idx, B=4096, lr=0.0, loss=loss)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / n_t
+    fl = mlp_train_flops_per_pair() * 4096
+    achieved = fl / (step_ms * 1e-3) / 1e12
+    pairs_s = 4096 / (step_ms * 1e-3)
+    train_s = sum(h[2] for h in hist)
+    train_steps = sum(h[3] for h in hist)
+    st = data["stats"]
+    out = {
+        "metric": "learned-proposal training pairs/sec", "value": pairs_s, "unit": "pairs/s", "n_gpus": 1,
+        "steps": n_t, "warmup": 5, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (fp32 accumulate, fp32 Adam)", "data": "synthetic (GPU closed loops)",
+        "config": {"workload": "proposal_training", "network": "40-512x4-144 SiLU", "batch": 4096,
+                   "pairs": int(data["X"].shape[0]), "held_out_pairs": int(ho.numel()), "epochs": args.epochs,
+                   "sources": "flat_walk (K=64,H=25,4 knots -> 6) + heightfield_walk (K=1024,H=50,6 knots)",
+                   "rollout_arithmetic": args.arith},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None, "flops_per_pair": mlp_train_flops_per_pair(),
+                     "scope": "whole train step (13 GEMMs, loss, reduction, Adam)"},
+        "held_out_nll": {"untrained": nll0, "per_epoch": [h[1] for h in hist]},
+        "train_nll_per_epoch": [h[0] for h in hist],
+        "epoch_seconds": train_s / max(len(hist), 1), "train_steps": train_steps,
+        "generation": {"seconds": gen_s, "batch_seconds": st["seconds"], "episodes": st["episodes"],
+                       "falls": st["falls"], "control_steps": st["control_steps"],
+                       "rollout_steps_per_s": st["rollout_steps"] / max(st["seconds"], 1e-9)},
     }
     print(json.dumps(out), flush=True)
 
