@@ -102,19 +102,15 @@ mppi_status mppi_policy_head(mppi_policy *pol, const float *d_out, int n_knots, 
 const char *mppi_policy_last_error(const mppi_policy *pol);
 
 /* ---- controller side -------------------------------------------------------------
- * DISABLED IN THIS BUILD: the three calls below validate nothing and return MPPI_EINVAL
- * ("disabled"); their first GPU run ended in a memory fault whose cause has not been
- * identified.  The intended behaviour, which the CPU oracle implements, is:
- *
  * One control step with an explicit proposal (mean d_center, std d_sd; 12 * n_knots
  * floats each, device): k_prop samples theta_0 = center, theta_1 = the current (shifted)
- * nominal, theta_n = center + sd * eps_n for 2 <= n < k_prop, with eps_n the same Philox
- * noise a plain step draws for sample n.  If the rollout cost of the centre is finite and
- * not above the nominal's, Eq. 1 and Eq. 2 run over these k_prop samples; otherwise the
- * step falls back to a plain step with K samples (the fallback launch is always queued
- * and exits at once when the proposal was accepted).  Then, as in mppi_step, the first
- * control goes to d_u0_out, the nominal is shifted and the step counter advances.
- * 2 <= k_prop <= K. */
+ * nominal, theta_n = center + sd * eps_n for 2 <= n < k_prop, with eps_n drawn from the
+ * same Philox counters as a plain step (Box-Muller evaluated as mppi_sample does).
+ * If the rollout cost of the centre is finite and not above the nominal's, Eq. 1 and
+ * Eq. 2 run over these k_prop samples; otherwise the step is a plain step with K
+ * samples.  Then, as in mppi_step, the first control goes to d_u0_out, the nominal is
+ * shifted and the step counter advances.  The two leading costs are read on the host to
+ * choose the branch, so the call synchronises the bound stream.  2 <= k_prop <= K. */
 mppi_status mppi_step_proposal(mppi_ctx *ctx, const float *d_x0, const float *d_center, const float *d_sd,
                                int k_prop, float *d_u0_out);
 /* Makes every later mppi_step of ctx use the policy: features of the current state and
@@ -123,7 +119,7 @@ mppi_status mppi_step_proposal(mppi_ctx *ctx, const float *d_x0, const float *d_
  * stream; the policy must not be used on another stream meanwhile.  pol NULL switches
  * the proposal off.  Requires a 37-float state model. */
 mppi_status mppi_set_proposal(mppi_ctx *ctx, mppi_policy *pol, int k_prop, const float *cmd, const float *origin_xy);
-/* Synchronises and reports how many proposal steps ran and how many were accepted. */
+/* How many proposal steps ran and how many were accepted (host counters). */
 mppi_status mppi_proposal_stats(mppi_ctx *ctx, int *accepted, int *steps);
 
 #ifdef __cplusplus

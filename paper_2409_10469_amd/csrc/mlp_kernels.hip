@@ -247,57 +247,59 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-// one block per 64 rows; thread d < 72 owns output pair (mean d, log-std 72 + d)
+// One block per kLossRows rows.  Phase 1: every (row, output pair d) element is
+// independent; thread t takes elements t, t + 256, ... (9 each), writes the row-major dz
+// and keeps both errors in an LDS tile.  Phase 2: the tile gives the transposed dz rows
+// (16-byte stores), the per-column sums of the block (fixed order) and the loss sum.
+constexpr int kLossRows = 32;
 __global__ __launch_bounds__(256) void loss_kernel(LossArgs a)
 {
+    __shared__ float sD[kOut][kLossRows + 1];
     __shared__ float red[256];
-    const int t = threadIdx.x, r0 = blockIdx.x * 64;
+    const int t = threadIdx.x, r0 = blockIdx.x * kLossRows;
     const float inv = 1.f / ((float)a.B * 72.f);
-    float lsum = 0.f, sm = 0.f, ss = 0.f;
-    for (int r8 = 0; r8 < 64; r8 += 8) {
-        bf16x8 pm, ps;
+    float lsum = 0.f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int r = r0 + r8 + u;
-            float dm = 0.f, dsv = 0.f;
-            if (t < 72 && r < a.B) {
-                const int row = a.idx ? a.idx[r] : r;
-                const float y = (a.Y[(size_t)row * 72 + t] - a.omean[t]) / a.ostd[t];
-                const float m = a.out[(size_t)r * kOut + t], s = a.out[(size_t)r * kOut + 72 + t];
-                const float e = y - m, w = expf(-2.f * s), q = e * e * w;
-                lsum += 0.5f * q + s;
-                dm = -e * w * inv;
-                dsv = (1.f - q) * inv;
-                sm += dm;
-                ss += dsv;
-            }
-            pm[u] = (__bf16)dm;
-            ps[u] = (__bf16)dsv;
-            if (t < 72) {
-                a.dZ[(size_t)r * kOutPad + t] = pm[u];
-                a.dZ[(size_t)r * kOutPad + 72 + t] = ps[u];
-            } else if (t >= 144 && t < kOutPad) {
-                a.dZ[(size_t)r * kOutPad + t] = pm[u];
-            }
+    for (int j = 0; j < kLossRows * 72 / 256; ++j) {
+        const int e = t + 256 * j, rr = e / 72, d = e - rr * 72, r = r0 + rr;
+        float dm = 0.f, dsv = 0.f;
+        if (r < a.B) {
+            const int row = a.idx ? a.idx[r] : r;
+            const float y = (a.Y[(size_t)row * 72 + d] - a.omean[d]) / a.ostd[d];
+            const float m = a.out[(size_t)r * kOut + d], s = a.out[(size_t)r * kOut + 72 + d];
+            const float err = y - m, w = expf(-2.f * s), q = err * err * w;
+            lsum += 0.5f * q + s;
+            dm = -err * w * inv;
+            dsv = (1.f - q) * inv;
         }
-        const size_t r = (size_t)(r0 + r8);
-        if (t < 72) {
-            *reinterpret_cast<bf16x8*>(a.dZt + (size_t)t * a.Bp + r) = pm;
-            *reinterpret_cast<bf16x8*>(a.dZt + (size_t)(72 + t) * a.Bp + r) = ps;
-        } else if (t >= 144 && t < kOutPad) {
-            *reinterpret_cast<bf16x8*>(a.dZt + (size_t)t * a.Bp + r) = pm;
-        }
+        sD[d][rr] = dm;
+        sD[72 + d][rr] = dsv;
+        a.dZ[(size_t)r * kOutPad + d] = (__bf16)dm;
+        a.dZ[(size_t)r * kOutPad + 72 + d] = (__bf16)dsv;
     }
-    if (t < 72) {
-        a.dbpart[(size_t)blockIdx.x * kOutPad + t] = sm;
-        a.dbpart[(size_t)blockIdx.x * kOutPad + 72 + t] = ss;
-    } else if (t >= 144 && t < kOutPad) {
-        a.dbpart[(size_t)blockIdx.x * kOutPad + t] = 0.f;
+    // zero padding columns of the row-major copy: 48 per row
+    for (int e = t; e < kLossRows * (kOutPad - kOut); e += 256) {
+        const int rr = e / (kOutPad - kOut), c = kOut + (e - rr * (kOutPad - kOut));
+        a.dZ[(size_t)(r0 + rr) * kOutPad + c] = (__bf16)0.f;
     }
     red[t] = lsum;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
+    // transposed rows: kOutPad columns x kLossRows rows in 8-element chunks
+    for (int e = t; e < kOutPad * (kLossRows / 8); e += 256) {
+        const int c = e / (kLossRows / 8), k8 = (e - c * (kLossRows / 8)) * 8;
+        bf16x8 v;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (__bf16)(c < kOut ? sD[c][k8 + u] : 0.f);
+        *reinterpret_cast<bf16x8*>(a.dZt + (size_t)c * a.Bp + r0 + k8) = v;
+    }
+    if (t < kOutPad) {
+        float cs = 0.f;
+        if (t < kOut)
+            for (int rr = 0; rr < kLossRows; ++rr) cs += sD[t][rr];
+        a.dbpart[(size_t)blockIdx.x * kOutPad + t] = cs;
+    }
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) red[t] += red[t + st];
         __syncthreads();
     }
     if (t == 0) a.lpart[blockIdx.x] = red[0];
@@ -305,10 +307,12 @@ __global__ __launch_bounds__(256) void loss_kernel(LossArgs a)
 
 hipError_t launch_loss(const LossArgs& a, hipStream_t st)
 {
-    if (a.Bp % 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(loss_kernel, dim3(a.Bp / 64), dim3(256), 0, st, a);
+    if (a.Bp % kLossRows) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(loss_kernel, dim3(a.Bp / kLossRows), dim3(256), 0, st, a);
     return hipGetLastError();
 }
+
+int loss_rows_per_block() { return kLossRows; }
 
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ int find_layer(const LayerGeom& g, int p)
@@ -320,6 +324,8 @@ __device__ __forceinline__ int find_layer(const LayerGeom& g, int p)
     return l;
 }
 
+__device__ __forceinline__ float reduced_grad(const ReduceArgs& a, int p);
+
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
@@ -329,6 +335,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
         a.loss[0] = s * a.lscale;
     }
     if (p >= a.g.off[kLayers]) return;
+    a.G[p] = reduced_grad(a, p);
+}
+
+// gradient of parameter p from the fixed-order partial sums
+__device__ __forceinline__ float reduced_grad(const ReduceArgs& a, int p)
+{
     const int l = find_layer(a.g, p);
     const int q = p - a.g.off[l], fi = a.g.fi[l], fo = a.g.fo[l], fop = a.g.fop[l];
     float s = 0.f;
@@ -342,7 +354,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
         const float* b = a.bpart[l] + o;
         for (int k = 0; k < a.T[l]; ++k) s += b[(size_t)k * fop];
     }
-    a.G[p] = s;
+    return s;
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st)
@@ -354,13 +366,10 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st)
 
 // Adam (Kingma and Ba): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
 // p <- p - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps); then the bf16 shadows
-__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a)
+__device__ __forceinline__ void adam_update(const AdamArgs& a, int p, float gr)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.g.off[kLayers]) return;
     float w = a.P[p];
     if (a.update) {
-        const float gr = a.G[p];
         const float m = a.b1 * a.m[p] + a.omb1 * gr;
         const float v = a.b2 * a.v[p] + a.omb2 * gr * gr;
         a.m[p] = m;
@@ -375,6 +384,34 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a)
         a.Wt[l][(size_t)o * a.g.fip[l] + i] = (__bf16)w;
         if (a.Wn[l]) a.Wn[l][(size_t)i * a.g.fop[l] + o] = (__bf16)w;
     }
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.g.off[kLayers]) return;
+    adam_update(a, p, a.update ? a.G[p] : 0.f);
+}
+
+// training step tail: fixed-order gradient reduction and Adam in one pass (the gradient
+// is not stored)
+__global__ __launch_bounds__(256) void reduce_adam_kernel(ReduceArgs r, AdamArgs a)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p == 0 && r.loss) {
+        float s = 0.f;
+        for (int i = 0; i < r.nl; ++i) s += r.lpart[i];
+        r.loss[0] = s * r.lscale;
+    }
+    if (p >= r.g.off[kLayers]) return;
+    adam_update(a, p, reduced_grad(r, p));
+}
+
+hipError_t launch_reduce_adam(const ReduceArgs& r, const AdamArgs& a, hipStream_t st)
+{
+    const int n = r.g.off[kLayers];
+    hipLaunchKernelGGL(reduce_adam_kernel, dim3((n + 255) / 256), dim3(256), 0, st, r, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st)

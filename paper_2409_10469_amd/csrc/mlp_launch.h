@@ -64,10 +64,11 @@ struct LossArgs {
     const float* ostd;
     __bf16* dZ;     // [Bp x 192]
     __bf16* dZt;    // [192 x Bp]
-    float* dbpart;  // [Bp / 64][192]
-    float* lpart;   // [Bp / 64]
+    float* dbpart;  // [Bp / loss_rows_per_block()][192]
+    float* lpart;   // [Bp / loss_rows_per_block()]
 };
 hipError_t launch_loss(const LossArgs& a, hipStream_t st);
+int loss_rows_per_block();  // rows of one loss workgroup (Bp must be a multiple); partial rows = Bp / this
 
 struct LayerGeom {
     int off[kLayers + 1];  // flat parameter offsets (W then b per layer)
@@ -102,6 +103,8 @@ struct AdamArgs {
     int update;
 };
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
+// the reduction of launch_reduce and the update of launch_adam in one pass (G not stored)
+hipError_t launch_reduce_adam(const ReduceArgs& r, const AdamArgs& a, hipStream_t st);
 
 // network output (standardised) -> proposal centre and std for nk knots per joint
 struct HeadArgs {

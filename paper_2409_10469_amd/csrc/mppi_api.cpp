@@ -14,6 +14,8 @@
 
 #include "mppi_device.h"
 #include "mppi_launch.h"
+#include "policy_internal.h"
+#include "proposal_launch.h"
 
 struct mppi_model {
     mppi_model_desc desc;
@@ -33,7 +35,13 @@ struct mppi_ctx {
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
     size_t off_B, off_S, off_hf, off_mu, off_eps, off_costs, off_w, off_status, total;
+    // learned proposal: command and origin, centre, std, proposal costs and noise
+    size_t off_cmd, off_center, off_sd, off_costs_p, off_eps_p;
     uint32_t step = 0;
+    mppi_policy* policy = nullptr;
+    int k_prop = 0;
+    float cmd_origin[8] = {};
+    int prop_accepted = 0, prop_steps = 0;
     std::string err;
 };
 
@@ -317,6 +325,11 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     c->off_costs = o; o = align256(o + sizeof(float) * p->K);
     c->off_w = o; o = align256(o + sizeof(float) * p->K);
     c->off_status = o; o = align256(o + sizeof(int) * 16);
+    c->off_cmd = o; o = align256(o + sizeof(float) * 8);
+    c->off_center = o; o = align256(o + sizeof(float) * c->D);
+    c->off_sd = o; o = align256(o + sizeof(float) * c->D);
+    c->off_costs_p = o; o = align256(o + sizeof(float) * p->K);
+    c->off_eps_p = o; o = align256(o + sizeof(float) * (size_t)c->D * p->K);
     c->total = o;
     *out = c;
     return MPPI_OK;
@@ -445,11 +458,80 @@ mppi_status mppi_update(mppi_ctx* c, const float* d_costs, const float* d_eps, f
     return update(c, d_costs, d_eps, d_knots_out, nullptr, nullptr, d_weights_out);
 }
 
+// Proposal step on the plain kernels: the k_prop samples theta_n = c + e_n are rolled out
+// through the explicit-noise path with unit scale, where e holds Philox noise scaled by
+// sd for n >= 2, zero for the centre (n = 0) and nominal - c for n = 1.  The gate reads
+// the two leading costs on the host.  Accepted: the update with centre c and unit scale
+// gives mu' = c + sum w_n e_n / sum w_n, the weighted mean of theta.  Otherwise the plain
+// step runs.
+static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int kp,
+                                 float* d_u0_out)
+{
+    mppi_status s;
+    mppi::DevParams Pp = dev_params(c);
+    Pp.K = kp;
+    Pp.sigma = 1.0f;
+    float* e = wsf(c, c->off_eps_p);
+    float* costs_p = wsf(c, c->off_costs_p);
+    if ((s = hip_check(c, mppi::launch_sample(Pp, c->D, e, nullptr, c->stream), "proposal noise launch"))) return s;
+    if ((s = hip_check(c, prop::launch_proposal_noise(kp, c->D, e, d_center, d_sd, wsf(c, c->off_mu), c->stream),
+                       "proposal scale launch")))
+        return s;
+    mppi::RolloutArgs a{};
+    a.B = (const double*)wsf(c, c->off_B);
+    a.hf = wsf(c, c->off_hf);
+    a.mu = d_center;
+    a.x0 = d_x0;
+    a.eps_in = e;
+    a.eps_sn = c->D;
+    a.eps_sd = 1;
+    a.costs = costs_p;
+    a.samples_per_block = 16;
+    if ((s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, Pp, a, c->stream),
+                       "proposal rollout launch")))
+        return s;
+    float head[2];
+    if ((s = hip_check(c, hipMemcpyAsync(head, costs_p, sizeof(head), hipMemcpyDeviceToHost, c->stream), "gate read")) ||
+        (s = hip_check(c, hipStreamSynchronize(c->stream), "gate synchronise")))
+        return s;
+    const bool accepted = std::isfinite(head[0]) && head[0] <= head[1];
+    c->prop_steps += 1;
+    if (accepted) {
+        c->prop_accepted += 1;
+        mppi::UpdateArgs u{};
+        u.costs = costs_p;
+        u.eps = e;
+        u.eps_sn = c->D;
+        u.eps_sd = 1;
+        u.mu = d_center;
+        u.S = wsf(c, c->off_S);
+        u.nominal_out = wsf(c, c->off_mu);
+        u.u0_out = d_u0_out;
+        u.status = (int*)wsf(c, c->off_status);
+        if ((s = hip_check(c, mppi::launch_update(Pp, u, c->stream), "proposal update launch"))) return s;
+        c->step += 1;
+        return MPPI_OK;
+    }
+    float* costs = wsf(c, c->off_costs);
+    if ((s = rollout(c, d_x0, nullptr, costs, nullptr))) return s;
+    if ((s = update(c, costs, nullptr, nullptr, wsf(c, c->off_mu), d_u0_out, nullptr))) return s;
+    c->step += 1;
+    return MPPI_OK;
+}
+
 mppi_status mppi_step(mppi_ctx* c, const float* d_x0, float* d_u0_out)
 {
     mppi_status s;
     if ((s = need_bound(c))) return s;
     if (!d_x0 || !d_u0_out) return fail(c, MPPI_EINVAL, "null state or control buffer");
+    if (c->policy) {
+        float* center = wsf(c, c->off_center);
+        float* sd = wsf(c, c->off_sd);
+        if ((s = mppi_host::policy_infer(c->policy, d_x0, wsf(c, c->off_cmd), c->p.n_knots, c->p.sigma, center, sd,
+                                         c->stream)))
+            return fail(c, s, std::string("proposal: ") + mppi_host::policy_error(c->policy));
+        return step_proposal(c, d_x0, center, sd, c->k_prop, d_u0_out);
+    }
     float* costs = wsf(c, c->off_costs);
     if ((s = rollout(c, d_x0, nullptr, costs, nullptr))) return s;
     if ((s = update(c, costs, nullptr, nullptr, wsf(c, c->off_mu), d_u0_out, nullptr))) return s;
@@ -479,21 +561,46 @@ mppi_status mppi_sync_status(mppi_ctx* c)
     return st ? MPPI_WARN_ALL_NONFINITE : MPPI_OK;
 }
 
-// The proposal control step is switched off: its first GPU run ended in a memory
-// fault whose cause has not been identified; these entry points refuse until it is.
-mppi_status mppi_step_proposal(mppi_ctx* c, const float*, const float*, const float*, int, float*)
+mppi_status mppi_step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int k_prop,
+                               float* d_u0_out)
 {
-    return fail(c, MPPI_EINVAL, "the learned-proposal control step is disabled in this build");
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!d_x0 || !d_center || !d_sd || !d_u0_out) return fail(c, MPPI_EINVAL, "null argument");
+    if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
+    return step_proposal(c, d_x0, d_center, d_sd, k_prop, d_u0_out);
 }
 
-mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy*, int, const float*, const float*)
+mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, const float* cmd, const float* origin_xy)
 {
-    return fail(c, MPPI_EINVAL, "the learned-proposal control step is disabled in this build");
+    mppi_status s;
+    if ((s = need_bound(c))) return s;
+    if (!pol) {
+        c->policy = nullptr;
+        return MPPI_OK;
+    }
+    if (c->model.nx != 37) return fail(c, MPPI_EINVAL, "the proposal needs a 37-float state model");
+    if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
+    if (!cmd || !origin_xy) return fail(c, MPPI_EINVAL, "null command or origin");
+    if (!(c->p.sigma > 0.f)) return fail(c, MPPI_EINVAL, "the proposal needs sigma > 0 (upper std clamp)");
+    for (int i = 0; i < 3; ++i) c->cmd_origin[i] = cmd[i];
+    c->cmd_origin[3] = origin_xy[0];
+    c->cmd_origin[4] = origin_xy[1];
+    if ((s = hip_check(c, hipMemcpyAsync(wsf(c, c->off_cmd), c->cmd_origin, sizeof(float) * 8, hipMemcpyHostToDevice,
+                                         c->stream), "upload command")) ||
+        (s = hip_check(c, hipStreamSynchronize(c->stream), "synchronise")))
+        return s;
+    c->policy = pol;
+    c->k_prop = k_prop;
+    return MPPI_OK;
 }
 
-mppi_status mppi_proposal_stats(mppi_ctx* c, int*, int*)
+mppi_status mppi_proposal_stats(mppi_ctx* c, int* accepted, int* steps)
 {
-    return fail(c, MPPI_EINVAL, "the learned-proposal control step is disabled in this build");
+    if (!c) return fail(nullptr, MPPI_EINVAL, "null context");
+    if (accepted) *accepted = c->prop_accepted;
+    if (steps) *steps = c->prop_steps;
+    return MPPI_OK;
 }
 
 mppi_status mppi_sim_step(const mppi_model* m, int arith, int n, const float* d_x, const float* d_u, float kp,

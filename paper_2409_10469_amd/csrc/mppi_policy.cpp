@@ -14,6 +14,7 @@
 
 #include "mlp_launch.h"
 #include "policy_internal.h"
+#include "proposal_launch.h"
 
 using namespace mlp;
 
@@ -28,7 +29,7 @@ struct mppi_policy {
     LayerGeom geom{};
     size_t o_P, o_m, o_v, o_G, o_Wt[kLayers], o_Wn[kLayers], o_norm, o_X0, o_X0t;
     size_t o_Z[kLayers - 1], o_H[kLayers - 1], o_Ht[kLayers - 1];
-    size_t o_out, o_dZ[2], o_dZt[2], o_wpart[kLayers], o_bpart[kLayers], o_lpart, o_loss;
+    size_t o_out, o_dZ[2], o_dZt[2], o_wpart[kLayers], o_bpart[kLayers], o_lpart, o_loss, o_feat, o_out1;
     size_t shadow_begin, shadow_end, total;
     std::string err;
 };
@@ -114,9 +115,13 @@ void layout(mppi_policy* p)
         p->o_dZt[i] = take(2ull * bp * kHidden);
     }
     for (int l = 0; l < kLayers; ++l) p->o_wpart[l] = take(4ull * kMaxSplits * kFip[l] * kFop[l]);
-    for (int l = 0; l < kLayers; ++l) p->o_bpart[l] = take(4ull * (bp / 64) * kFop[l]);
-    p->o_lpart = take(4ull * (bp / 64));
+    // column-sum partials: at most one row per 32 batch rows (loss workgroups; the
+    // input-gradient GEMM tiles are 64 or 128 rows)
+    for (int l = 0; l < kLayers; ++l) p->o_bpart[l] = take(4ull * (bp / 32) * kFop[l]);
+    p->o_lpart = take(4ull * (bp / 32));
     p->o_loss = take(4ull * 4);
+    p->o_feat = take(4ull * kIn);
+    p->o_out1 = take(4ull * kOut);
     p->total = o;
 }
 
@@ -180,8 +185,9 @@ mppi_status forward(mppi_policy* p, const float* d_in, const int* d_idx, int B, 
     return MPPI_OK;
 }
 
-mppi_status grad(mppi_policy* p, const float* d_in, const float* d_target, const int* d_idx, int B, float* d_grad,
-                 float* d_loss, hipStream_t st)
+// forward, loss and backward products; ra receives the partial-sum layout of the gradient
+mppi_status backward(mppi_policy* p, const float* d_in, const float* d_target, const int* d_idx, int B,
+                     ReduceArgs& ra, hipStream_t st)
 {
     const int bp = pad64(B);
     mppi_status s;
@@ -191,9 +197,9 @@ mppi_status grad(mppi_policy* p, const float* d_in, const float* d_target, const
     LossArgs la{out, d_target, d_idx, B, bp, nrm + 80, nrm + 152, at<__bf16>(p, p->o_dZ[0]),
                 at<__bf16>(p, p->o_dZt[0]), at<float>(p, p->o_bpart[kLayers - 1]), at<float>(p, p->o_lpart)};
     if ((s = phip(p, launch_loss(la, st), "loss launch"))) return s;
-    ReduceArgs ra{};
+    ra = ReduceArgs{};
     ra.g = p->geom;
-    ra.T[kLayers - 1] = bp / 64;
+    ra.T[kLayers - 1] = bp / loss_rows_per_block();
     const int S = batch_splits(bp);
     int cur = 0;
     for (int l = kLayers - 1; l >= 0; --l) {
@@ -234,15 +240,24 @@ mppi_status grad(mppi_policy* p, const float* d_in, const float* d_target, const
         if ((s = phip(p, launch_gemm(EPI_DACT, d, 1, st), "input-gradient launch"))) return s;
         cur ^= 1;
     }
-    ra.G = d_grad;
     ra.lpart = at<float>(p, p->o_lpart);
-    ra.nl = bp / 64;
+    ra.nl = bp / loss_rows_per_block();
     ra.lscale = (float)(1.0 / ((double)B * 72.0));
+    return MPPI_OK;
+}
+
+mppi_status grad(mppi_policy* p, const float* d_in, const float* d_target, const int* d_idx, int B, float* d_grad,
+                 float* d_loss, hipStream_t st)
+{
+    ReduceArgs ra;
+    mppi_status s;
+    if ((s = backward(p, d_in, d_target, d_idx, B, ra, st))) return s;
+    ra.G = d_grad;
     ra.loss = d_loss;
     return phip(p, launch_reduce(ra, st), "reduce launch");
 }
 
-mppi_status adam(mppi_policy* p, const float* d_grad, float lr, hipStream_t st)
+AdamArgs adam_args(mppi_policy* p, const float* d_grad, float lr)
 {
     const int t = p->steps + 1;
     AdamArgs a{};
@@ -264,8 +279,13 @@ mppi_status adam(mppi_policy* p, const float* d_grad, float lr, hipStream_t st)
         a.Wn[l] = l ? at<__bf16>(p, p->o_Wn[l]) : nullptr;
     }
     a.update = 1;
-    mppi_status s = phip(p, launch_adam(a, st), "adam launch");
-    if (!s) p->steps = t;
+    return a;
+}
+
+mppi_status adam(mppi_policy* p, const float* d_grad, float lr, hipStream_t st)
+{
+    mppi_status s = phip(p, launch_adam(adam_args(p, d_grad, lr), st), "adam launch");
+    if (!s) p->steps += 1;
     return s;
 }
 
@@ -292,6 +312,27 @@ void resample_matrix(int nk, float R[8][kKnots])
 }  // namespace
 
 namespace mppi_host {
+mppi_status policy_infer(mppi_policy* p, const float* d_x, const float* d_cmd_origin, int nk, float sigma_max,
+                         float* d_center, float* d_sd, hipStream_t st)
+{
+    mppi_status s;
+    if ((s = need_bound(p))) return s;
+    float* feat = at<float>(p, p->o_feat);
+    float* out = at<float>(p, p->o_out1);
+    if ((s = phip(p, prop::launch_features(d_x, d_cmd_origin, feat, st), "features launch"))) return s;
+    if ((s = forward(p, feat, nullptr, 1, out, false, st))) return s;
+    HeadArgs h{};
+    h.out = out;
+    h.omean = at<float>(p, p->o_norm) + 80;
+    h.ostd = at<float>(p, p->o_norm) + 152;
+    h.nk = nk;
+    resample_matrix(nk, h.R);
+    h.log_lo = std::log(0.02f);
+    h.log_hi = std::log(sigma_max);
+    h.center = d_center;
+    h.sd = d_sd;
+    return phip(p, launch_head(h, st), "head launch");
+}
 const char* policy_error(const mppi_policy* p) { return p ? p->err.c_str() : g_perr.c_str(); }
 }  // namespace mppi_host
 
@@ -480,9 +521,12 @@ mppi_status mppi_policy_train_step(mppi_policy* p, const float* d_in, const floa
     if (!d_in || !d_target) return pfail(p, MPPI_EINVAL, "null input or target");
     if ((s = check_batch(p, B))) return s;
     if (!(lr >= 0.f) || !std::isfinite(lr)) return pfail(p, MPPI_EINVAL, "learning rate must be finite and >= 0");
-    float* G = at<float>(p, p->o_G);
-    if ((s = grad(p, d_in, d_target, d_index, B, G, d_loss, p->stream))) return s;
-    return adam(p, G, lr, p->stream);
+    ReduceArgs ra;
+    if ((s = backward(p, d_in, d_target, d_index, B, ra, p->stream))) return s;
+    ra.loss = d_loss;
+    if ((s = phip(p, launch_reduce_adam(ra, adam_args(p, nullptr, lr), p->stream), "reduce-adam launch"))) return s;
+    p->steps += 1;
+    return MPPI_OK;
 }
 
 int mppi_policy_steps(const mppi_policy* p) { return p ? p->steps : 0; }

@@ -7,6 +7,10 @@
 struct mppi_policy;
 
 namespace mppi_host {
+// features of state d_x (37) and d_cmd_origin (cmd[3], origin[2]) -> forward pass of one
+// row -> proposal centre and std for nk knots per joint, all on stream st
+mppi_status policy_infer(mppi_policy* p, const float* d_x, const float* d_cmd_origin, int nk, float sigma_max,
+                         float* d_center, float* d_sd, hipStream_t st);
 const char* policy_error(const mppi_policy* p);
 // value at t of the not-a-knot spline through nk knots on [0, T] with knot k = 1, others 0
 double spline_basis_at(int nk, double T, int k, double t);

@@ -1,6 +1,8 @@
 """GPU parity of the learned proposal against the oracle: the BF16 MFMA network (forward,
-gradient, Adam), the head and checkpoints.  The proposal control step's tests are
-skipped: the step is switched off (see the skip reason).
+gradient, Adam), the head, checkpoints, the proposal control step (built on the plain
+explicit-noise rollout and update kernels) and the learned step end to end.  The two
+tests of an earlier implementation of the step, which ran a modified rollout kernel
+that faulted the GPU, stay skipped with the reason.
 
 Tolerances (relative L2 over the compared array unless stated):
   forward vs the BF16-operand oracle       <= 1e-3  (same operand roundings; FP32 vs FP64
@@ -262,3 +264,63 @@ def test_training_pipeline_on_closed_loop_data(B):
     hist = PR.train(pol, data, tr, epochs=4, batch=1024, lr=1e-3, seed=0, held=ho, log=lambda *a: None)
     after = hist[-1][1]
     assert np.isfinite(after) and after < before - 0.5, (before, after)
+
+
+# ---------------------------------------------------------------------------- proposal step
+@pytest.mark.parametrize("accept", [True, False])
+def test_proposal_step_on_plain_kernels_matches_oracle(B, accept):
+    """The proposal step in both branches against the oracle's proposal step."""
+    md, p, orc, ctl = _ctl(B)
+    D = 12 * p["nk"]
+    rng = np.random.default_rng(2)
+    mu = f32(W.stance_knots(p["nk"]))
+    x0 = f32(W.initial_state(3))
+    if accept:   # nominal perturbed badly, proposal near the stance
+        nominal = f32(mu + 0.5)
+        center = f32(mu + 0.02 * rng.normal(size=D))
+    else:        # proposal far worse than the nominal
+        nominal = mu
+        center = f32(mu + 0.8)
+    sd = f32(rng.uniform(0.05, 0.2, D))
+    Kp = 16
+    ctl.set_nominal(_dev(nominal))
+    ctl.set_step(5)
+    u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), Kp).cpu().numpy()
+    nom = ctl.get_nominal().cpu().numpy()
+    acc, steps = ctl.proposal_stats()
+    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp)
+    assert oacc == accept and acc == int(accept) and steps == 1
+    assert ctl.sync_status() == 0 and ctl.step_counter == 6
+    assert np.abs(u0 - ou0).max() <= KNOT_TOL
+    assert np.abs(nom - onom).max() <= KNOT_TOL
+
+
+def test_learned_step_on_plain_kernels_matches_oracle_chain(B):
+    """mppi_step through the policy: features, BF16 forward, head and proposal step against
+    the oracle's features, BF16-operand forward, head and proposal step."""
+    md, p, orc, ctl = _ctl(B, K=64, H=10)
+    pol = B.Policy(max_batch=1, seed=5)
+    rng = np.random.default_rng(6)
+    im, isd = rng.normal(size=40) * 0.1, rng.uniform(0.5, 2.0, 40)
+    om = np.repeat(np.tile(W.STANCE_JOINTS, 4), 6)   # joint-major: 6 knots per joint
+    osd = np.full(72, 0.05)
+    pol.set_normalization(im, isd, om, osd)
+    cmd, origin = (0.5, 0.0, 0.0), (0.1, -0.2)
+    ctl.set_proposal(pol, k_prop=16, cmd=cmd, origin=origin)
+    x0 = f32(W.initial_state(2))
+    mu = f32(W.stance_knots(p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    ctl.set_step(0)
+    u0 = ctl.step(_dev(x0)).cpu().numpy()
+    nom = ctl.get_nominal().cpu().numpy()
+    acc, steps = ctl.proposal_stats()
+    feat = O.policy_features(x0, f32(cmd), f32(origin), f32(im), f32(isd))
+    out = O.mlp_forward(_params(pol), feat[None], bf16=True)[0]
+    c, sd = O.policy_head(out, f32(om), f32(osd), p["nk"], p["sigma"])
+    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 0, x0, mu, f32(c), f32(sd), 16)
+    assert steps == 1 and acc == int(oacc)
+    assert np.abs(u0 - ou0).max() <= KNOT_TOL
+    assert np.abs(nom - onom).max() <= KNOT_TOL
+    ctl.set_proposal(None)
+    ctl.step(_dev(x0))
+    assert ctl.proposal_stats()[1] == 1  # plain steps are not counted
