@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pairs", type=int, default=1_000_000, help="proposal_training: closed-loop pairs")
     ap.add_argument("--epochs", type=int, default=8, help="proposal_training: Adam epochs")
+    ap.add_argument("--eval-seeds", type=int, default=10, help="proposal_training: evaluation episodes")
+    ap.add_argument("--eval-steps", type=int, default=200, help="proposal_training: steps per evaluation episode")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -269,6 +271,7 @@ def bench_proposal(args):
     fl = mlp_train_flops_per_pair() * 4096
     achieved = fl / (step_ms * 1e-3) / 1e12
     pairs_s = 4096 / (step_ms * 1e-3)
+    ev = PR.evaluate(pol, seeds=range(100, 100 + args.eval_seeds), steps=args.eval_steps, arith=args.arith, log=log)
     train_s = sum(h[2] for h in hist)
     train_steps = sum(h[3] for h in hist)
     st = data["stats"]
@@ -285,6 +288,16 @@ def bench_proposal(args):
                      "scope": "whole train step (13 GEMMs, loss, reduction, Adam)"},
         "held_out_nll": {"untrained": nll0, "per_epoch": [h[1] for h in hist]},
         "train_nll_per_epoch": [h[0] for h in hist],
+        "equal_cost_evaluation": {
+            "task": "heightfield walk, v_ref 0.5, closed loop", "seeds": ev["seeds"], "steps": ev["steps"],
+            "plain_episode_cost": {str(k): v["mean"] for k, v in ev["plain"].items()},
+            "learned": {g: {"episode_cost": ev["learned_" + g]["mean"], "k_prop": ev["learned_" + g]["k_prop"],
+                            "fallback_K": ev["learned_" + g]["K_fallback"],
+                            "acceptance": ev["learned_" + g]["acceptance"],
+                            "samples_per_step": ev["learned_" + g]["samples_per_step"]}
+                        for g in ("cost", "none")},
+            "gates": "cost: proposal only when its centre costs no more than the nominal (plain K otherwise); "
+                     "none: always the K/4 proposal samples, nominal kept as sample 1"},
         "epoch_seconds": train_s / max(len(hist), 1), "train_steps": train_steps,
         "generation": {"seconds": gen_s, "batch_seconds": st["seconds"], "episodes": st["episodes"],
                        "falls": st["falls"], "control_steps": st["control_steps"],

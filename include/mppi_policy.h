@@ -109,16 +109,23 @@ const char *mppi_policy_last_error(const mppi_policy *pol);
  * If the rollout cost of the centre is finite and not above the nominal's, Eq. 1 and
  * Eq. 2 run over these k_prop samples; otherwise the step is a plain step with K
  * samples.  Then, as in mppi_step, the first control goes to d_u0_out, the nominal is
- * shifted and the step counter advances.  The two leading costs are read on the host to
- * choose the branch, so the call synchronises the bound stream.  2 <= k_prop <= K. */
+ * shifted and the step counter advances.  With MPPI_PROPOSAL_GATE_COST the two leading
+ * costs are read on the host to choose the branch, so the call synchronises the bound
+ * stream; MPPI_PROPOSAL_GATE_NONE always takes the proposal branch (the nominal still
+ * competes as sample 1).  2 <= k_prop <= K. */
+enum {
+    MPPI_PROPOSAL_GATE_COST = 0, /* proposal only if its centre's cost is finite and not above the nominal's */
+    MPPI_PROPOSAL_GATE_NONE = 1  /* always the proposal's k_prop samples */
+};
 mppi_status mppi_step_proposal(mppi_ctx *ctx, const float *d_x0, const float *d_center, const float *d_sd,
-                               int k_prop, float *d_u0_out);
+                               int k_prop, int gate, float *d_u0_out);
 /* Makes every later mppi_step of ctx use the policy: features of the current state and
  * command (host cmd[3]) relative to the host origin_xy[2], a forward pass, the head, and
- * mppi_step_proposal with k_prop samples.  The policy's kernels then run on ctx's
+ * mppi_step_proposal with k_prop samples and the given gate.  The policy's kernels then run on ctx's
  * stream; the policy must not be used on another stream meanwhile.  pol NULL switches
  * the proposal off.  Requires a 37-float state model. */
-mppi_status mppi_set_proposal(mppi_ctx *ctx, mppi_policy *pol, int k_prop, const float *cmd, const float *origin_xy);
+mppi_status mppi_set_proposal(mppi_ctx *ctx, mppi_policy *pol, int k_prop, int gate, const float *cmd,
+                              const float *origin_xy);
 /* How many proposal steps ran and how many were accepted (host counters). */
 mppi_status mppi_proposal_stats(mppi_ctx *ctx, int *accepted, int *steps);
 

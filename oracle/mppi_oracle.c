@@ -1196,12 +1196,12 @@ int orc_mppi_step(const orc_model *m, const orc_params *p, uint32_t step, const 
    network-given proposal is the reading of this library).  With Kp samples around the
    proposal: theta_0 = c (proposal mean), theta_1 = mu (shifted nominal), and
    theta_n = c + sd * eps_n for 2 <= n < Kp, eps from the same counters as a plain step.
-   When L(c) is finite and L(c) <= L(mu) the Eq. 1-2 update runs over these Kp samples;
-   otherwise the step falls back to a plain step with K samples around mu.
-   *accepted reports which branch ran; costs_p (Kp) and costs (K, fallback only) are
-   optional outputs. */
+   With gate 0, when L(c) is finite and L(c) <= L(mu) the Eq. 1-2 update runs over these
+   Kp samples, otherwise the step falls back to a plain step with K samples around mu;
+   gate 1 always takes the Kp samples.  *accepted reports which branch ran; costs_p (Kp)
+   and costs (K, fallback only) are optional outputs. */
 int orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t step, const double *x0, double *mu,
-                           const double *center, const double *sd, int Kp, double *u0, double *costs_p,
+                           const double *center, const double *sd, int Kp, int gate, double *u0, double *costs_p,
                            double *costs, int *accepted, int nthreads)
 {
     int D = 12 * p->nk, nx = orc_nx(m);
@@ -1224,7 +1224,7 @@ int orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t ste
     (void)nthreads;
     (void)nx;
     if (costs_p) memcpy(costs_p, L, sizeof(double) * Kp);
-    int acc = Kp >= 2 && isfinite(L[0]) && L[0] <= L[1];
+    int acc = gate == 1 || (Kp >= 2 && isfinite(L[0]) && L[0] <= L[1]);
     if (accepted) *accepted = acc;
     int rc;
     if (acc) {

@@ -96,7 +96,7 @@ void orc_shift(const orc_params *p, const double *mu_prime, double *mu_out, doub
 int  orc_mppi_step(const orc_model *m, const orc_params *p, uint32_t step, const double *x0, double *mu,
                    double *u0, double *costs, int nthreads);
 int  orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t step, const double *x0, double *mu,
-                            const double *center, const double *sd, int Kp, double *u0, double *costs_p,
+                            const double *center, const double *sd, int Kp, int gate, double *u0, double *costs_p,
                             double *costs, int *accepted, int nthreads);
 
 /* Learned proposal network (mlp_oracle.c). */

@@ -96,7 +96,7 @@ def lib():
             "orc_update": (C.c_int, [pp, dp, dp, dp, dp, dp]),
             "orc_shift": (None, [pp, dp, dp, dp]),
             "orc_mppi_step": (C.c_int, [mp, pp, C.c_uint32, dp, dp, dp, dp, C.c_int]),
-            "orc_mppi_step_proposal": (C.c_int, [mp, pp, C.c_uint32, dp, dp, dp, dp, C.c_int, dp, dp, dp,
+            "orc_mppi_step_proposal": (C.c_int, [mp, pp, C.c_uint32, dp, dp, dp, dp, C.c_int, C.c_int, dp, dp, dp,
                                                  C.POINTER(C.c_int), C.c_int]),
             "orc_policy_features": (None, [dp, dp, dp, dp, dp, dp]),
             "orc_policy_head": (None, [dp, dp, dp, C.c_int, C.c_double, dp, dp]),
@@ -268,7 +268,7 @@ class Oracle:
                                   _dp(costs), int(nthreads))
         return u0, mu, costs, rc
 
-    def mppi_step_proposal(self, p: dict, step: int, x0, mu, center, sd, Kp, nthreads=0):
+    def mppi_step_proposal(self, p: dict, step: int, x0, mu, center, sd, Kp, gate=0, nthreads=0):
         """Learned-proposal step; returns (u0, shifted nominal, proposal costs (Kp),
         fallback costs (K, zeros when accepted), accepted, status)."""
         ps = self.params(p)
@@ -277,7 +277,7 @@ class Oracle:
         u0, cp, cf = np.zeros(12), np.zeros(Kp), np.zeros(p["K"])
         acc = C.c_int(0)
         rc = self.L.orc_mppi_step_proposal(C.byref(self.m), C.byref(ps), int(step), _dp(_f64(x0, self.nx)), _dp(mu),
-                                           _dp(_f64(center, D)), _dp(_f64(sd, D)), int(Kp), _dp(u0), _dp(cp),
+                                           _dp(_f64(center, D)), _dp(_f64(sd, D)), int(Kp), int(gate), _dp(u0), _dp(cp),
                                            _dp(cf), C.byref(acc), int(nthreads))
         return u0, mu, cp, cf, bool(acc.value), rc
 

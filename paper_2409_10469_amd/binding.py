@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG, "libmppi.so")
 
 OK, WARN_ALL_NONFINITE, EINVAL, ENOMEM, EHIP, ESTATE = 0, 1, -1, -2, -3, -6
 ARITH = {"fp64": 0, "fp32": 1}
+GATE = {"cost": 0, "none": 1}
 
 
 class MppiError(RuntimeError):
@@ -85,8 +86,8 @@ def lib():
                                         vp]),
             "mppi_status_str": (C.c_char_p, [C.c_int]),
             "mppi_last_error": (C.c_char_p, [vp]),
-            "mppi_step_proposal": (C.c_int, [vp, fp, fp, fp, C.c_int, fp]),
-            "mppi_set_proposal": (C.c_int, [vp, vp, C.c_int, vp, vp]),
+            "mppi_step_proposal": (C.c_int, [vp, fp, fp, fp, C.c_int, C.c_int, fp]),
+            "mppi_set_proposal": (C.c_int, [vp, vp, C.c_int, C.c_int, vp, vp]),
             "mppi_proposal_stats": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
             "mppi_policy_n_params": (C.c_int, []),
             "mppi_policy_create": (C.c_int, [C.c_char_p, C.c_uint64, C.c_int, C.POINTER(C.c_void_p)]),
@@ -289,18 +290,19 @@ class Controller:
     def sync_status(self):
         return self._s(lib().mppi_sync_status(self.h))
 
-    def step_proposal(self, x0, center, sd, k_prop, u0=None):
+    def step_proposal(self, x0, center, sd, k_prop, u0=None, gate="cost"):
         """One control step sampling k_prop knots around an explicit proposal (mean, std)."""
         import torch
         u0 = u0 if u0 is not None else torch.empty(12, dtype=torch.float32, device="cuda")
-        self._s(lib().mppi_step_proposal(self.h, _ptr(x0), _ptr(center), _ptr(sd), int(k_prop), _ptr(u0)))
+        self._s(lib().mppi_step_proposal(self.h, _ptr(x0), _ptr(center), _ptr(sd), int(k_prop), GATE[gate],
+                                         _ptr(u0)))
         return u0
 
-    def set_proposal(self, policy, k_prop=0, cmd=(0.0, 0.0, 0.0), origin=(0.0, 0.0)):
+    def set_proposal(self, policy, k_prop=0, cmd=(0.0, 0.0, 0.0), origin=(0.0, 0.0), gate="cost"):
         """Route later step() calls through the learned proposal (policy None: plain MPPI)."""
         c = np.ascontiguousarray(cmd, dtype=np.float32)
         o = np.ascontiguousarray(origin, dtype=np.float32)
-        self._s(lib().mppi_set_proposal(self.h, policy.h if policy is not None else None, int(k_prop),
+        self._s(lib().mppi_set_proposal(self.h, policy.h if policy is not None else None, int(k_prop), GATE[gate],
                                         c.ctypes.data_as(C.c_void_p), o.ctypes.data_as(C.c_void_p)))
         self._policy = policy  # keep alive while in use
 

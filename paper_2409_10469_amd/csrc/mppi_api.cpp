@@ -39,7 +39,7 @@ struct mppi_ctx {
     size_t off_cmd, off_center, off_sd, off_costs_p, off_eps_p;
     uint32_t step = 0;
     mppi_policy* policy = nullptr;
-    int k_prop = 0;
+    int k_prop = 0, prop_gate = 0;
     float cmd_origin[8] = {};
     int prop_accepted = 0, prop_steps = 0;
     std::string err;
@@ -465,7 +465,7 @@ mppi_status mppi_update(mppi_ctx* c, const float* d_costs, const float* d_eps, f
 // gives mu' = c + sum w_n e_n / sum w_n, the weighted mean of theta.  Otherwise the plain
 // step runs.
 static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int kp,
-                                 float* d_u0_out)
+                                 int gate, float* d_u0_out)
 {
     mppi_status s;
     mppi::DevParams Pp = dev_params(c);
@@ -490,11 +490,15 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
     if ((s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, Pp, a, c->stream),
                        "proposal rollout launch")))
         return s;
-    float head[2];
-    if ((s = hip_check(c, hipMemcpyAsync(head, costs_p, sizeof(head), hipMemcpyDeviceToHost, c->stream), "gate read")) ||
-        (s = hip_check(c, hipStreamSynchronize(c->stream), "gate synchronise")))
-        return s;
-    const bool accepted = std::isfinite(head[0]) && head[0] <= head[1];
+    bool accepted = true;
+    if (gate == MPPI_PROPOSAL_GATE_COST) {
+        float head[2];
+        if ((s = hip_check(c, hipMemcpyAsync(head, costs_p, sizeof(head), hipMemcpyDeviceToHost, c->stream),
+                           "gate read")) ||
+            (s = hip_check(c, hipStreamSynchronize(c->stream), "gate synchronise")))
+            return s;
+        accepted = std::isfinite(head[0]) && head[0] <= head[1];
+    }
     c->prop_steps += 1;
     if (accepted) {
         c->prop_accepted += 1;
@@ -530,7 +534,7 @@ mppi_status mppi_step(mppi_ctx* c, const float* d_x0, float* d_u0_out)
         if ((s = mppi_host::policy_infer(c->policy, d_x0, wsf(c, c->off_cmd), c->p.n_knots, c->p.sigma, center, sd,
                                          c->stream)))
             return fail(c, s, std::string("proposal: ") + mppi_host::policy_error(c->policy));
-        return step_proposal(c, d_x0, center, sd, c->k_prop, d_u0_out);
+        return step_proposal(c, d_x0, center, sd, c->k_prop, c->prop_gate, d_u0_out);
     }
     float* costs = wsf(c, c->off_costs);
     if ((s = rollout(c, d_x0, nullptr, costs, nullptr))) return s;
@@ -562,16 +566,18 @@ mppi_status mppi_sync_status(mppi_ctx* c)
 }
 
 mppi_status mppi_step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int k_prop,
-                               float* d_u0_out)
+                               int gate, float* d_u0_out)
 {
     mppi_status s;
     if ((s = need_bound(c))) return s;
     if (!d_x0 || !d_center || !d_sd || !d_u0_out) return fail(c, MPPI_EINVAL, "null argument");
     if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
-    return step_proposal(c, d_x0, d_center, d_sd, k_prop, d_u0_out);
+    if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE) return fail(c, MPPI_EINVAL, "unknown gate");
+    return step_proposal(c, d_x0, d_center, d_sd, k_prop, gate, d_u0_out);
 }
 
-mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, const float* cmd, const float* origin_xy)
+mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, int gate, const float* cmd,
+                              const float* origin_xy)
 {
     mppi_status s;
     if ((s = need_bound(c))) return s;
@@ -582,6 +588,7 @@ mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, const f
     if (c->model.nx != 37) return fail(c, MPPI_EINVAL, "the proposal needs a 37-float state model");
     if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
     if (!cmd || !origin_xy) return fail(c, MPPI_EINVAL, "null command or origin");
+    if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE) return fail(c, MPPI_EINVAL, "unknown gate");
     if (!(c->p.sigma > 0.f)) return fail(c, MPPI_EINVAL, "the proposal needs sigma > 0 (upper std clamp)");
     for (int i = 0; i < 3; ++i) c->cmd_origin[i] = cmd[i];
     c->cmd_origin[3] = origin_xy[0];
@@ -592,6 +599,7 @@ mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, const f
         return s;
     c->policy = pol;
     c->k_prop = k_prop;
+    c->prop_gate = gate;
     return MPPI_OK;
 }
 

@@ -189,3 +189,66 @@ def train(policy, data, rows, epochs=10, batch=4096, lr=1e-3, seed=0, held=None,
         hist.append((tl, hl, dt, steps))
         log(f"  epoch {ep}: train NLL {tl:.4f}  held-out NLL {hl:.4f}  {dt:.2f} s ({steps} steps)")
     return hist
+
+
+def _stage_cost_torch(x, tau, p):
+    """Running cost of the walking task at state x after a plant step with torques tau."""
+    z, qx, qy, vx = x[2], x[4], x[5], x[19]
+    rzz = 1.0 - 2.0 * (qx * qx + qy * qy)
+    return (p["w_h"] * (z - p["h_ref"]) ** 2 + p["w_o"] * (1.0 - rzz * rzz) + p["w_v"] * (vx - p["v_ref"]) ** 2
+            + p["w_tau"] * (tau * tau).sum())
+
+
+def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="cost"):
+    """One closed-loop episode of the heightfield walk from the seeded stance; returns the
+    episode cost sum dt * l, the final state and the proposal counters."""
+    import torch
+    from . import binding as Bd
+    ctl = Bd.Controller(model, dict(p, seed=seed, arith=arith))
+    x0 = W.initial_state(seed, W.SCENE_HEIGHTFIELD)
+    x = torch.tensor(x0, dtype=torch.float32, device="cuda")
+    xn = torch.empty_like(x)
+    tau = torch.empty(12, dtype=torch.float32, device="cuda")
+    u0 = torch.empty(12, dtype=torch.float32, device="cuda")
+    ctl.set_nominal(torch.tensor(W.stance_knots(p["nk"]), dtype=torch.float32, device="cuda"))
+    if policy is not None:
+        ctl.set_proposal(policy, k_prop=k_prop, cmd=(p["v_ref"], 0.0, 0.0), origin=(float(x0[0]), float(x0[1])),
+                         gate=gate)
+    cost = torch.zeros((), dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        ctl.step(x, u0)
+        model.sim_step_into(x.view(1, -1), u0.view(1, -1), p["kp"], p["kd"], p["dt"], xn.view(1, -1),
+                            tau_out=tau.view(1, -1), arith=arith)
+        cost += p["dt"] * _stage_cost_torch(xn.double(), tau.double(), p)
+        x, xn = xn, x
+    acc, n = ctl.proposal_stats() if policy is not None else (0, 0)
+    return float(cost.item()), x.cpu().numpy(), acc, n
+
+
+def evaluate(policy, K_plain=(64, 128, 256, 512, 1024), K_learned=1024, ratio=4, seeds=range(100, 110), steps=200,
+             v_ref=0.5, arith="fp64", log=print):
+    """Plain MPPI at each K against the learned proposal with K_learned / ratio samples
+    (K_learned on fallback steps) over the same seeds; episode costs, fallback rate and the
+    average samples per step."""
+    from . import binding as Bd
+    wl = W.TERRAIN_WALK
+    model = Bd.Model(W.model_dict(wl, 0))
+    p = W.params_dict(wl, 0, v_ref=v_ref)
+    out = {"plain": {}, "seeds": list(seeds), "steps": steps, "v_ref": v_ref}
+    for K in K_plain:
+        costs = [episode(model, dict(p, K=K), s, steps, arith=arith)[0] for s in seeds]
+        out["plain"][K] = dict(mean=float(np.mean(costs)), costs=costs, samples_per_step=K)
+        log(f"  plain K={K}: episode cost {np.mean(costs):.3f}")
+    kp = K_learned // ratio
+    for gate in ("cost", "none"):
+        res = [episode(model, dict(p, K=K_learned), s, steps, policy=policy, k_prop=kp, arith=arith, gate=gate)
+               for s in seeds]
+        costs = [r[0] for r in res]
+        acc = sum(r[2] for r in res)
+        n = sum(r[3] for r in res)
+        samples = (n * kp + (n - acc) * K_learned) / max(n, 1)
+        out["learned_" + gate] = dict(mean=float(np.mean(costs)), costs=costs, k_prop=kp, K_fallback=K_learned,
+                                      accepted=acc, steps=n, acceptance=acc / max(n, 1), samples_per_step=samples)
+        log(f"  learned K/{ratio}={kp}, gate {gate}: episode cost {np.mean(costs):.3f}, "
+            f"acceptance {acc / max(n, 1):.2f}, {samples:.0f} samples/step")
+    return out

@@ -140,6 +140,6 @@ def test_batch_create_validation():
 
 def test_proposal_calls_reject_a_null_context():
     L = B.lib()
-    assert L.mppi_step_proposal(None, None, None, None, 16, None) == B.EINVAL
-    assert L.mppi_set_proposal(None, None, 16, None, None) == B.EINVAL
+    assert L.mppi_step_proposal(None, None, None, None, 16, 0, None) == B.EINVAL
+    assert L.mppi_set_proposal(None, None, 16, 0, None, None) == B.EINVAL
     assert L.mppi_proposal_stats(None, None, None) == B.EINVAL

@@ -202,11 +202,13 @@ def test_step_proposal_matches_oracle(B, accept):
     Kp = 16
     ctl.set_nominal(_dev(nominal))
     ctl.set_step(5)
-    u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), Kp).cpu().numpy()
+    u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), Kp, gate=gate).cpu().numpy()
     nom = ctl.get_nominal().cpu().numpy()
     acc, steps = ctl.proposal_stats()
-    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp)
-    assert oacc == accept and acc == int(accept) and steps == 1
+    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp,
+                                                         gate=0 if gate == "cost" else 1)
+    taken = accept or gate == "none"
+    assert oacc == taken and acc == int(taken) and steps == 1
     assert ctl.sync_status() == 0 and ctl.step_counter == 6
     assert np.abs(u0 - ou0).max() <= KNOT_TOL
     assert np.abs(nom - onom).max() <= KNOT_TOL
@@ -267,9 +269,9 @@ def test_training_pipeline_on_closed_loop_data(B):
 
 
 # ---------------------------------------------------------------------------- proposal step
-@pytest.mark.parametrize("accept", [True, False])
-def test_proposal_step_on_plain_kernels_matches_oracle(B, accept):
-    """The proposal step in both branches against the oracle's proposal step."""
+@pytest.mark.parametrize("accept,gate", [(True, "cost"), (False, "cost"), (False, "none")])
+def test_proposal_step_on_plain_kernels_matches_oracle(B, accept, gate):
+    """The proposal step in both branches, and ungated, against the oracle's proposal step."""
     md, p, orc, ctl = _ctl(B)
     D = 12 * p["nk"]
     rng = np.random.default_rng(2)
@@ -285,11 +287,13 @@ def test_proposal_step_on_plain_kernels_matches_oracle(B, accept):
     Kp = 16
     ctl.set_nominal(_dev(nominal))
     ctl.set_step(5)
-    u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), Kp).cpu().numpy()
+    u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), Kp, gate=gate).cpu().numpy()
     nom = ctl.get_nominal().cpu().numpy()
     acc, steps = ctl.proposal_stats()
-    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp)
-    assert oacc == accept and acc == int(accept) and steps == 1
+    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp,
+                                                         gate=0 if gate == "cost" else 1)
+    taken = accept or gate == "none"
+    assert oacc == taken and acc == int(taken) and steps == 1
     assert ctl.sync_status() == 0 and ctl.step_counter == 6
     assert np.abs(u0 - ou0).max() <= KNOT_TOL
     assert np.abs(nom - onom).max() <= KNOT_TOL
@@ -324,3 +328,30 @@ def test_learned_step_on_plain_kernels_matches_oracle_chain(B):
     ctl.set_proposal(None)
     ctl.step(_dev(x0))
     assert ctl.proposal_stats()[1] == 1  # plain steps are not counted
+
+
+def test_trained_proposal_gains_over_plain_and_untrained_at_equal_samples(B):
+    """What the trained network gains: closed-loop heightfield walks (3 seeds x 100 steps,
+    v_ref 0.5) with the K/4 = 256-sample proposal (ungated, nominal kept as sample 1)
+    against plain MPPI with the same 256 samples and against the untrained network."""
+    from paper_2409_10469_amd import proposal as PR
+    data = PR.generate(n_pairs=200000, episode_steps=100, instances=256, seed=11, log=lambda *a: None)
+    tr, ho = PR.split(data, holdout=0.05, seed=0)
+    norm = PR.normalization(data, tr)
+    trained = B.Policy(max_batch=4096, seed=1)
+    trained.set_normalization(*norm)
+    PR.train(trained, data, tr, epochs=4, batch=4096, lr=1e-3, seed=0, held=None, log=lambda *a: None)
+    untrained = B.Policy(max_batch=1, seed=1)
+    untrained.set_normalization(*norm)
+    wl = W.TERRAIN_WALK
+    model = B.Model(W.model_dict(wl, 0))
+    p = W.params_dict(wl, 0, v_ref=0.5)
+    seeds, steps = (100, 101, 102), 100
+    plain = np.mean([PR.episode(model, dict(p, K=256), s, steps)[0] for s in seeds])
+    learned = np.mean([PR.episode(model, dict(p, K=1024), s, steps, policy=trained, k_prop=256, gate="none")[0]
+                       for s in seeds])
+    naive = np.mean([PR.episode(model, dict(p, K=1024), s, steps, policy=untrained, k_prop=256, gate="none")[0]
+                     for s in seeds])
+    assert np.isfinite([plain, learned, naive]).all()
+    assert learned < 0.8 * plain, (learned, plain)
+    assert learned < naive, (learned, naive)

@@ -99,3 +99,22 @@ def test_proposal_nonfinite_mean_falls_back():
     assert not acc and math.isinf(cp[0])
     u0p, nomp, _, _ = o.mppi_step(p, 0, x0, mu)
     np.testing.assert_array_equal(nom, nomp)
+
+
+def test_ungated_proposal_takes_the_proposal_samples():
+    """gate 1: the weighted mean of the proposal samples even when the centre is worse."""
+    o, p, x0, mu = _setup()
+    D = 12 * p["nk"]
+    center = mu + 0.8
+    sd = np.full(D, 0.1)
+    Kp = 6
+    u0, nom, cp, cf, acc, rc = o.mppi_step_proposal(p, 1, x0, mu, center, sd, Kp, gate=1)
+    assert acc and cp[0] > cp[1] and not cf.any()
+    eps = O.sample_eps(dict(p, K=Kp), 1)
+    thetas = [center, mu] + [center + sd * eps[n] for n in range(2, Kp)]
+    L = np.array([o.rollout(p, x0, th) for th in thetas])
+    w = np.exp(-(L - L.min()) / p["lam"])
+    w /= w.sum()
+    want_nom, want_u0 = O.shift(p, sum(wi * th for wi, th in zip(w, thetas)))
+    np.testing.assert_allclose(nom, want_nom, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(u0, want_u0, rtol=1e-12, atol=1e-14)
