@@ -291,10 +291,12 @@ def bench_proposal(args):
         "equal_cost_evaluation": {
             "task": "heightfield walk, v_ref 0.5, closed loop", "seeds": ev["seeds"], "steps": ev["steps"],
             "plain_episode_cost": {str(k): v["mean"] for k, v in ev["plain"].items()},
+            "plain_step_latency_ms": {str(k): v["latency_ms"] for k, v in ev["plain"].items()},
             "learned": {g: {"episode_cost": ev["learned_" + g]["mean"], "k_prop": ev["learned_" + g]["k_prop"],
                             "fallback_K": ev["learned_" + g]["K_fallback"],
                             "acceptance": ev["learned_" + g]["acceptance"],
-                            "samples_per_step": ev["learned_" + g]["samples_per_step"]}
+                            "samples_per_step": ev["learned_" + g]["samples_per_step"],
+                            "step_latency_ms": ev["learned_" + g]["latency_ms"]}
                         for g in ("cost", "none")},
             "gates": "cost: proposal only when its centre costs no more than the nominal (plain K otherwise); "
                      "none: always the K/4 proposal samples, nominal kept as sample 1"},

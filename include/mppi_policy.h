@@ -129,6 +129,22 @@ mppi_status mppi_set_proposal(mppi_ctx *ctx, mppi_policy *pol, int k_prop, int g
 /* How many proposal steps ran and how many were accepted (host counters). */
 mppi_status mppi_proposal_stats(mppi_ctx *ctx, int *accepted, int *steps);
 
+/* ---- batched serving side ---------------------------------------------------------
+ * Makes instance id of a batch (mppi.h) take its samples from the policy, ungated: each
+ * mppi_batch_step then runs, for all such instances together and before the batch's
+ * graph, the features of each one's current state, one forward pass over them as a
+ * batch, and the head; the instance's K admitted samples are then theta_0 = centre,
+ * theta_1 = its shifted nominal, theta_n = centre + sd * eps_n (its own Philox counters,
+ * as mppi_step_proposal draws them), and Eq. 1 / Eq. 2 over them give the new nominal,
+ * as mppi_step_proposal does with MPPI_PROPOSAL_GATE_NONE.  The admitted sigma is the
+ * upper clamp of the proposal's std.  cmd[3] and origin_xy[2] are host arrays copied
+ * here.  Every proposal instance of a batch shares one policy, whose max_batch must
+ * cover their number; its kernels run on the batch's stream, and it must not be used on
+ * another stream while steps are queued.  pol NULL returns the instance to plain
+ * sampling.  Requires a 37-float state model and K >= 2.  Does not launch work. */
+mppi_status mppi_batch_set_proposal(mppi_batch *b, int id, mppi_policy *pol, const float *cmd,
+                                    const float *origin_xy);
+
 #ifdef __cplusplus
 }
 #endif

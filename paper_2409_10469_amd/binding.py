@@ -437,6 +437,7 @@ class Batch:
                 "mppi_batch_stats": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_size_t),
                                                C.POINTER(C.c_size_t)]),
                 "mppi_batch_last_error": (C.c_char_p, [vp]),
+                "mppi_batch_set_proposal": (C.c_int, [vp, C.c_int, vp, vp, vp]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -497,6 +498,20 @@ class Batch:
             self._records.pop(i, None)
         else:
             self._records[i] = rec
+
+    def set_proposal(self, i, policy=None, cmd=(0.0, 0.0, 0.0), origin=(0.0, 0.0)):
+        """Instance i takes its K samples from the policy (ungated), or plain samples again
+        with policy None.  Every proposal instance shares one policy; it is kept alive here."""
+        c = np.ascontiguousarray(cmd, dtype=np.float32)
+        o = np.ascontiguousarray(origin, dtype=np.float32)
+        assert c.shape == (3,) and o.shape == (2,)
+        self._chk(self.L.mppi_batch_set_proposal(self.h, int(i), policy.h if policy is not None else None,
+                                                 c.ctypes.data_as(C.c_void_p), o.ctypes.data_as(C.c_void_p)))
+        self._policies = getattr(self, "_policies", {})
+        if policy is None:
+            self._policies.pop(i, None)
+        else:
+            self._policies[i] = policy
 
     def set_tuning(self, blocks_per_cu, order):
         self._chk(self.L.mppi_batch_set_tuning(self.h, blocks_per_cu, order))

@@ -7,6 +7,12 @@
 // The device instance table, tile map and tile count live at the front of the
 // workspace and are re-uploaded (stream-ordered) when the set of instances changes, so
 // the captured graph stays valid: the persistent kernel reads everything from the table.
+//
+// Instances may take their samples from the learned proposal (ungated: every step uses
+// the proposal's K samples, the shifted nominal kept as sample 1).  Before the graph, one
+// features launch, one network forward over all such instances as a batch, and one
+// head-and-noise launch write each one's centre into its nominal slot and its rollout
+// noise; the persistent kernel then reads that noise instead of drawing Philox noise.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +28,9 @@
 #include "mppi.h"
 #include "mppi_device.h"
 #include "mppi_launch.h"
+#include "mppi_policy.h"
+#include "policy_internal.h"
+#include "proposal_launch.h"
 
 // defined in mppi_api.cpp
 extern "C++" {
@@ -94,6 +103,8 @@ struct Instance {
     size_t off = 0, bytes = 0;
     float* rec = nullptr;  // caller's record buffer
     int rec_cap = 0;
+    bool prop = false;     // samples from the batch's proposal network
+    float cmd_origin[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     // offsets inside the allocation
     size_t o_B, o_S, o_x, o_mu, o_eps, o_costs, o_w, o_u0, o_acc, o_done, o_step;
 };
@@ -107,6 +118,7 @@ struct mppi_batch {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // used only to capture the graph
     size_t o_table, o_models, o_pool;
+    size_t o_prows, o_feat, o_pout, o_rtab;  // proposal rows, features, network outputs, resampling
     size_t o_tiles[4], o_total[4], o_head[4], o_exited[4];  // one work queue per scene
     int scene_tiles[4] = {0, 0, 0, 0};
     bool scene_used[4] = {false, false, false, false};
@@ -120,6 +132,10 @@ struct mppi_batch {
     bool dirty = true, upload_pending = false;
     int total_tiles = 0, n_live = 0;
     int grid = 0, blocks_per_cu = 4, order = 1;
+    mppi_policy* policy = nullptr;  // shared by every proposal instance
+    prop::BatchPropRow* h_prows = nullptr;
+    int n_prop = 0;
+    bool rtab_ready = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string err;
@@ -142,6 +158,12 @@ mppi_status bhip(mppi_batch* b, hipError_t e, const char* what)
 }
 char* wsp(mppi_batch* b, size_t off) { return (char*)b->ws + off; }
 size_t model_size(int arith) { return arith == 1 ? sizeof(mppi::ModelT<float>) : sizeof(mppi::ModelT<double>); }
+// proposal rows, feature rows (40 floats), network output rows (144 floats), resampling table
+size_t prop_bytes(int max_inst)
+{
+    return align_up(sizeof(prop::BatchPropRow) * max_inst) + align_up(sizeof(float) * 40 * max_inst) +
+           align_up(sizeof(float) * 144 * max_inst) + align_up(sizeof(float) * 9 * 8 * 6);
+}
 
 void drop_graph(mppi_batch* b)
 {
@@ -165,7 +187,7 @@ mppi_status upload_table(mppi_batch* b)
     mppi_status s;
     if (b->upload_pending && (s = bhip(b, hipEventSynchronize(b->upload_done), "wait upload"))) return s;
     const int tiles_per_scene = b->max_inst * (4096 / mppi::kTileSamples);
-    int row = 0, all_tiles = 0;
+    int row = 0, all_tiles = 0, np = 0;
     for (int sc = 0; sc < 4; ++sc) {
         std::vector<int> ids;
         for (int i = 0; i < b->max_inst; ++i)
@@ -206,6 +228,15 @@ mppi_status upload_table(mppi_batch* b)
             d.step = (uint32_t*)(base + in.o_step);
             d.rec = in.rec;
             d.rec_cap = in.rec_cap;
+            if (in.prop) {  // unit scale around the centre; the admitted sigma is the std clamp
+                d.explicit_eps = 1;
+                d.P.sigma = 1.f;
+                prop::BatchPropRow& pr = b->h_prows[np++];
+                pr.row = row;
+                pr.nk = p.n_knots;
+                pr.log_hi = std::log(p.sigma);
+                for (int q = 0; q < 5; ++q) pr.cmd_origin[q] = in.cmd_origin[q];
+            }
             for (int k = 0; k < d.ntiles; ++k) map[tile + k] = row;
             tile += d.ntiles;
             ++row;
@@ -216,6 +247,7 @@ mppi_status upload_table(mppi_batch* b)
     }
     b->total_tiles = all_tiles;
     b->n_live = row;
+    b->n_prop = np;
     hipStream_t st = b->stream;
     if ((s = bhip(b, hipMemcpyAsync(wsp(b, b->o_table), b->h_table, sizeof(mppi::InstDesc) * std::max(row, 1),
                                     hipMemcpyHostToDevice, st), "upload table")))
@@ -230,6 +262,9 @@ mppi_status upload_table(mppi_batch* b)
                                         hipMemcpyHostToDevice, st), "upload tile count")))
             return s;
     }
+    if (np && (s = bhip(b, hipMemcpyAsync(wsp(b, b->o_prows), b->h_prows, sizeof(prop::BatchPropRow) * np,
+                                          hipMemcpyHostToDevice, st), "upload proposal rows")))
+        return s;
     if ((s = bhip(b, hipEventRecord(b->upload_done, st), "record upload"))) return s;
     b->upload_pending = true;
     b->dirty = false;
@@ -279,6 +314,27 @@ mppi_status capture(mppi_batch* b)
     return bhip(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "instantiate graph");
 }
 
+// learned-proposal instances: features, one forward over all of them, head and noise
+mppi_status proposal_prestep(mppi_batch* b)
+{
+    mppi_status s;
+    hipStream_t st = b->stream;
+    const auto* table = (const mppi::InstDesc*)wsp(b, b->o_table);
+    const auto* rows = (const prop::BatchPropRow*)wsp(b, b->o_prows);
+    float* feat = (float*)wsp(b, b->o_feat);
+    float* out = (float*)wsp(b, b->o_pout);
+    if ((s = bhip(b, prop::launch_batch_features(b->n_prop, table, rows, feat, st), "proposal features launch")))
+        return s;
+    if (mppi_host::policy_forward_rows(b->policy, feat, b->n_prop, out, st) != MPPI_OK)
+        return bfail(b, MPPI_EINVAL, std::string("proposal forward: ") + mppi_host::policy_error(b->policy));
+    const float *omean, *ostd;
+    if (mppi_host::policy_out_norm(b->policy, &omean, &ostd) != MPPI_OK)
+        return bfail(b, MPPI_ESTATE, std::string("proposal: ") + mppi_host::policy_error(b->policy));
+    return bhip(b, prop::launch_batch_head_noise(b->n_prop, table, rows, out, omean, ostd,
+                                                 (const float*)wsp(b, b->o_rtab), std::log(0.02f), st),
+                "proposal head launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -306,6 +362,8 @@ mppi_status mppi_batch_create(int max_instances, int max_horizon, int max_hf_cel
     if (hipHostMalloc((void**)&b->h_table, sizeof(mppi::InstDesc) * max_instances, hipHostMallocDefault) !=
             hipSuccess ||
         hipHostMalloc((void**)&b->h_tiles, sizeof(int) * 4 * (max_tiles + 1), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_prows, sizeof(prop::BatchPropRow) * max_instances, hipHostMallocDefault) !=
+            hipSuccess ||
         hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming) != hipSuccess) {
         mppi_batch_destroy(b);
         return bfail(nullptr, MPPI_EHIP, "pinned host allocation failed");
@@ -323,6 +381,7 @@ void mppi_batch_destroy(mppi_batch* b)
     if (b->cap_stream) hipStreamDestroy(b->cap_stream);
     if (b->h_table) hipHostFree(b->h_table);
     if (b->h_tiles) hipHostFree(b->h_tiles);
+    if (b->h_prows) hipHostFree(b->h_prows);
     delete b;
 }
 
@@ -330,7 +389,7 @@ size_t mppi_batch_control_bytes(int max_instances, int arith)
 {
     const int max_tiles = max_instances * (4096 / mppi::kTileSamples);
     return align_up(sizeof(mppi::InstDesc) * max_instances) + 4 * (align_up(sizeof(int) * max_tiles) + 3 * kAlign) +
-           align_up(model_size(arith) * MPPI_BATCH_MAX_MODELS);
+           align_up(model_size(arith) * MPPI_BATCH_MAX_MODELS) + prop_bytes(max_instances);
 }
 
 mppi_status mppi_batch_bind(mppi_batch* b, void* ws, size_t bytes, void* stream)
@@ -356,12 +415,19 @@ mppi_status mppi_batch_bind(mppi_batch* b, void* ws, size_t bytes, void* stream)
         o += align_up(sizeof(int) * b->max_inst * (4096 / mppi::kTileSamples));
     }
     b->o_models = o; o += align_up(model_size(b->arith) * MPPI_BATCH_MAX_MODELS);
+    b->o_prows = o; o += align_up(sizeof(prop::BatchPropRow) * b->max_inst);
+    b->o_feat = o; o += align_up(sizeof(float) * 40 * b->max_inst);
+    b->o_pout = o; o += align_up(sizeof(float) * 144 * b->max_inst);
+    b->o_rtab = o; o += align_up(sizeof(float) * 9 * 8 * 6);
     b->o_pool = o;
     b->arena.reset(o, bytes - o);
     b->models.clear();
     b->model_blob.assign(model_size(b->arith) * MPPI_BATCH_MAX_MODELS, 0);
     for (auto& in : b->inst) in = Instance{};
     for (int sc = 0; sc < 4; ++sc) b->scene_used[sc] = false;
+    b->policy = nullptr;
+    b->n_prop = 0;
+    b->rtab_ready = false;
     b->dirty = true;
     hipStream_t st = b->stream;
     mppi_status s;
@@ -483,6 +549,45 @@ mppi_status mppi_batch_record(mppi_batch* b, int id, float* d_rec, int cap)
     return MPPI_OK;
 }
 
+mppi_status mppi_batch_set_proposal(mppi_batch* b, int id, mppi_policy* pol, const float* cmd, const float* origin_xy)
+{
+    if (!b || id < 0 || id >= b->max_inst || !b->inst[id].live) return bfail(b, MPPI_EINVAL, "unknown instance");
+    Instance& in = b->inst[id];
+    if (!pol) {
+        if (in.prop) b->dirty = true;
+        in.prop = false;
+        return MPPI_OK;
+    }
+    if (b->models[in.model].nx != 37) return bfail(b, MPPI_EINVAL, "the proposal needs a 37-float state model");
+    if (!cmd || !origin_xy) return bfail(b, MPPI_EINVAL, "null command or origin");
+    if (in.p.K < 2) return bfail(b, MPPI_EINVAL, "the proposal needs K >= 2 samples");
+    if (!(in.p.sigma > 0.f)) return bfail(b, MPPI_EINVAL, "the proposal needs sigma > 0 (upper std clamp)");
+    if (b->policy && b->policy != pol)
+        for (const auto& o : b->inst)
+            if (o.live && o.prop && &o != &in)
+                return bfail(b, MPPI_EINVAL, "every proposal instance of a batch uses the same policy");
+    const float *om, *os;
+    if (mppi_host::policy_out_norm(pol, &om, &os) != MPPI_OK)
+        return bfail(b, MPPI_ESTATE, std::string("proposal: ") + mppi_host::policy_error(pol));
+    mppi_status s;
+    if (!b->rtab_ready) {
+        float rtab[9 * 8 * 6];
+        mppi_host::policy_resample_table(rtab);
+        if ((s = bhip(b, hipMemcpyAsync(wsp(b, b->o_rtab), rtab, sizeof(rtab), hipMemcpyHostToDevice, b->stream),
+                      "upload resampling table")) ||
+            (s = bhip(b, hipStreamSynchronize(b->stream), "synchronise")))
+            return s;
+        b->rtab_ready = true;
+    }
+    b->policy = pol;
+    for (int q = 0; q < 3; ++q) in.cmd_origin[q] = cmd[q];
+    in.cmd_origin[3] = origin_xy[0];
+    in.cmd_origin[4] = origin_xy[1];
+    in.prop = true;
+    b->dirty = true;
+    return MPPI_OK;
+}
+
 mppi_status mppi_batch_step(mppi_batch* b)
 {
     if (!b) return bfail(nullptr, MPPI_EINVAL, "null batch");
@@ -491,6 +596,7 @@ mppi_status mppi_batch_step(mppi_batch* b)
     if (b->dirty && (s = upload_table(b))) return s;
     if (b->total_tiles == 0) return MPPI_OK;
     if (!b->exec && (s = capture(b))) return s;
+    if (b->n_prop && (s = proposal_prestep(b))) return s;
     return bhip(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
 }
 

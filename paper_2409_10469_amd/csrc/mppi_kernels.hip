@@ -393,7 +393,10 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchArgs<R> a)
         stage_lds(P, SCENE, I.hf_cells, I.B, I.hf, sB, sHF);
         __syncthreads();
         const int n_base = (t - I.tile0) * kTileSamples;
-        rollout_samples<SCENE, R>(M, P, sB, sHF, sTh, I.mu, I.x, nullptr, 0, 0, I.eps, I.costs, nullptr, n_base);
+        // Philox noise drawn here and stored for the tail, or the given dimension-major noise
+        const float* ein = I.explicit_eps ? I.eps : nullptr;
+        rollout_samples<SCENE, R>(M, P, sB, sHF, sTh, I.mu, I.x, ein, 1, P.K, ein ? nullptr : I.eps, I.costs, nullptr,
+                                  n_base);
         __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) s_last = (atomicAdd(I.done, 1) == I.ntiles - 1);

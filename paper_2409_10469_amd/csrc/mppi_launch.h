@@ -65,13 +65,14 @@ constexpr int kTileSamples = 16;  // samples per 64-lane tile (one sample per qu
 struct InstDesc {
     DevParams P;                // K, H, nk, nx, dt, sigma, 1/lambda, gains, cost weights, seed, instance
     int scene, model, ntiles, tile0;
-    int hf_cells, pad0;
+    int hf_cells;
+    int explicit_eps;           // 1: eps holds the rollout noise (written before the step), 0: Philox
     const double* B;            // spline basis H x nk
     const float* S;             // shift matrix nk x nk
     const float* hf;            // heightfield of the model (scene 1)
     float* x;                   // current state (nx)
     float* mu;                  // nominal knots (12 nk)
-    float* eps;                 // noise, D x K
+    float* eps;                 // noise, D x K (dimension-major)
     float* costs;               // K
     float* w;                   // K unnormalised weights
     float* u0;                  // last first control (12)

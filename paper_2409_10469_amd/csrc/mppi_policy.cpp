@@ -334,6 +334,32 @@ mppi_status policy_infer(mppi_policy* p, const float* d_x, const float* d_cmd_or
     return phip(p, launch_head(h, st), "head launch");
 }
 const char* policy_error(const mppi_policy* p) { return p ? p->err.c_str() : g_perr.c_str(); }
+
+// network output rows (B x 144) of raw feature rows (B x 40) on stream st
+mppi_status policy_forward_rows(mppi_policy* p, const float* d_in, int B, float* d_out, hipStream_t st)
+{
+    mppi_status s;
+    if ((s = need_bound(p))) return s;
+    if ((s = check_batch(p, B))) return s;
+    return forward(p, d_in, nullptr, B, d_out, false, st);
+}
+
+// device pointers of the output standardisation (mean and std of the 72 means)
+mppi_status policy_out_norm(mppi_policy* p, const float** omean, const float** ostd)
+{
+    mppi_status s;
+    if ((s = need_bound(p))) return s;
+    *omean = at<float>(p, p->o_norm) + 80;
+    *ostd = at<float>(p, p->o_norm) + 152;
+    return MPPI_OK;
+}
+
+// the head's resampling matrices for every knot count: rtab[nk][i][k], 9 x 8 x 6 floats
+void policy_resample_table(float* rtab)
+{
+    std::memset(rtab, 0, sizeof(float) * 9 * 8 * kKnots);
+    for (int nk = 2; nk <= 8; ++nk) resample_matrix(nk, reinterpret_cast<float(*)[kKnots]>(rtab + nk * 8 * kKnots));
+}
 }  // namespace mppi_host
 
 extern "C" {

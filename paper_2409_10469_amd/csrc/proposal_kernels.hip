@@ -4,8 +4,11 @@
 //                           (the shifted nominal), e_n = sd * eps_n for n >= 2
 //   features_kernel       - network input of one state: base xy relative to the origin,
 //                           then the command
+//   batch_features_kernel, batch_head_noise_kernel - the same for the learned-proposal
+//                           instances of a batch, one row per instance
 #include <hip/hip_runtime.h>
 
+#include "mppi_device.h"
 #include "proposal_launch.h"
 
 namespace prop {
@@ -42,6 +45,90 @@ __global__ void features_kernel(const float* __restrict__ x, const float* __rest
 hipError_t launch_features(const float* x, const float* cmd_origin, float* feat, hipStream_t st)
 {
     hipLaunchKernelGGL(features_kernel, dim3(1), dim3(64), 0, st, x, cmd_origin, feat);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void batch_features_kernel(int np, const mppi::InstDesc* __restrict__ table,
+                                                             const BatchPropRow* __restrict__ rows,
+                                                             float* __restrict__ feat)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= np * 40) return;
+    const int r = i / 40, t = i - r * 40;
+    const BatchPropRow& pr = rows[r];
+    const float* x = table[pr.row].x;
+    feat[i] = t < 37 ? x[t] - (t == 0 ? pr.cmd_origin[3] : t == 1 ? pr.cmd_origin[4] : 0.f) : pr.cmd_origin[t - 37];
+}
+
+hipError_t launch_batch_features(int np, const mppi::InstDesc* table, const BatchPropRow* rows, float* feat,
+                                 hipStream_t st)
+{
+    hipLaunchKernelGGL(batch_features_kernel, dim3((unsigned)((np * 40 + 255) / 256)), dim3(256), 0, st, np, table,
+                       rows, feat);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void batch_head_noise_kernel(const mppi::InstDesc* __restrict__ table,
+                                                               const BatchPropRow* __restrict__ rows,
+                                                               const float* __restrict__ out,
+                                                               const float* __restrict__ omean,
+                                                               const float* __restrict__ ostd,
+                                                               const float* __restrict__ rtab, float log_lo)
+{
+    __shared__ float sC[12 * 8], sSD[12 * 8];
+    const BatchPropRow pr = rows[blockIdx.x];
+    const mppi::InstDesc& I = table[pr.row];
+    const int nk = pr.nk, D = 12 * nk, K = I.P.K, t = threadIdx.x;
+    const float* o = out + (size_t)blockIdx.x * 144;
+    if (t < D) {  // head: de-standardised mean and log-std of joint j, resampled to knot i
+        const int j = t / nk, i = t - j * nk;
+        const float* R = rtab + (size_t)(nk * 8 + i) * 6;
+        float m = 0.f, s = 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int d = j * 6 + k;
+            const float sd = ostd[d];
+            m += R[k] * (o[d] * sd + omean[d]);
+            s += R[k] * (o[72 + d] + logf(sd));
+        }
+        s = fminf(fmaxf(s, log_lo), pr.log_hi);
+        sC[t] = m;
+        sSD[t] = expf(s);
+    }
+    __syncthreads();
+    // noise: counter (d / 4, n, step, instance), Box-Muller on word pairs, as the sampler
+    const uint32_t step = I.step[0];
+    const int nb = (D + 3) >> 2;
+    for (int idx = t; idx < K * nb; idx += 256) {
+        const int cb = idx / K, n = idx - cb * K;
+        uint32_t w[4] = {(uint32_t)cb, (uint32_t)n, step, I.P.instance};
+        mppi::philox4x32_10(w, I.P.seed_lo, I.P.seed_hi);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float r = sqrtf(-2.0f * logf(mppi::u24<float>(w[2 * h])));
+            float sn, co;
+            sincospif(2.0f * mppi::u24<float>(w[2 * h + 1]), &sn, &co);
+            const float g[2] = {r * co, r * sn};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int d = 4 * cb + 2 * h + q;
+                if (d < D) {
+                    const float e = n == 0 ? 0.f : n == 1 ? I.mu[d] - sC[d] : sSD[d] * g[q];
+                    I.eps[(size_t)d * K + n] = e;
+                }
+            }
+        }
+    }
+    __syncthreads();  // the nominal has been read (n = 1) before the centre takes its place
+    if (t < D) I.mu[t] = sC[t];
+}
+
+hipError_t launch_batch_head_noise(int np, const mppi::InstDesc* table, const BatchPropRow* rows, const float* out,
+                                   const float* omean, const float* ostd, const float* rtab, float log_lo,
+                                   hipStream_t st)
+{
+    hipLaunchKernelGGL(batch_head_noise_kernel, dim3((unsigned)np), dim3(256), 0, st, table, rows, out, omean, ostd,
+                       rtab, log_lo);
     return hipGetLastError();
 }
 

@@ -199,9 +199,12 @@ def _stage_cost_torch(x, tau, p):
             + p["w_tau"] * (tau * tau).sum())
 
 
-def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="cost"):
+def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="cost", lat=None):
     """One closed-loop episode of the heightfield walk from the seeded stance; returns the
-    episode cost sum dt * l, the final state and the proposal counters."""
+    episode cost sum dt * l, the final state and the proposal counters.  With a list
+    `lat`, appends each control step's latency in ms: stream events around the step, so
+    the time runs from the moment the plant state is on the device to the first control,
+    including any host round trip of the cost gate."""
     import torch
     from . import binding as Bd
     ctl = Bd.Controller(model, dict(p, seed=seed, arith=arith))
@@ -215,13 +218,23 @@ def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="co
         ctl.set_proposal(policy, k_prop=k_prop, cmd=(p["v_ref"], 0.0, 0.0), origin=(float(x0[0]), float(x0[1])),
                          gate=gate)
     cost = torch.zeros((), dtype=torch.float64, device="cuda")
+    ev = []
     for _ in range(steps):
+        if lat is not None:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
         ctl.step(x, u0)
+        if lat is not None:
+            e1.record()
+            ev.append((e0, e1))
         model.sim_step_into(x.view(1, -1), u0.view(1, -1), p["kp"], p["kd"], p["dt"], xn.view(1, -1),
                             tau_out=tau.view(1, -1), arith=arith)
         cost += p["dt"] * _stage_cost_torch(xn.double(), tau.double(), p)
         x, xn = xn, x
     acc, n = ctl.proposal_stats() if policy is not None else (0, 0)
+    if lat is not None:
+        torch.cuda.synchronize()
+        lat.extend(a.elapsed_time(b) for a, b in ev)
     return float(cost.item()), x.cpu().numpy(), acc, n
 
 
@@ -234,21 +247,29 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024), K_learned=1024, ratio=4,
     wl = W.TERRAIN_WALK
     model = Bd.Model(W.model_dict(wl, 0))
     p = W.params_dict(wl, 0, v_ref=v_ref)
+    def pct(v):
+        return dict(p50=float(np.percentile(v, 50)), p99=float(np.percentile(v, 99)), mean=float(np.mean(v)))
+
     out = {"plain": {}, "seeds": list(seeds), "steps": steps, "v_ref": v_ref}
     for K in K_plain:
-        costs = [episode(model, dict(p, K=K), s, steps, arith=arith)[0] for s in seeds]
-        out["plain"][K] = dict(mean=float(np.mean(costs)), costs=costs, samples_per_step=K)
-        log(f"  plain K={K}: episode cost {np.mean(costs):.3f}")
+        lat = []
+        costs = [episode(model, dict(p, K=K), s, steps, arith=arith, lat=lat)[0] for s in seeds]
+        out["plain"][K] = dict(mean=float(np.mean(costs)), costs=costs, samples_per_step=K, latency_ms=pct(lat))
+        log(f"  plain K={K}: episode cost {np.mean(costs):.3f}, step latency p50 {np.percentile(lat, 50):.3f} "
+            f"p99 {np.percentile(lat, 99):.3f} ms")
     kp = K_learned // ratio
     for gate in ("cost", "none"):
-        res = [episode(model, dict(p, K=K_learned), s, steps, policy=policy, k_prop=kp, arith=arith, gate=gate)
-               for s in seeds]
+        lat = []
+        res = [episode(model, dict(p, K=K_learned), s, steps, policy=policy, k_prop=kp, arith=arith, gate=gate,
+                       lat=lat) for s in seeds]
         costs = [r[0] for r in res]
         acc = sum(r[2] for r in res)
         n = sum(r[3] for r in res)
         samples = (n * kp + (n - acc) * K_learned) / max(n, 1)
         out["learned_" + gate] = dict(mean=float(np.mean(costs)), costs=costs, k_prop=kp, K_fallback=K_learned,
-                                      accepted=acc, steps=n, acceptance=acc / max(n, 1), samples_per_step=samples)
+                                      accepted=acc, steps=n, acceptance=acc / max(n, 1), samples_per_step=samples,
+                                      latency_ms=pct(lat))
         log(f"  learned K/{ratio}={kp}, gate {gate}: episode cost {np.mean(costs):.3f}, "
-            f"acceptance {acc / max(n, 1):.2f}, {samples:.0f} samples/step")
+            f"acceptance {acc / max(n, 1):.2f}, {samples:.0f} samples/step, step latency p50 "
+            f"{np.percentile(lat, 50):.3f} p99 {np.percentile(lat, 99):.3f} ms")
     return out

@@ -143,3 +143,4 @@ def test_proposal_calls_reject_a_null_context():
     assert L.mppi_step_proposal(None, None, None, None, 16, 0, None) == B.EINVAL
     assert L.mppi_set_proposal(None, None, 16, 0, None, None) == B.EINVAL
     assert L.mppi_proposal_stats(None, None, None) == B.EINVAL
+    assert L.mppi_batch_set_proposal(None, 0, None, None, None) == B.EINVAL
