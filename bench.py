@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=8, help="proposal_training: Adam epochs")
     ap.add_argument("--eval-seeds", type=int, default=10, help="proposal_training: evaluation episodes")
     ap.add_argument("--eval-steps", type=int, default=200, help="proposal_training: steps per evaluation episode")
+    ap.add_argument("--eval-instances", type=int, default=256,
+                    help="proposal_training: instances of the batched-serving evaluation")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -272,6 +274,7 @@ def bench_proposal(args):
     achieved = fl / (step_ms * 1e-3) / 1e12
     pairs_s = 4096 / (step_ms * 1e-3)
     ev = PR.evaluate(pol, seeds=range(100, 100 + args.eval_seeds), steps=args.eval_steps, arith=args.arith, log=log)
+    evb = PR.evaluate_batched(pol, n_inst=args.eval_instances, steps=args.eval_steps, arith=args.arith, log=log)
     train_s = sum(h[2] for h in hist)
     train_steps = sum(h[3] for h in hist)
     st = data["stats"]
@@ -300,6 +303,7 @@ def bench_proposal(args):
                         for g in ("cost", "none")},
             "gates": "cost: proposal only when its centre costs no more than the nominal (plain K otherwise); "
                      "none: always the K/4 proposal samples, nominal kept as sample 1"},
+        "batched_equal_cost": evb,
         "epoch_seconds": train_s / max(len(hist), 1), "train_steps": train_steps,
         "generation": {"seconds": gen_s, "batch_seconds": st["seconds"], "episodes": st["episodes"],
                        "falls": st["falls"], "control_steps": st["control_steps"],

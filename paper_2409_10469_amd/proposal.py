@@ -273,3 +273,72 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024), K_learned=1024, ratio=4,
             f"acceptance {acc / max(n, 1):.2f}, {samples:.0f} samples/step, step latency p50 "
             f"{np.percentile(lat, 50):.3f} p99 {np.percentile(lat, 99):.3f} ms")
     return out
+
+
+def evaluate_batched(policy, n_inst=256, K_plain=(256, 1024), k_prop=256, steps=200, seed0=100, v_ref=0.5,
+                     arith="fp64", budget=1 << 30, log=print):
+    """Batched serving of n_inst heightfield walks (initial states from seeds seed0, ...)
+    in one batch per controller: plain MPPI at each K in K_plain and the learned proposal
+    with k_prop samples (ungated, the shifted nominal kept as sample 1).  The batch's
+    tuning is chosen by the autotuner on a separate batch of the same instances, so the
+    evaluated closed loops start from their initial states.  Per controller: the mean
+    episode cost (the batch's running cost, sum of dt * l), the fraction of instances
+    whose base ended below the fall height, the latency of each whole batch step (stream
+    events around it, including the proposal's features, network pass and head), and
+    rollout-steps/s over the steps."""
+    import torch
+    from . import binding as Bd
+    wl = W.TERRAIN_WALK
+    model = Bd.Model(W.model_dict(wl, 0))
+    nk, H = wl["nk"], wl["H"]
+
+    def make(K, learned):
+        batch = Bd.Batch(max_instances=n_inst, budget_bytes=budget, max_horizon=H, max_hf_cells=W.HF_N * W.HF_N,
+                         arith=arith)
+        slot = batch.add_model(model)
+        ids = []
+        for k in range(n_inst):
+            s = seed0 + k
+            p = dict(W.params_dict(wl, s, v_ref=v_ref, instance=k, arith=arith), K=K)
+            x0 = W.initial_state(s, W.SCENE_HEIGHTFIELD)
+            i = batch.admit(slot, p, x0, W.stance_knots(nk))
+            if i is None:
+                raise RuntimeError("the batch does not fit in the evaluation budget")
+            if learned:
+                batch.set_proposal(i, policy, cmd=(v_ref, 0.0, 0.0), origin=(float(x0[0]), float(x0[1])))
+            ids.append(i)
+        return batch, ids
+
+    out = {"task": "heightfield walk, v_ref %.2f, closed loop" % v_ref, "instances": n_inst, "steps": steps,
+           "seeds": [seed0, seed0 + n_inst - 1], "controllers": {}}
+    runs = [("plain_K%d" % K, K, False) for K in K_plain] + [("learned_K%d" % k_prop, k_prop, True)]
+    for name, K, learned in runs:
+        tb, _ = make(K, learned)
+        bpc, order, _ = tb.autotune(steps=3)
+        del tb
+        batch, ids = make(K, learned)
+        batch.set_tuning(bpc, order)
+        ev = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            batch.step()
+            e1.record()
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        reads = [batch.read(i, 37, nk) for i in ids]
+        costs = np.array([r[3] for r in reads], dtype=np.float64)
+        falls = int(sum(1 for r in reads if not (r[0][2] > FALL_Z)))
+        out["controllers"][name] = dict(
+            samples_per_step=K, proposal=learned, episode_cost=float(np.mean(costs)),
+            episode_cost_median=float(np.median(costs)), falls=falls,
+            latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                            mean=float(lat.mean())),
+            rollout_steps_per_s=n_inst * K * H * steps / wall, tuning=dict(blocks_per_cu=bpc, order=order))
+        log(f"  batched {name}: episode cost {np.mean(costs):.3f}, falls {falls}/{n_inst}, step latency p50 "
+            f"{np.percentile(lat, 50):.3f} p99 {np.percentile(lat, 99):.3f} ms")
+        del batch
+    return out

@@ -333,7 +333,8 @@ def test_learned_step_on_plain_kernels_matches_oracle_chain(B):
 def test_trained_proposal_gains_over_plain_and_untrained_at_equal_samples(B):
     """What the trained network gains: closed-loop heightfield walks (3 seeds x 100 steps,
     v_ref 0.5) with the K/4 = 256-sample proposal (ungated, nominal kept as sample 1)
-    against plain MPPI with the same 256 samples and against the untrained network."""
+    against plain MPPI with the same 256 samples and against the untrained network; then
+    in batched serving, where fewer samples also shorten the step."""
     from paper_2409_10469_amd import proposal as PR
     data = PR.generate(n_pairs=200000, episode_steps=100, instances=256, seed=11, log=lambda *a: None)
     tr, ho = PR.split(data, holdout=0.05, seed=0)
@@ -355,3 +356,9 @@ def test_trained_proposal_gains_over_plain_and_untrained_at_equal_samples(B):
     assert np.isfinite([plain, learned, naive]).all()
     assert learned < 0.8 * plain, (learned, plain)
     assert learned < naive, (learned, naive)
+    # batched serving (64 instances in one batch): the learned proposal at 256 samples
+    # against plain MPPI at 256 samples (cost) and at 1024 samples (step latency)
+    evb = PR.evaluate_batched(trained, n_inst=64, K_plain=(256, 1024), k_prop=256, steps=100, log=lambda *a: None)
+    c = evb["controllers"]
+    assert c["learned_K256"]["episode_cost"] < 0.8 * c["plain_K256"]["episode_cost"], c
+    assert c["learned_K256"]["latency_ms"]["p99"] < c["plain_K1024"]["latency_ms"]["p99"], c
