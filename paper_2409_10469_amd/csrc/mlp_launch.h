@@ -9,6 +9,7 @@ namespace mlp {
 constexpr int kLayers = 5;
 constexpr int kIn = 40, kInPad = 64, kHidden = 512, kOut = 144, kOutPad = 192, kKnots = 6;
 constexpr int kGemmBK = 64;  // reduction tile; every K handed to a GEMM is a multiple of it
+constexpr int kMaxSplits = 8;  // most batch splits of a weight-gradient product
 
 enum Epilogue {
     EPI_HIDDEN = 0,  // z = acc + b -> Z (fp32, optional), silu(z) -> H (bf16) and H^T (bf16, optional)
@@ -80,7 +81,7 @@ struct ReduceArgs {
     LayerGeom g;
     const float* wpart[kLayers];  // [S][fip][fop]
     const float* bpart[kLayers];  // [T][fop]
-    int S[kLayers], T[kLayers];
+    int S[kLayers], T[kLayers];  // S <= kMaxSplits
     float* G;
     const float* lpart;
     int nl;

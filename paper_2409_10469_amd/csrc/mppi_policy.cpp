@@ -42,7 +42,6 @@ const int kFi[kLayers] = {kIn, kHidden, kHidden, kHidden, kHidden};
 const int kFo[kLayers] = {kHidden, kHidden, kHidden, kHidden, kOut};
 const int kFip[kLayers] = {kInPad, kHidden, kHidden, kHidden, kHidden};
 const int kFop[kLayers] = {kHidden, kHidden, kHidden, kHidden, kOutPad};
-constexpr int kMaxSplits = 8;
 
 mppi_status pfail(mppi_policy* p, mppi_status s, const std::string& msg)
 {

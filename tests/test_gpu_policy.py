@@ -114,6 +114,24 @@ def test_gradient_is_deterministic(B):
     assert torch.equal(g1, g2) and torch.equal(l1, l2)
 
 
+def test_train_step_equals_gradient_then_adam(B):
+    """The fused training step (reduction and Adam in one pass) against the separate
+    gradient and Adam calls: same loss, same parameters, bit for bit."""
+    rng = np.random.default_rng(3)
+    N, Bsz = 700, 512
+    X, Y = _dev(rng.normal(size=(N, 40))), _dev(rng.normal(size=(N, 72)))
+    idx = _dev(rng.permutation(N)[:Bsz], np.int32)
+    a, b = B.Policy(max_batch=Bsz, seed=12), B.Policy(max_batch=Bsz, seed=12)
+    for _ in range(2):
+        la = a.train_step(X, Y, index=idx, B=Bsz, lr=1e-3)
+        lb, g = b.grad(X, Y, idx, B=Bsz)
+        b.adam(g, 1e-3)
+        assert torch.equal(la, lb)
+        assert torch.equal(a.get_params(), b.get_params())
+    out_a, out_b = a.forward(X[:64]), b.forward(X[:64])
+    assert torch.equal(out_a, out_b)  # the BF16 shadows agree too
+
+
 # ---------------------------------------------------------------------------- Adam
 def test_adam_two_steps_match_oracle_and_refresh_bf16_weights(B):
     pol = B.Policy(max_batch=64, seed=4)
