@@ -1,7 +1,8 @@
 """Benchmark of the whole-body MPPI hot path on one MI355X.
 
 One step = one closed-loop control step of the heightfield walking workload
-(K = 1024 samples, horizon H = 50 at dt = 0.01 s, 6 knots per joint): Philox sampling,
+(K = 1024 samples, horizon H = 50 at dt = 0.01 s, 6 knots per joint; by default 2000
+timed steps as 10 episodes of 200 steps from seeds 0-9): Philox sampling,
 the fused rollout of all samples, the Eq. 1 / Eq. 2 update with first-control
 extraction and shift, and one plant step with the chosen control -- all on the GPU,
 inputs resident in HBM.  Prints one JSON line.
@@ -74,11 +75,13 @@ def cpu_baseline(workload, seed, seconds):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000, help="timed control steps")
+    ap.add_argument("--episode-steps", type=int, default=200,
+                    help="control steps per closed-loop episode (a new seed every episode)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="heightfield_walk",
-                    help="heightfield_walk (default), flat_walk, box_push, box_climb, batched_serving or "
-                         "proposal_training")
+                    help="heightfield_walk (default), flat_walk, box_push, box_climb, batched_serving, "
+                         "proposal_training or sampling_ablation")
     ap.add_argument("--arith", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -110,21 +113,36 @@ def main():
         return bench_serving(args)
     if args.workload == "proposal_training":
         return bench_proposal(args)
+    if args.workload == "sampling_ablation":
+        return bench_ablation(args)
     wl = W.WORKLOADS[args.workload]
     md = W.model_dict(wl, args.seed)
     p = W.params_dict(wl, args.seed, arith=args.arith)
     model = B.Model(md)
-    ctl = B.Controller(model, p)
     K, H, nk = p["K"], p["H"], p["nk"]
     stream = torch.cuda.current_stream()
-
-    x = [torch.tensor(W.initial_state(args.seed, wl["scene"]), dtype=torch.float32, device="cuda"),
-         torch.empty(model.nx, dtype=torch.float32, device="cuda")]
-    ctl.set_nominal(torch.tensor(W.stance_knots(nk), dtype=torch.float32, device="cuda"))
+    # closed-loop episodes of `episode_steps` control steps on one terrain, each from its
+    # own seeded initial state with its own controller (own Philox key); controllers and
+    # buffers are made before the timed region
+    n_ep = max(1, -(-args.steps // args.episode_steps))
+    seeds = [args.seed + e for e in range(n_ep)]
+    ctls = [B.Controller(model, dict(p, seed=sd)) for sd in seeds]
+    x0s = [torch.tensor(W.initial_state(sd, wl["scene"]), dtype=torch.float32, device="cuda") for sd in seeds]
+    stance = torch.tensor(W.stance_knots(nk), dtype=torch.float32, device="cuda")
+    x = [torch.empty(model.nx, dtype=torch.float32, device="cuda") for _ in range(2)]
     costs = torch.empty(K, dtype=torch.float32, device="cuda")
     u0 = torch.empty(12, dtype=torch.float32, device="cuda")
+    cur = {"ctl": ctls[0], "i": 0}
 
-    def control_step(i, ev=None):
+    def start_episode(e):
+        cur["ctl"] = ctls[e]
+        cur["ctl"].set_nominal(stance)
+        cur["ctl"].set_step(0)
+        x[0].copy_(x0s[e])
+        cur["i"] = 0
+
+    def control_step(ev=None):
+        i, ctl = cur["i"], cur["ctl"]
         xi, xo = x[i % 2], x[(i + 1) % 2]
         if ev:
             ev[0].record(stream)
@@ -136,6 +154,7 @@ def main():
                             arith=args.arith)
         if ev:
             ev[2].record(stream)
+        cur["i"] = i + 1
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -144,20 +163,23 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for i in range(args.warmup):
-        control_step(i)
+    start_episode(0)
+    for _ in range(args.warmup):
+        control_step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        control_step(args.warmup + i, evs[i])
+    for k in range(args.steps):
+        if k % args.episode_steps == 0:
+            start_episode(k // args.episode_steps)
+        control_step(evs[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
     roll_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
-    status = ctl.sync_status()
-    xf = x[(args.warmup + args.steps) % 2].cpu().numpy()
+    status = max(c.sync_status() for c in ctls)
+    xf = x[cur["i"] % 2].cpu().numpy()
 
     value = K * H * args.steps / elapsed
     flops = flops_per_rollout_step(wl["scene"], nk) * K * H
@@ -178,7 +200,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "K": K, "H": H, "dt": p["dt"], "n_knots": nk, "scene": "heightfield 64x64"
                    if wl["scene"] == 1 else wl["name"], "closed_loop": True, "state": "f32",
-                   "step_arithmetic": args.arith},
+                   "step_arithmetic": args.arith, "episodes": n_ep, "episode_steps": args.episode_steps,
+                   "seeds": [seeds[0], seeds[-1]]},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "mean": float(step_ms.mean())},
         "rollout_kernel_ms": float(roll_ms.mean()),
@@ -294,12 +317,16 @@ def bench_proposal(args):
         "equal_cost_evaluation": {
             "task": "heightfield walk, v_ref 0.5, closed loop", "seeds": ev["seeds"], "steps": ev["steps"],
             "plain_episode_cost": {str(k): v["mean"] for k, v in ev["plain"].items()},
+            "plain_episode_cost_ci95": {str(k): v["ci95"] for k, v in ev["plain"].items()},
             "plain_step_latency_ms": {str(k): v["latency_ms"] for k, v in ev["plain"].items()},
             "learned": {g: {"episode_cost": ev["learned_" + g]["mean"], "k_prop": ev["learned_" + g]["k_prop"],
                             "fallback_K": ev["learned_" + g]["K_fallback"],
                             "acceptance": ev["learned_" + g]["acceptance"],
                             "samples_per_step": ev["learned_" + g]["samples_per_step"],
-                            "step_latency_ms": ev["learned_" + g]["latency_ms"]}
+                            "step_latency_ms": ev["learned_" + g]["latency_ms"],
+                            "episode_cost_ci95": ev["learned_" + g]["ci95"],
+                            "smallest_plain_K_matching": ev["learned_" + g]["smallest_plain_K_matching"],
+                            "sample_ratio": ev["learned_" + g]["sample_ratio"]}
                         for g in ("cost", "none")},
             "gates": "cost: proposal only when its centre costs no more than the nominal (plain K otherwise); "
                      "none: always the K/4 proposal samples, nominal kept as sample 1"},
@@ -309,6 +336,25 @@ def bench_proposal(args):
                        "falls": st["falls"], "control_steps": st["control_steps"],
                        "rollout_steps_per_s": st["rollout_steps"] / max(st["seconds"], 1e-9)},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_ablation(args):
+    """The sampling-representation ablation: closed-loop episodes of plain MPPI with the
+    cubic, linear and zeroth-order knot interpolation (same seeds, samples and horizon)."""
+    from paper_2409_10469_amd import proposal as PR
+    log = lambda m: print(m, flush=True)
+    t0 = time.perf_counter()
+    res = PR.sampling_ablation(seeds=range(args.seed, args.seed + args.eval_seeds), steps=args.eval_steps,
+                               arith=args.arith, log=log)
+    walk = res["heightfield_walk_6_knots"]["bases"]
+    out = {"metric": "closed-loop episode cost by knot interpolation", "value": walk["cubic"]["mean"],
+           "unit": "episode cost (heightfield walk, cubic)", "n_gpus": 1, "steps": args.eval_steps,
+           "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.arith == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": "sampling_ablation", "seeds": [args.seed, args.seed + args.eval_seeds - 1],
+                      "episode_steps": args.eval_steps},
+           "tasks": res, "seconds": time.perf_counter() - t0}
     print(json.dumps(out), flush=True)
 
 

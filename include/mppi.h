@@ -98,7 +98,17 @@ typedef struct mppi_params {
     uint64_t seed;
     uint32_t instance;
     int32_t arith;              /* MPPI_ARITH_FP64 (0, default) or MPPI_ARITH_FP32 */
+    int32_t basis;              /* knot interpolation, MPPI_BASIS_* (0: cubic, the default) */
 } mppi_params;
+
+/* Interpolation of the knots into per-step joint targets (Sec. III-B uses the cubic
+ * spline and names zeroth-order and linear interpolation as the alternatives):
+ *   CUBIC  not-a-knot cubic spline through the knots;
+ *   LINEAR straight lines between neighbouring knots;
+ *   ZERO   each knot's value held from its time until the next knot's.
+ * All three pass through the knots, so u0 is the first knot; the warm-start shift
+ * evaluates the same interpolant one step later. */
+enum { MPPI_BASIS_CUBIC = 0, MPPI_BASIS_LINEAR = 1, MPPI_BASIS_ZERO = 2 };
 
 typedef struct mppi_model mppi_model;
 typedef struct mppi_ctx mppi_ctx;
@@ -118,6 +128,11 @@ int mppi_model_nx(const mppi_model *model);
 mppi_status mppi_create(const mppi_model *model, const mppi_params *params, mppi_ctx **out);
 void mppi_destroy(mppi_ctx *ctx);
 size_t mppi_workspace_bytes(const mppi_ctx *ctx);
+/* Host copies of the matrices built at creation (Sec. III-B interpolation, Algorithm 1
+ * shift): B_out (HOST, H x n_knots, row k = weights of the knots in step k's joint
+ * targets) and S_out (HOST, n_knots x n_knots, the warm-start shift); either may be NULL.
+ * Launches nothing; needs no workspace. */
+mppi_status mppi_get_basis(const mppi_ctx *ctx, double *B_out, float *S_out);
 /* Binds a caller-owned device workspace and stream; uploads model data, spline basis and
  * shift matrix, and sets the nominal to zero.  The step counter is reset to 0. */
 mppi_status mppi_bind(mppi_ctx *ctx, void *d_workspace, size_t bytes, void *hip_stream);

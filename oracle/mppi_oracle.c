@@ -997,20 +997,46 @@ void orc_spline_eval(int nk, double T, const double *knots, double t, double *ou
     free(coef);
 }
 
-void orc_spline_basis(int nk, int H, double dt, double *B)
+/* Lower-order interpolations of the same knots (Sec. III-B): the segment is the knot
+   interval containing t (the last interval for t at or past the horizon end). */
+void orc_interp_eval(int basis, int nk, double T, const double *knots, double t, double *out)
+{
+    if (basis == 0) {
+        orc_spline_eval(nk, T, knots, t, out);
+        return;
+    }
+    double hk = T / (nk - 1);
+    if (basis == 2) {           /* zeroth order: the knot at the start of the interval; a time
+                                   within 1e-9 of an interval of a knot time counts as on it */
+        int s = (int)floor(t / hk + 1e-9);
+        if (s < 0) s = 0;
+        if (s > nk - 1) s = nk - 1;
+        *out = knots[s];
+        return;
+    }
+    int s = (int)floor(t / hk); /* linear */
+    if (s < 0) s = 0;
+    if (s > nk - 2) s = nk - 2;
+    double a = (t - s * hk) / hk;
+    *out = (1 - a) * knots[s] + a * knots[s + 1];
+}
+
+void orc_basis_matrix(int basis, int nk, int H, double dt, double *B)
 {
     double T = H * dt;
     double *e = calloc(nk, sizeof(double));
     for (int j = 0; j < nk; ++j) {
         memset(e, 0, sizeof(double) * nk);
         e[j] = 1;
-        for (int k = 0; k < H; ++k) orc_spline_eval(nk, T, e, k * dt, &B[k * nk + j]);
+        for (int k = 0; k < H; ++k) orc_interp_eval(basis, nk, T, e, k * dt, &B[k * nk + j]);
     }
     free(e);
 }
 
-/* warm-start shift: new knot j = old spline at t_j + dt, held at the horizon end */
-void orc_shift_matrix(int nk, int H, double dt, double *S)
+void orc_spline_basis(int nk, int H, double dt, double *B) { orc_basis_matrix(0, nk, H, dt, B); }
+
+/* warm-start shift: new knot j = old interpolant at t_j + dt, held at the horizon end */
+void orc_shift_matrix_b(int basis, int nk, int H, double dt, double *S)
 {
     double T = H * dt;
     double *e = calloc(nk, sizeof(double));
@@ -1020,11 +1046,13 @@ void orc_shift_matrix(int nk, int H, double dt, double *S)
         for (int i = 0; i < nk; ++i) {
             double t = i * T / (nk - 1) + dt;
             if (t > T) t = T;
-            orc_spline_eval(nk, T, e, t, &S[i * nk + j]);
+            orc_interp_eval(basis, nk, T, e, t, &S[i * nk + j]);
         }
     }
     free(e);
 }
+
+void orc_shift_matrix(int nk, int H, double dt, double *S) { orc_shift_matrix_b(0, nk, H, dt, S); }
 
 /* ------------------------------------------------------------------ */
 /* cost, rollout, MPPI                                                  */
@@ -1088,7 +1116,7 @@ static double rollout_with_basis(const orc_model *m, const orc_params *p, const 
 double orc_rollout(const orc_model *m, const orc_params *p, const double *x0, const double *theta, double *traj)
 {
     double *B = malloc(sizeof(double) * p->H * p->nk);
-    orc_spline_basis(p->nk, p->H, p->dt, B);
+    orc_basis_matrix(p->basis, p->nk, p->H, p->dt, B);
     double L = rollout_with_basis(m, p, B, x0, theta, traj);
     free(B);
     return L;
@@ -1100,7 +1128,7 @@ void orc_rollout_batch(const orc_model *m, const orc_params *p, const double *x0
 {
     int D = 12 * p->nk, nx = orc_nx(m);
     double *B = malloc(sizeof(double) * p->H * p->nk);
-    orc_spline_basis(p->nk, p->H, p->dt, B);
+    orc_basis_matrix(p->basis, p->nk, p->H, p->dt, B);
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
@@ -1164,9 +1192,9 @@ void orc_shift(const orc_params *p, const double *mu_prime, double *mu_out, doub
     int nk = p->nk;
     double T = p->H * p->dt;
     double *S = malloc(sizeof(double) * nk * nk);
-    orc_shift_matrix(nk, p->H, p->dt, S);
+    orc_shift_matrix_b(p->basis, nk, p->H, p->dt, S);
     for (int j = 0; j < 12; ++j) {
-        if (u0) orc_spline_eval(nk, T, mu_prime + j * nk, 0.0, &u0[j]);
+        if (u0) orc_interp_eval(p->basis, nk, T, mu_prime + j * nk, 0.0, &u0[j]);
         for (int i = 0; i < nk; ++i) {
             double s = 0;
             for (int l = 0; l < nk; ++l) s += S[i * nk + l] * mu_prime[j * nk + l];
@@ -1212,7 +1240,7 @@ int orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t ste
     double *theta = malloc(sizeof(double) * (size_t)Kp * D);
     double *B = malloc(sizeof(double) * p->H * p->nk);
     orc_sample_eps(&q, step, eps);
-    orc_spline_basis(p->nk, p->H, p->dt, B);
+    orc_basis_matrix(p->basis, p->nk, p->H, p->dt, B);
     for (int n = 0; n < Kp; ++n)
         for (int d = 0; d < D; ++d)
             theta[(size_t)n * D + d] = n == 0 ? center[d] : n == 1 ? mu[d] : center[d] + sd[d] * eps[(size_t)n * D + d];

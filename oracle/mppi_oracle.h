@@ -43,7 +43,8 @@ typedef struct orc_model {
 } orc_model;
 
 typedef struct orc_params {
-    int32_t K, H, nk, pad0;
+    int32_t K, H, nk;
+    int32_t basis;                /* knot interpolation: 0 cubic (not-a-knot), 1 linear, 2 zeroth order */
     double dt, sigma, lambda, kp, kd;
     double w_h, h_ref, w_o, w_v, v_ref, w_tau, w_reach, w_box;
     double goal[2];
@@ -62,6 +63,12 @@ void orc_philox_raw(const orc_params *p, uint32_t step, uint32_t *raw /* K x 4*c
 void orc_spline_basis(int nk, int H, double dt, double *B);
 void orc_spline_eval(int nk, double T, const double *knots, double t, double *out);
 void orc_shift_matrix(int nk, int H, double dt, double *S);
+/* The same for a chosen interpolation of the knots (Sec. III-B names the alternatives):
+   basis 0 the cubic spline above, 1 straight lines between neighbouring knots, 2 the
+   value of the knot at the start of each knot interval held until the next knot. */
+void orc_interp_eval(int basis, int nk, double T, const double *knots, double t, double *out);
+void orc_basis_matrix(int basis, int nk, int H, double dt, double *B);
+void orc_shift_matrix_b(int basis, int nk, int H, double dt, double *S);
 
 /* Rigid-body terms (no contact). */
 void orc_fk(const orc_model *m, const double *q, double *R /*13x9*/, double *pos /*13x3*/, double *com /*13x3*/);

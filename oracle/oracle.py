@@ -46,7 +46,7 @@ class Model(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [
-        ("K", C.c_int32), ("H", C.c_int32), ("nk", C.c_int32), ("pad0", C.c_int32),
+        ("K", C.c_int32), ("H", C.c_int32), ("nk", C.c_int32), ("basis", C.c_int32),
         ("dt", C.c_double), ("sigma", C.c_double), ("lam", C.c_double), ("kp", C.c_double), ("kd", C.c_double),
         ("w_h", C.c_double), ("h_ref", C.c_double), ("w_o", C.c_double), ("w_v", C.c_double),
         ("v_ref", C.c_double), ("w_tau", C.c_double), ("w_reach", C.c_double), ("w_box", C.c_double),
@@ -73,6 +73,9 @@ def lib():
             "orc_sample_eps": (None, [pp, C.c_uint32, dp]),
             "orc_philox_raw": (None, [pp, C.c_uint32, u32p]),
             "orc_spline_basis": (None, [C.c_int, C.c_int, C.c_double, dp]),
+            "orc_basis_matrix": (None, [C.c_int, C.c_int, C.c_int, C.c_double, dp]),
+            "orc_shift_matrix_b": (None, [C.c_int, C.c_int, C.c_int, C.c_double, dp]),
+            "orc_interp_eval": (None, [C.c_int, C.c_int, C.c_double, dp, C.c_double, dp]),
             "orc_spline_eval": (None, [C.c_int, C.c_double, dp, C.c_double, dp]),
             "orc_shift_matrix": (None, [C.c_int, C.c_int, C.c_double, dp]),
             "orc_fk": (None, [mp, dp, dp, dp, dp]),
@@ -162,6 +165,7 @@ class Oracle:
         s.goal[:] = [float(v) for v in p.get("goal", (0.0, 0.0))]
         s.seed = int(p.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
         s.instance = int(p.get("instance", 0))
+        s.basis = int(p.get("basis", 0))
         return s
 
     # ---- rigid body ----------------------------------------------------
@@ -312,6 +316,26 @@ def spline_basis(nk, H, dt):
     B = np.zeros((H, nk))
     lib().orc_spline_basis(int(nk), int(H), float(dt), _dp(B))
     return B
+
+
+def basis_matrix(basis, nk, H, dt):
+    """H x nk matrix of the knot interpolation (0 cubic, 1 linear, 2 zeroth order) at k dt."""
+    B = np.zeros((H, nk))
+    lib().orc_basis_matrix(int(basis), int(nk), int(H), float(dt), _dp(B))
+    return B
+
+
+def shift_matrix_b(basis, nk, H, dt):
+    S = np.zeros((nk, nk))
+    lib().orc_shift_matrix_b(int(basis), int(nk), int(H), float(dt), _dp(S))
+    return S
+
+
+def interp_eval(basis, knots, T, t):
+    k = _f64(knots)
+    out = np.zeros(1)
+    lib().orc_interp_eval(int(basis), int(k.size), float(T), _dp(k), float(t), _dp(out))
+    return out[0]
 
 
 def spline_eval(knots, T, t):

@@ -49,7 +49,7 @@ class Params(C.Structure):
         ("w_height", C.c_float), ("h_ref", C.c_float), ("w_upright", C.c_float), ("w_vel", C.c_float),
         ("v_ref", C.c_float), ("w_torque", C.c_float), ("w_reach", C.c_float), ("w_box", C.c_float),
         ("goal", C.c_float * 2),
-        ("seed", C.c_uint64), ("instance", C.c_uint32), ("arith", C.c_int32),
+        ("seed", C.c_uint64), ("instance", C.c_uint32), ("arith", C.c_int32), ("basis", C.c_int32),
     ]
 
 
@@ -71,6 +71,7 @@ def lib():
             "mppi_create": (C.c_int, [vp, C.POINTER(Params), C.POINTER(C.c_void_p)]),
             "mppi_destroy": (None, [vp]),
             "mppi_workspace_bytes": (C.c_size_t, [vp]),
+            "mppi_get_basis": (C.c_int, [vp, vp, vp]),
             "mppi_bind": (C.c_int, [vp, vp, C.c_size_t, vp]),
             "mppi_set_nominal": (C.c_int, [vp, fp]),
             "mppi_get_nominal": (C.c_int, [vp, fp]),
@@ -171,6 +172,7 @@ def params_struct(p: dict) -> Params:
     s.seed = int(p.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
     s.instance = int(p.get("instance", 0))
     s.arith = ARITH[p.get("arith", "fp64")]
+    s.basis = int(p.get("basis", 0))  # 0 cubic, 1 linear, 2 zeroth order
     return s
 
 

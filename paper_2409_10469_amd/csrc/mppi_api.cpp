@@ -122,7 +122,24 @@ double spline_value(int n, double h, const double* y, const double* m, double t)
            (y[s + 1] / h - m[s + 1] * h / 6) * tau;
 }
 
-void build_spline(int nk, int H, double dt, std::vector<double>& B, std::vector<float>& S)
+// weight of knot j in the lower-order interpolants at time t (knot spacing h); the
+// zeroth-order hold switches to a knot at its time, taken to within 1e-9 of an interval
+// so that k dt landing on a knot time holds that knot whatever the rounding of k dt / h
+double low_order_weight(int basis, int nk, double h, int j, double t)
+{
+    if (basis == MPPI_BASIS_ZERO) {
+        const int s = (int)std::floor(t / h + 1e-9);
+        return std::min(std::max(s, 0), nk - 1) == j ? 1.0 : 0.0;
+    }
+    int s = (int)std::floor(t / h);
+    s = std::min(std::max(s, 0), nk - 2);
+    const double a = (t - s * h) / h;
+    return j == s ? 1.0 - a : j == s + 1 ? a : 0.0;
+}
+
+// B[k][j]: weight of knot j in the joint target of step k; S[i][j]: weight of old knot j
+// in new knot i (the interpolant one step later, held at the horizon end)
+void build_spline(int nk, int H, double dt, int basis, std::vector<double>& B, std::vector<float>& S)
 {
     const double T = H * dt, h = T / (nk - 1);
     B.assign((size_t)H * nk, 0.0);
@@ -132,11 +149,12 @@ void build_spline(int nk, int H, double dt, std::vector<double>& B, std::vector<
         std::fill(y.begin(), y.end(), 0.0);
         y[j] = 1.0;
         second_derivatives(nk, h, y.data(), m.data());
-        for (int k = 0; k < H; ++k) B[(size_t)k * nk + j] = spline_value(nk, h, y.data(), m.data(), k * dt);
-        for (int i = 0; i < nk; ++i) {
-            const double t = std::min(i * h + dt, T);
-            S[(size_t)i * nk + j] = (float)spline_value(nk, h, y.data(), m.data(), t);
-        }
+        auto value = [&](double t) {
+            return basis == MPPI_BASIS_CUBIC ? spline_value(nk, h, y.data(), m.data(), t)
+                                             : low_order_weight(basis, nk, h, j, t);
+        };
+        for (int k = 0; k < H; ++k) B[(size_t)k * nk + j] = value(k * dt);
+        for (int i = 0; i < nk; ++i) S[(size_t)i * nk + j] = (float)value(std::min(i * h + dt, T));
     }
 }
 
@@ -212,9 +230,9 @@ bool model_info(const mppi_model* m, int* scene, int* nx, const float** hf, int*
     *dev_d = &m->dev_d;
     return true;
 }
-void spline_matrices(int nk, int H, double dt, std::vector<double>& B, std::vector<float>& S)
+void spline_matrices(int nk, int H, double dt, int basis, std::vector<double>& B, std::vector<float>& S)
 {
-    build_spline(nk, H, dt, B, S);
+    build_spline(nk, H, dt, basis, B, S);
 }
 double spline_basis_at(int nk, double T, int k, double t)
 {
@@ -310,12 +328,14 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     if (!std::isfinite(p->kp) || !std::isfinite(p->kd) || p->kd < 0.f)
         return fail(nullptr, MPPI_EINVAL, "kp must be finite, kd >= 0");
     if ((long)p->K * p->H > (1L << 31)) return fail(nullptr, MPPI_EINVAL, "K * H too large");
+    if (p->basis < MPPI_BASIS_CUBIC || p->basis > MPPI_BASIS_ZERO)
+        return fail(nullptr, MPPI_EINVAL, "basis must be MPPI_BASIS_CUBIC, _LINEAR or _ZERO");
     mppi_ctx* c = new (std::nothrow) mppi_ctx();
     if (!c) return fail(nullptr, MPPI_ENOMEM, "host allocation failed");
     c->model = *model;
     c->p = *p;
     c->D = 12 * p->n_knots;
-    build_spline(p->n_knots, p->H, p->dt, c->B, c->S);
+    build_spline(p->n_knots, p->H, p->dt, p->basis, c->B, c->S);
     size_t o = 0;
     c->off_B = o; o = align256(o + sizeof(double) * c->B.size());
     c->off_S = o; o = align256(o + sizeof(float) * c->S.size());
@@ -338,6 +358,14 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
 void mppi_destroy(mppi_ctx* c) { delete c; }
 
 size_t mppi_workspace_bytes(const mppi_ctx* c) { return c ? c->total : 0; }
+
+mppi_status mppi_get_basis(const mppi_ctx* c, double* B_out, float* S_out)
+{
+    if (!c) return fail(nullptr, MPPI_EINVAL, "null context");
+    if (B_out) std::memcpy(B_out, c->B.data(), sizeof(double) * c->B.size());
+    if (S_out) std::memcpy(S_out, c->S.data(), sizeof(float) * c->S.size());
+    return MPPI_OK;
+}
 
 mppi_status mppi_bind(mppi_ctx* c, void* ws, size_t bytes, void* stream)
 {

@@ -37,7 +37,7 @@ extern "C++" {
 namespace mppi_host {
 bool model_info(const mppi_model* m, int* scene, int* nx, const float** hf, int* hf_cells, const void** dev_f,
                 const void** dev_d);
-void spline_matrices(int nk, int H, double dt, std::vector<double>& B, std::vector<float>& S);
+void spline_matrices(int nk, int H, double dt, int basis, std::vector<double>& B, std::vector<float>& S);
 }  // namespace mppi_host
 }
 
@@ -481,6 +481,7 @@ mppi_status mppi_batch_admit(mppi_batch* b, int slot, const mppi_params* p, cons
     if (p->H < 1 || p->H > b->max_H) return bfail(b, MPPI_EINVAL, "H outside [1, max_horizon]");
     if (p->n_knots < 2 || p->n_knots > MPPI_MAX_KNOTS) return bfail(b, MPPI_EINVAL, "n_knots must be in [2, 8]");
     if (!(p->dt > 0.f) || !(p->lambda > 0.f) || !(p->sigma >= 0.f)) return bfail(b, MPPI_EINVAL, "bad dt/lambda/sigma");
+    if (p->basis < MPPI_BASIS_CUBIC || p->basis > MPPI_BASIS_ZERO) return bfail(b, MPPI_EINVAL, "unknown basis");
     int id = -1;
     for (int i = 0; i < b->max_inst; ++i)
         if (!b->inst[i].live) {
@@ -510,7 +511,7 @@ mppi_status mppi_batch_admit(mppi_batch* b, int slot, const mppi_params* p, cons
     std::vector<char> init(in.bytes, 0);
     std::vector<double> Bm;
     std::vector<float> Sm;
-    mppi_host::spline_matrices(p->n_knots, p->H, p->dt, Bm, Sm);
+    mppi_host::spline_matrices(p->n_knots, p->H, p->dt, p->basis, Bm, Sm);
     std::memcpy(&init[in.o_B], Bm.data(), sizeof(double) * Bm.size());
     std::memcpy(&init[in.o_S], Sm.data(), sizeof(float) * Sm.size());
     std::memcpy(&init[in.o_x], x0, sizeof(float) * nx);

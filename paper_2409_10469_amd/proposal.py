@@ -200,7 +200,8 @@ def _stage_cost_torch(x, tau, p):
 
 
 def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="cost", lat=None):
-    """One closed-loop episode of the heightfield walk from the seeded stance; returns the
+    """One closed-loop episode of a walking task (the model's scene, walking cost of p)
+    from the seeded stance; returns the
     episode cost sum dt * l, the final state and the proposal counters.  With a list
     `lat`, appends each control step's latency in ms: stream events around the step, so
     the time runs from the moment the plant state is on the device to the first control,
@@ -208,7 +209,7 @@ def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="co
     import torch
     from . import binding as Bd
     ctl = Bd.Controller(model, dict(p, seed=seed, arith=arith))
-    x0 = W.initial_state(seed, W.SCENE_HEIGHTFIELD)
+    x0 = W.initial_state(seed, model.scene)
     x = torch.tensor(x0, dtype=torch.float32, device="cuda")
     xn = torch.empty_like(x)
     tau = torch.empty(12, dtype=torch.float32, device="cuda")
@@ -250,11 +251,17 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024), K_learned=1024, ratio=4,
     def pct(v):
         return dict(p50=float(np.percentile(v, 50)), p99=float(np.percentile(v, 99)), mean=float(np.mean(v)))
 
+    def ci95(v):  # normal-approximation interval of the mean over the seeds
+        v = np.asarray(v, dtype=np.float64)
+        h = 1.96 * v.std(ddof=1) / np.sqrt(v.size) if v.size > 1 else float("nan")
+        return [float(v.mean() - h), float(v.mean() + h)]
+
     out = {"plain": {}, "seeds": list(seeds), "steps": steps, "v_ref": v_ref}
     for K in K_plain:
         lat = []
         costs = [episode(model, dict(p, K=K), s, steps, arith=arith, lat=lat)[0] for s in seeds]
-        out["plain"][K] = dict(mean=float(np.mean(costs)), costs=costs, samples_per_step=K, latency_ms=pct(lat))
+        out["plain"][K] = dict(mean=float(np.mean(costs)), ci95=ci95(costs), costs=costs, samples_per_step=K,
+                               latency_ms=pct(lat))
         log(f"  plain K={K}: episode cost {np.mean(costs):.3f}, step latency p50 {np.percentile(lat, 50):.3f} "
             f"p99 {np.percentile(lat, 99):.3f} ms")
     kp = K_learned // ratio
@@ -266,9 +273,15 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024), K_learned=1024, ratio=4,
         acc = sum(r[2] for r in res)
         n = sum(r[3] for r in res)
         samples = (n * kp + (n - acc) * K_learned) / max(n, 1)
-        out["learned_" + gate] = dict(mean=float(np.mean(costs)), costs=costs, k_prop=kp, K_fallback=K_learned,
+        out["learned_" + gate] = dict(mean=float(np.mean(costs)), ci95=ci95(costs), costs=costs, k_prop=kp,
+                                      K_fallback=K_learned,
                                       accepted=acc, steps=n, acceptance=acc / max(n, 1), samples_per_step=samples,
                                       latency_ms=pct(lat))
+        # the smallest plain K whose mean episode cost is not above the learned controller's
+        match = [K for K in K_plain if out["plain"][K]["mean"] <= np.mean(costs)]
+        out["learned_" + gate]["smallest_plain_K_matching"] = min(match) if match else None
+        out["learned_" + gate]["sample_ratio"] = (min(match) / samples if match else
+                                                  "> %g" % (max(K_plain) / samples))
         log(f"  learned K/{ratio}={kp}, gate {gate}: episode cost {np.mean(costs):.3f}, "
             f"acceptance {acc / max(n, 1):.2f}, {samples:.0f} samples/step, step latency p50 "
             f"{np.percentile(lat, 50):.3f} p99 {np.percentile(lat, 99):.3f} ms")
@@ -341,4 +354,40 @@ def evaluate_batched(policy, n_inst=256, K_plain=(256, 1024), k_prop=256, steps=
         log(f"  batched {name}: episode cost {np.mean(costs):.3f}, falls {falls}/{n_inst}, step latency p50 "
             f"{np.percentile(lat, 50):.3f} p99 {np.percentile(lat, 99):.3f} ms")
         del batch
+    return out
+
+
+BASES = {"cubic": 0, "linear": 1, "zeroth_order": 2}
+
+
+def sampling_ablation(seeds=range(10), steps=200, arith="fp64", log=print):
+    """Closed-loop episode cost of plain MPPI with each knot interpolation (the paper's
+    sampling-representation ablation, Sec. IV) on three synthetic tasks: the heightfield
+    walk with 6 and with 4 knots per joint, and the climb onto a 0.3 m box with the base
+    height target raised by the box height.  Same seeds, samples and horizon for every
+    basis; returns per task and basis the mean episode cost, its 95% interval over the
+    seeds, and the falls."""
+    tasks = [
+        ("heightfield_walk_6_knots", W.TERRAIN_WALK, {}),
+        ("heightfield_walk_4_knots", W.TERRAIN_WALK, {"nk": 4}),
+        ("box_climb_6_knots", W.BOX_CLIMB, {"h_ref": W.WALK_COST["h_ref"] + 2 * W.CLIMB_BOX_HALF[2]}),
+    ]
+    out = {}
+    for name, wl, over in tasks:
+        model = B.Model(W.model_dict(wl, 0))
+        res = {}
+        for bname, basis in BASES.items():
+            costs, falls = [], 0
+            for sd in seeds:
+                p = dict(W.params_dict(wl, sd, **over), basis=basis)
+                c, xf, _, _ = episode(model, p, sd, steps, arith=arith)
+                costs.append(c)
+                falls += int(not (xf[2] > FALL_Z))
+            v = np.asarray(costs)
+            h = 1.96 * v.std(ddof=1) / np.sqrt(v.size) if v.size > 1 else float("nan")
+            res[bname] = dict(mean=float(v.mean()), ci95=[float(v.mean() - h), float(v.mean() + h)], falls=falls,
+                              costs=[float(c) for c in costs])
+            log(f"  {name} {bname}: episode cost {v.mean():.3f} +- {h:.3f}, falls {falls}/{v.size}")
+        order = sorted(res, key=lambda b: res[b]["mean"])
+        out[name] = dict(K=wl["K"], H=wl["H"], nk=over.get("nk", wl["nk"]), bases=res, ranking=order)
     return out

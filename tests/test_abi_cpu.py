@@ -78,7 +78,7 @@ def test_heightfield_validation():
 
 
 @pytest.mark.parametrize("over", [dict(K=0), dict(H=0), dict(H=1000), dict(nk=1), dict(nk=9), dict(dt=0.0),
-                                  dict(lam=0.0), dict(sigma=-1.0), dict(kd=-1.0)])
+                                  dict(lam=0.0), dict(sigma=-1.0), dict(kd=-1.0), dict(basis=3), dict(basis=-1)])
 def test_params_validation(over):
     rc, mh = _model_handle()
     assert rc == 0
@@ -144,3 +144,26 @@ def test_proposal_calls_reject_a_null_context():
     assert L.mppi_set_proposal(None, None, 16, 0, None, None) == B.EINVAL
     assert L.mppi_proposal_stats(None, None, None) == B.EINVAL
     assert L.mppi_batch_set_proposal(None, 0, None, None, None) == B.EINVAL
+
+
+@pytest.mark.parametrize("basis", [0, 1, 2])
+@pytest.mark.parametrize("nk,H,dt", [(2, 10, 0.02), (4, 25, 0.02), (6, 50, 0.01), (8, 60, 0.01), (5, 80, 0.01)])
+def test_library_basis_and_shift_equal_the_oracle(basis, nk, H, dt):
+    """The controller's host-built interpolation and shift matrices against the oracle's,
+    from the same FP32 dt (so knot-time steps of the zeroth-order hold are decided alike)."""
+    import numpy as np
+    from oracle import oracle as O
+    rc, mh = _model_handle()
+    p = W.params_dict(W.FLAT_WALK, 0, K=8, H=H, nk=nk)
+    p["basis"], p["dt"] = basis, float(np.float32(dt))
+    ps = B.params_struct(p)
+    h = C.c_void_p()
+    assert B.lib().mppi_create(mh, C.byref(ps), C.byref(h)) == 0
+    Bm = np.zeros((H, nk))
+    Sm = np.zeros((nk, nk), dtype=np.float32)
+    assert B.lib().mppi_get_basis(h, Bm.ctypes.data_as(C.c_void_p), Sm.ctypes.data_as(C.c_void_p)) == 0
+    np.testing.assert_allclose(Bm, O.basis_matrix(basis, nk, H, p["dt"]), atol=1e-12)
+    np.testing.assert_allclose(Sm, O.shift_matrix_b(basis, nk, H, p["dt"]), atol=1e-6)
+    assert B.lib().mppi_get_basis(None, None, None) == B.EINVAL
+    B.lib().mppi_destroy(h)
+    B.lib().mppi_model_destroy(mh)

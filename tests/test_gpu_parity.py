@@ -359,3 +359,36 @@ def test_static_box_climb_one_step(B, seed):
     want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
     err = step_error(got, want)
     assert err.max() <= STEP_TOL, (err.max(), int(err.argmax()))
+
+
+# ---------------------------------------------------------------------------- lower-order knot bases
+@pytest.mark.parametrize("basis", [1, 2])
+@pytest.mark.parametrize("workload,K,H", [(W.FLAT_WALK, 64, 25), (W.TERRAIN_WALK, 128, 50)])
+def test_mppi_step_with_lower_order_bases_matches_oracle(B, workload, K, H, basis):
+    """Full control steps with linear and zeroth-order knot interpolation: the same
+    kernels read the host-built matrices of the chosen basis."""
+    md, p, orc, model, ctl = _setup(B, workload, K=K, H=H, basis=basis)
+    for seed in range(2):
+        x0 = f32(W.initial_state(seed, workload["scene"]))
+        mu = f32(W.stance_knots(p["nk"]) + np.random.default_rng(seed).uniform(-0.05, 0.05, 12 * p["nk"]))
+        ctl.set_nominal(_dev(mu))
+        ctl.set_step(seed)
+        u0 = ctl.step(_dev(x0)).cpu().numpy()
+        nominal = ctl.get_nominal().cpu().numpy()
+        assert ctl.sync_status() == 0
+        ou0, omu, _, _ = orc.mppi_step(p, seed, x0, mu)
+        assert np.abs(u0 - ou0).max() <= KNOT_TOL, (basis, seed)
+        assert np.abs(nominal - omu).max() <= KNOT_TOL, (basis, seed)
+
+
+@pytest.mark.parametrize("basis", [1, 2])
+def test_rollout_costs_10_steps_lower_order_bases(B, basis):
+    md, p, orc, model, ctl = _setup(B, W.TERRAIN_WALK, K=48, H=10, basis=basis)
+    x0 = f32(W.initial_state(3, W.SCENE_HEIGHTFIELD))
+    mu = f32(W.stance_knots(p["nk"]) + np.random.default_rng(2).uniform(-0.1, 0.1, 12 * p["nk"]))
+    eps = f32(W.explicit_noise(5, 48, p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    got = ctl.rollout_batch(_dev(x0), eps=_dev(eps)).cpu().numpy().astype(np.float64)
+    want = orc.rollout_batch(p, x0, mu, eps)
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6)
+    assert rel.max() <= COST_TOL, (rel.max(), int(rel.argmax()))

@@ -116,3 +116,62 @@ def test_shift_of_constant_and_line(nk):
     line = 0.2 + 1.5 * tk
     want = 0.2 + 1.5 * np.minimum(tk + dt, T)
     np.testing.assert_allclose(S @ line, want, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------- lower-order knot bases
+# The paper samples knots of a cubic spline and names zeroth-order and linear
+# interpolation as the alternatives (Sec. III-B, the sampling-representation ablation of
+# Sec. IV).  Pins: numpy's piecewise-linear interpolation, a step lookup by sorted search,
+# partition of unity, and interpolation at the knot times.
+LINEAR, ZERO = 1, 2
+
+
+@pytest.mark.parametrize("nk,H,dt", [(2, 10, 0.02), (4, 25, 0.02), (6, 50, 0.01), (8, 60, 0.01)])
+def test_linear_basis_is_numpy_interp(nk, H, dt):
+    T = H * dt
+    tk = np.linspace(0, T, nk)
+    t = dt * np.arange(H)
+    y = np.random.default_rng(nk).normal(size=nk)
+    np.testing.assert_allclose(O.basis_matrix(LINEAR, nk, H, dt) @ y, np.interp(t, tk, y), atol=1e-12)
+    S = O.shift_matrix_b(LINEAR, nk, H, dt)
+    np.testing.assert_allclose(S @ y, np.interp(np.minimum(tk + dt, T), tk, y), atol=1e-12)
+
+
+@pytest.mark.parametrize("nk,H,dt", [(2, 10, 0.02), (4, 25, 0.02), (6, 50, 0.01), (8, 60, 0.01)])
+def test_zeroth_order_basis_holds_the_left_knot(nk, H, dt):
+    T = H * dt
+    tk = np.linspace(0, T, nk)
+    t = dt * np.arange(H)
+    y = np.random.default_rng(nk + 1).normal(size=nk)
+    # the knot interval holding t: the last knot time not after t (small slack for the
+    # rounding of k dt against j T / (nk - 1))
+    idx = np.searchsorted(tk, t + 1e-12, side="right") - 1
+    np.testing.assert_allclose(O.basis_matrix(ZERO, nk, H, dt) @ y, y[idx], atol=0)
+    # one step later is still inside each knot interval when dt < T / (nk - 1): S = I
+    np.testing.assert_allclose(O.shift_matrix_b(ZERO, nk, H, dt), np.eye(nk), atol=0)
+
+
+@pytest.mark.parametrize("basis", [0, LINEAR, ZERO])
+def test_bases_partition_unity_and_pass_through_knots(basis):
+    nk, H, dt = 4, 12, 0.02  # knot times fall on steps 0, 4, 8 (and the horizon end)
+    B = O.basis_matrix(basis, nk, H, dt)
+    np.testing.assert_allclose(B.sum(1), 1.0, atol=1e-12)
+    for j, k in enumerate((0, 4, 8)):
+        e = np.zeros(nk)
+        e[j] = 1
+        np.testing.assert_allclose(B[k], e, atol=1e-12)
+    # u0 is the first knot for every basis
+    y = np.array([0.3, -0.1, 0.5, 0.2])
+    assert O.interp_eval(basis, y, H * dt, 0.0) == pytest.approx(0.3, abs=1e-14)
+    if basis == 0:
+        np.testing.assert_allclose(B, O.spline_basis(nk, H, dt), atol=0)
+
+
+def test_linear_basis_reproduces_lines_and_is_not_cubic():
+    nk, H, dt = 6, 50, 0.01
+    tk = np.linspace(0, H * dt, nk)
+    t = dt * np.arange(H)
+    BL = O.basis_matrix(LINEAR, nk, H, dt)
+    np.testing.assert_allclose(BL @ (0.4 - 2.0 * tk), 0.4 - 2.0 * t, atol=1e-12)
+    q = tk ** 2
+    assert np.abs(BL @ q - t ** 2).max() > 1e-4  # a parabola is only matched at the knots
