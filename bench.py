@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="heightfield_walk",
                     help="heightfield_walk (default), flat_walk, box_push, box_climb, batched_serving, "
-                         "proposal_training or sampling_ablation")
+                         "proposal_training or ablations")
     ap.add_argument("--arith", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -113,7 +113,7 @@ def main():
         return bench_serving(args)
     if args.workload == "proposal_training":
         return bench_proposal(args)
-    if args.workload == "sampling_ablation":
+    if args.workload == "ablations":
         return bench_ablation(args)
     wl = W.WORKLOADS[args.workload]
     md = W.model_dict(wl, args.seed)
@@ -340,21 +340,24 @@ def bench_proposal(args):
 
 
 def bench_ablation(args):
-    """The sampling-representation ablation: closed-loop episodes of plain MPPI with the
-    cubic, linear and zeroth-order knot interpolation (same seeds, samples and horizon)."""
-    from paper_2409_10469_amd import proposal as PR
+    """The ablations of the plain method: closed-loop episodes with the cubic, linear and
+    zeroth-order knot interpolation (same seeds, samples and horizon), then one-at-a-time
+    sweeps of lambda, H, K and the control rate on the heightfield walk."""
+    from paper_2409_10469_amd import ablations as AB
     log = lambda m: print(m, flush=True)
     t0 = time.perf_counter()
-    res = PR.sampling_ablation(seeds=range(args.seed, args.seed + args.eval_seeds), steps=args.eval_steps,
+    res = AB.sampling_ablation(seeds=range(args.seed, args.seed + args.eval_seeds), steps=args.eval_steps,
                                arith=args.arith, log=log)
+    sweeps = AB.hyperparameter_sweeps(seeds=range(args.seed, args.seed + args.eval_seeds), steps=args.eval_steps,
+                                      arith=args.arith, log=log)
     walk = res["heightfield_walk_6_knots"]["bases"]
-    out = {"metric": "closed-loop episode cost by knot interpolation", "value": walk["cubic"]["mean"],
+    out = {"metric": "closed-loop episode cost of the plain method's ablations", "value": walk["cubic"]["mean"],
            "unit": "episode cost (heightfield walk, cubic)", "n_gpus": 1, "steps": args.eval_steps,
            "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.arith == "fp64" else "f32", "data": "synthetic",
-           "config": {"workload": "sampling_ablation", "seeds": [args.seed, args.seed + args.eval_seeds - 1],
+           "config": {"workload": "ablations", "seeds": [args.seed, args.seed + args.eval_seeds - 1],
                       "episode_steps": args.eval_steps},
-           "tasks": res, "seconds": time.perf_counter() - t0}
+           "tasks": res, "sweeps": sweeps, "seconds": time.perf_counter() - t0}
     print(json.dumps(out), flush=True)
 
 

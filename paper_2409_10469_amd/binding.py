@@ -251,6 +251,13 @@ class Controller:
     def set_step(self, step):
         self._s(lib().mppi_set_step(self.h, int(step)))
 
+    def basis_matrices(self):
+        """Host copies of the interpolation matrix B (H x nk) and the shift S (nk x nk)."""
+        Bm = np.zeros((self.p["H"], self.p["nk"]))
+        Sm = np.zeros((self.p["nk"], self.p["nk"]), dtype=np.float32)
+        self._s(lib().mppi_get_basis(self.h, Bm.ctypes.data_as(C.c_void_p), Sm.ctypes.data_as(C.c_void_p)))
+        return Bm, Sm
+
     @property
     def step_counter(self):
         return lib().mppi_get_step(self.h)

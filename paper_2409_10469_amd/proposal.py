@@ -356,38 +356,3 @@ def evaluate_batched(policy, n_inst=256, K_plain=(256, 1024), k_prop=256, steps=
         del batch
     return out
 
-
-BASES = {"cubic": 0, "linear": 1, "zeroth_order": 2}
-
-
-def sampling_ablation(seeds=range(10), steps=200, arith="fp64", log=print):
-    """Closed-loop episode cost of plain MPPI with each knot interpolation (the paper's
-    sampling-representation ablation, Sec. IV) on three synthetic tasks: the heightfield
-    walk with 6 and with 4 knots per joint, and the climb onto a 0.3 m box with the base
-    height target raised by the box height.  Same seeds, samples and horizon for every
-    basis; returns per task and basis the mean episode cost, its 95% interval over the
-    seeds, and the falls."""
-    tasks = [
-        ("heightfield_walk_6_knots", W.TERRAIN_WALK, {}),
-        ("heightfield_walk_4_knots", W.TERRAIN_WALK, {"nk": 4}),
-        ("box_climb_6_knots", W.BOX_CLIMB, {"h_ref": W.WALK_COST["h_ref"] + 2 * W.CLIMB_BOX_HALF[2]}),
-    ]
-    out = {}
-    for name, wl, over in tasks:
-        model = B.Model(W.model_dict(wl, 0))
-        res = {}
-        for bname, basis in BASES.items():
-            costs, falls = [], 0
-            for sd in seeds:
-                p = dict(W.params_dict(wl, sd, **over), basis=basis)
-                c, xf, _, _ = episode(model, p, sd, steps, arith=arith)
-                costs.append(c)
-                falls += int(not (xf[2] > FALL_Z))
-            v = np.asarray(costs)
-            h = 1.96 * v.std(ddof=1) / np.sqrt(v.size) if v.size > 1 else float("nan")
-            res[bname] = dict(mean=float(v.mean()), ci95=[float(v.mean() - h), float(v.mean() + h)], falls=falls,
-                              costs=[float(c) for c in costs])
-            log(f"  {name} {bname}: episode cost {v.mean():.3f} +- {h:.3f}, falls {falls}/{v.size}")
-        order = sorted(res, key=lambda b: res[b]["mean"])
-        out[name] = dict(K=wl["K"], H=wl["H"], nk=over.get("nk", wl["nk"]), bases=res, ranking=order)
-    return out
