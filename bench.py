@@ -48,6 +48,26 @@ def traffic_from_profile(workload: str, arith: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def counter_rate(flops_per_launch, kernel_ms, peak):
+    if flops_per_launch is None:
+        return None
+    tf = flops_per_launch / (kernel_ms * 1e-3) / 1e12
+    return {"achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak, "flops_per_launch": flops_per_launch,
+            "source": "VALU instruction counters, 64 x (ADD + MUL + 2 FMA + TRANS)"}
+
+
+def counter_flops_from_profile(workload: str, arith: str):
+    """Counter FLOPs per rollout launch (64 x (ADD + MUL + 2 FMA + TRANS) from the VALU
+    instruction counters), if the committed summary was taken on the current source."""
+    path = os.path.join(ROOT, "profiles", f"rollout_{workload}_{arith}_flops.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("counter_flops_per_launch")
+
+
 def cpu_baseline(workload, seed, seconds):
     import numpy as np
     from oracle import oracle as O
@@ -208,6 +228,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic_from_profile(wl["name"], args.arith),
                      "flops_per_rollout_step": flops_per_rollout_step(wl["scene"], nk)},
+        "counter_flops": counter_rate(counter_flops_from_profile(wl["name"], args.arith), roll_ms.mean(), peak),
         "final_state_finite": bool(np.isfinite(xf).all()),
         "update_status": int(status),
     }
