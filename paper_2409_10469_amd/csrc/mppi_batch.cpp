@@ -165,12 +165,13 @@ size_t prop_bytes(int max_inst)
            align_up(sizeof(float) * 144 * max_inst) + align_up(sizeof(float) * 9 * 8 * 6);
 }
 
+// teardown: errors here have no caller to report to and do not change what is released
 void drop_graph(mppi_batch* b)
 {
     // an executable graph may still be running on the caller's stream: let it finish
-    if (b->exec && b->stream) hipStreamSynchronize(b->stream);
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec && b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
 }
@@ -375,13 +376,13 @@ mppi_status mppi_batch_create(int max_instances, int max_horizon, int max_hf_cel
 void mppi_batch_destroy(mppi_batch* b)
 {
     if (!b) return;
-    if (b->stream) hipStreamSynchronize(b->stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    if (b->upload_done) hipEventDestroy(b->upload_done);
-    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
-    if (b->h_table) hipHostFree(b->h_table);
-    if (b->h_tiles) hipHostFree(b->h_tiles);
-    if (b->h_prows) hipHostFree(b->h_prows);
+    if (b->upload_done) (void)hipEventDestroy(b->upload_done);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->h_table) (void)hipHostFree(b->h_table);
+    if (b->h_tiles) (void)hipHostFree(b->h_tiles);
+    if (b->h_prows) (void)hipHostFree(b->h_prows);
     delete b;
 }
 
@@ -620,21 +621,24 @@ mppi_status mppi_batch_autotune(mppi_batch* b, int steps, int* best_blocks_per_c
     const int cand_blocks[] = {2, 4, 8, 16};
     float best = 1e30f;
     int bb = b->blocks_per_cu, bo = b->order;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return bfail(b, MPPI_EHIP, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return bfail(b, MPPI_EHIP, "event create");
+    }
     mppi_status s = MPPI_OK;
     for (int order = 0; order < 2 && !s; ++order)
         for (int cb : cand_blocks) {
             if ((s = mppi_batch_set_tuning(b, cb, order))) break;
             if ((s = mppi_batch_step(b))) break;  // warm-up and capture
-            hipEventRecord(e0, b->stream);
+            if ((s = bhip(b, hipEventRecord(e0, b->stream), "autotune event"))) break;
             for (int i = 0; i < steps && !s; ++i) s = mppi_batch_step(b);
-            hipEventRecord(e1, b->stream);
-            if (s) break;
-            hipEventSynchronize(e1);
+            if (s || (s = bhip(b, hipEventRecord(e1, b->stream), "autotune event"))) break;
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
+            if ((s = bhip(b, hipEventSynchronize(e1), "autotune wait")) ||
+                (s = bhip(b, hipEventElapsedTime(&ms, e0, e1), "autotune timing")))
+                break;
             ms /= steps;
             if (ms < best) {
                 best = ms;
@@ -642,8 +646,8 @@ mppi_status mppi_batch_autotune(mppi_batch* b, int steps, int* best_blocks_per_c
                 bo = order;
             }
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (s) return s;
     if ((s = mppi_batch_set_tuning(b, bb, bo))) return s;
     if (best_blocks_per_cu) *best_blocks_per_cu = bb;
