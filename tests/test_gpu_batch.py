@@ -197,3 +197,61 @@ def test_record_rows_are_step_states_and_unshifted_updates(B):
     torch.cuda.synchronize()
     assert torch.equal(snap, rec)  # recording stopped
     batch.remove(other)
+
+
+def test_full_size_serving_batch_sampled_instances(B):
+    """The serving workload at full size: 256 requests drawn as the serving driver draws
+    them (mixed tasks, K log-uniform in [256, 4096], H uniform in [20, 80]), all admitted,
+    one step in the persistent launch.  Sampled instances (the largest and smallest K of
+    each task) against the single-instance controller, the two smallest also against the
+    oracle."""
+    from paper_2409_10469_amd import serving as SV
+    rng = np.random.default_rng(2024)
+    reqs = [SV.draw_request(rng, i) for i in range(256)]
+    batch = B.Batch(max_instances=256, budget_bytes=1 << 30, max_horizon=SV.H_RANGE[1],
+                    max_hf_cells=W.HF_N * W.HF_N)
+    models, mds, slots = {}, {}, {}
+    for name, t in SV.TASKS.items():
+        mds[name] = round_model(W.model_dict(t["workload"], 0))
+        models[name] = B.Model(mds[name])
+        slots[name] = batch.add_model(models[name])
+    ids, refs = [], []
+    for r in reqs:
+        t = SV.TASKS[r["task"]]
+        p = round_params(W.params_dict(t["workload"], r["seed"], K=r["K"], H=r["H"], nk=t["nk"], dt=t["dt"],
+                                       sigma=t["sigma"], lam=t["lam"], instance=r["id"]))
+        x0 = _init_state(t["workload"], r["seed"])
+        mu = f32(W.stance_knots(t["nk"]))
+        i = batch.admit(slots[r["task"]], p, x0, mu)
+        assert i is not None
+        ids.append(i)
+        refs.append((r["task"], p, x0, mu))
+    assert batch.stats()["live"] == 256
+    batch.step()
+    torch.cuda.synchronize()
+    picks = set()
+    for name in SV.TASKS:
+        of_task = [k for k, r in enumerate(reqs) if r["task"] == name]
+        picks.add(max(of_task, key=lambda k: reqs[k]["K"]))
+        picks.add(min(of_task, key=lambda k: reqs[k]["K"]))
+    smallest = sorted(picks, key=lambda k: reqs[k]["K"] * reqs[k]["H"])[:2]
+    for k in sorted(picks):
+        name, p, x0, mu = refs[k]
+        model = models[name]
+        bx, bu0, bmu, acc, bstep = batch.read(ids[k], model.nx, p["nk"])
+        assert bstep == 1
+        ctl = B.Controller(model, p)
+        ctl.set_nominal(_dev(mu))
+        ctl.set_step(0)
+        u0 = ctl.step(_dev(x0))
+        nominal = ctl.get_nominal().cpu().numpy()
+        x1 = model.sim_step(_dev(x0[None]), u0[None].contiguous(), p["kp"], p["kd"], p["dt"]).cpu().numpy()[0]
+        box = SV.TASKS[name]["workload"]["scene"] == W.SCENE_FREE_BOX
+        assert np.abs(bu0 - u0.cpu().numpy()).max() <= 1e-5, (name, p["K"], p["H"])
+        assert np.abs(bmu - nominal).max() <= 1e-5, (name, p["K"], p["H"])
+        assert step_error(bx.astype(np.float64), x1.astype(np.float64), box=box).max() <= STEP_TOL, name
+        if k in smallest:
+            orc = O.Oracle(mds[name])
+            ou0, omu, _, _ = orc.mppi_step(p, 0, x0, mu)
+            assert np.abs(bu0 - ou0).max() <= KNOT_TOL, (name, p["K"], p["H"])
+            assert np.abs(bmu - omu).max() <= KNOT_TOL, (name, p["K"], p["H"])

@@ -105,6 +105,24 @@ def test_gradient_matches_oracle(B, Bsz, gather):
     assert G @ Ge / (np.linalg.norm(G) * np.linalg.norm(Ge)) >= 0.999
 
 
+def test_gradient_with_batch_splits_matches_oracle(B):
+    """Batch 1024 (gathered rows): the weight gradients reduce 8 batch splits and the bias
+    gradients 16 to 32 per-tile column partials, as in the training launches."""
+    pol = B.Policy(max_batch=1024, seed=31)
+    P = _params(pol)
+    rng = np.random.default_rng(77)
+    N, Bsz = 1500, 1024
+    Xall = rng.normal(size=(N, 40)).astype(np.float32)
+    Yall = rng.normal(size=(N, 72)).astype(np.float32)
+    idx = rng.permutation(N)[:Bsz].astype(np.int32)
+    loss, G = pol.grad(_dev(Xall), _dev(Yall), _dev(idx, np.int32), B=Bsz)
+    G = G.cpu().numpy().astype(np.float64)
+    Lb, Gb = O.mlp_grad(P, f32(Xall[idx]), f32(Yall[idx]), bf16=True)
+    assert abs(float(loss.item()) - Lb) <= 1e-3 * abs(Lb)
+    for sl in _layer_slices():
+        assert _rel(G[sl], Gb[sl]) <= 1e-2, (sl, _rel(G[sl], Gb[sl]))
+
+
 def test_gradient_is_deterministic(B):
     pol = B.Policy(max_batch=256, seed=2)
     rng = np.random.default_rng(0)
