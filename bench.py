@@ -68,16 +68,21 @@ def counter_flops_from_profile(workload: str, arith: str):
     return d.get("counter_flops_per_launch")
 
 
-def cpu_baseline(workload, seed, seconds):
-    import numpy as np
-    from oracle import oracle as O
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(orc, workload, p, seed, seconds, threads):
+    """Closed-loop control steps of the oracle for about `seconds`: rollout-steps/s, steps."""
     from paper_2409_10469_amd import workloads as W
-    md = W.model_dict(workload, seed)
-    p = W.params_dict(workload, seed)
-    orc = O.Oracle(md)
     x = W.initial_state(seed, workload["scene"])
     mu = W.stance_knots(p["nk"])
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     steps, t0 = 0, time.perf_counter()
     while True:
         u0, mu, _, _ = orc.mppi_step(p, steps, x, mu, nthreads=threads)
@@ -86,10 +91,30 @@ def cpu_baseline(workload, seed, seconds):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    rs = steps * p["K"] * p["H"]
-    return {"value": rs / el, "unit": "rollout-steps/s", "cores": threads, "kind": "oracle",
+    return steps * p["K"] * p["H"] / el, steps, el
+
+
+def cpu_baseline(workload, seed, seconds):
+    """The FP64 oracle on this host: all cores (OpenMP over samples) for `seconds`, one
+    thread for a third of that; the paper's CPU rate is quoted beside it as context."""
+    from oracle import oracle as O
+    from paper_2409_10469_amd import workloads as W
+    md = W.model_dict(workload, seed)
+    p = W.params_dict(workload, seed)
+    orc = O.Oracle(md)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    rate, steps, el = _oracle_rate(orc, workload, p, seed, seconds, threads)
+    rate1, steps1, el1 = _oracle_rate(orc, workload, p, seed, seconds / 3, 1)
+    return {"value": rate, "unit": "rollout-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} closed-loop control steps of {workload['name']} (K={p['K']}, H={p['H']}) "
-                      f"in {el:.1f} s, FP64 oracle, OpenMP over samples"}
+                      f"in {el:.1f} s, FP64 oracle, OpenMP over samples",
+            "single_thread": {"value": rate1, "unit": "rollout-steps/s",
+                              "sample": f"{steps1} control steps in {el1:.1f} s on one thread"},
+            "ms_per_update": el / steps * 1e3, "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "paper_reference": {"value": 1.2e5, "unit": "rollout-steps/s",
+                                "derived_from": "100 Hz control with 30 samples x 40 steps (Sec. IV-A), a lower bound",
+                                "hardware": "Intel i9-12900KS, multi-threaded MuJoCo rollouts",
+                                "note": "different simulator and contact model; context, not a target"}}
 
 
 def main():
