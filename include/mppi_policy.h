@@ -77,13 +77,15 @@ mppi_status mppi_policy_set_params(mppi_policy *pol, const float *d_params);
 mppi_status mppi_policy_forward(mppi_policy *pol, const float *d_in, int B, float *d_out);
 /* Loss and gradient over the B rows d_index[0..B) (or rows 0..B-1 if d_index is NULL)
  * of d_in (x 40) and d_target (x 72): d_grad receives n_params floats in the parameter
- * layout, d_loss one float (either may be NULL). */
+ * layout, d_loss one float (either may be NULL).  Every index must be a row that d_in
+ * and d_target hold: the indices are device data the library does not read on the host,
+ * and an index outside the caller's rows makes the kernels read outside those buffers. */
 mppi_status mppi_policy_grad(mppi_policy *pol, const float *d_in, const float *d_target, const int *d_index, int B,
                              float *d_grad, float *d_loss);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; Kingma and Ba) with
  * the given gradient (n_params floats, device) and learning rate. */
 mppi_status mppi_policy_adam(mppi_policy *pol, const float *d_grad, float lr);
-/* mppi_policy_grad followed by mppi_policy_adam on its gradient. */
+/* mppi_policy_grad followed by mppi_policy_adam on its gradient (same index rule). */
 mppi_status mppi_policy_train_step(mppi_policy *pol, const float *d_in, const float *d_target, const int *d_index,
                                    int B, float lr, float *d_loss);
 /* Adam steps taken so far. */

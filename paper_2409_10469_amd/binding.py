@@ -382,6 +382,8 @@ class Policy:
         return out
 
     def grad(self, X, Y, index=None, B=None):
+        """Loss and gradient over rows index[:B] of X and Y (int32 device indices, each a
+        valid row; they are not checked on the host) or the first B rows."""
         import torch
         assert index is None or index.dtype == torch.int32
         B = int(B if B is not None else (index.shape[0] if index is not None else X.shape[0]))
@@ -394,6 +396,7 @@ class Policy:
         self._s(lib().mppi_policy_adam(self.h, _ptr(G), float(lr)))
 
     def train_step(self, X, Y, index=None, B=None, lr=1e-3, loss=None):
+        """Gradient then Adam over rows index[:B] of X and Y (as grad)."""
         import torch
         assert index is None or index.dtype == torch.int32
         B = int(B if B is not None else (index.shape[0] if index is not None else X.shape[0]))
