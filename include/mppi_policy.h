@@ -143,7 +143,9 @@ mppi_status mppi_proposal_stats(mppi_ctx *ctx, int *accepted, int *steps);
  * here.  Every proposal instance of a batch shares one policy, whose max_batch must
  * cover their number; its kernels run on the batch's stream, and it must not be used on
  * another stream while steps are queued.  pol NULL returns the instance to plain
- * sampling.  Requires a 37-float state model and K >= 2.  Does not launch work. */
+ * sampling.  Requires a 37-float state model and K >= 2.  Launches no kernel; the first
+ * call copies the head's resampling table into the batch workspace and synchronises the
+ * batch stream. */
 mppi_status mppi_batch_set_proposal(mppi_batch *b, int id, mppi_policy *pol, const float *cmd,
                                     const float *origin_xy);
 

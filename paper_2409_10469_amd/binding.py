@@ -495,6 +495,7 @@ class Batch:
     def remove(self, i):
         self._chk(self.L.mppi_batch_remove(self.h, int(i)))
         getattr(self, "_records", {}).pop(i, None)
+        getattr(self, "_policies", {}).pop(i, None)
 
     def step(self):
         self._chk(self.L.mppi_batch_step(self.h))
