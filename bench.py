@@ -48,6 +48,15 @@ def traffic_from_profile(workload: str, arith: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def hbm_rate(bytes_per_launch, kernel_ms):
+    """HBM bytes of the rollout launch (counters, copy-calibrated) over its live duration."""
+    if bytes_per_launch is None:
+        return None
+    gbs = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    return {"achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+            "bytes_per_launch": bytes_per_launch}
+
+
 def counter_rate(flops_per_launch, kernel_ms, peak):
     if flops_per_launch is None:
         return None
@@ -254,6 +263,7 @@ def main():
                      "traffic": traffic_from_profile(wl["name"], args.arith),
                      "flops_per_rollout_step": flops_per_rollout_step(wl["scene"], nk)},
         "counter_flops": counter_rate(counter_flops_from_profile(wl["name"], args.arith), roll_ms.mean(), peak),
+        "hbm_gbs": hbm_rate(traffic_from_profile(wl["name"], args.arith), roll_ms.mean()),
         "final_state_finite": bool(np.isfinite(xf).all()),
         "update_status": int(status),
     }
