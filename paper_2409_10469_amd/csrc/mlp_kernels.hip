@@ -56,7 +56,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     float* sC = reinterpret_cast<float*>(smem);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    // M-tiles vary fastest: workgroups go round-robin to the 8 XCDs, so the N-tiles of one
+    // row panel of A share an XCD and its L2 (A is the large operand; B is re-read per XCD)
+    const int mt = blockIdx.x, m0 = mt * BM, n0 = blockIdx.y * BN;
     const size_t kb = (size_t)blockIdx.z * g.K;
     const __bf16* A = g.A + (size_t)m0 * g.lda + kb;
     const __bf16* B = g.B + (size_t)n0 * g.ldb + kb;
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
         }
         __syncthreads();
         for (int c = tid; c < BN; c += 256)
-            g.colpart[(size_t)blockIdx.y * g.N + n0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+            g.colpart[(size_t)mt * g.N + n0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
     }
 }
 
@@ -260,7 +262,7 @@ int gemm_tile_m(int M, int N, int splits)
 template <int BM, int BN>
 static void launch_tile(int epi, const GemmArgs& g, int splits, hipStream_t st)
 {
-    const dim3 grid(g.N / BN, g.M / BM, splits);
+    const dim3 grid(g.M / BM, g.N / BN, splits);
     switch (epi) {
     case EPI_HIDDEN: hipLaunchKernelGGL((gemm_kernel<BM, BN, EPI_HIDDEN>), grid, dim3(256), 0, st, g); break;
     case EPI_OUT: hipLaunchKernelGGL((gemm_kernel<BM, BN, EPI_OUT>), grid, dim3(256), 0, st, g); break;
