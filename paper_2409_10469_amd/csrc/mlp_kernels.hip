@@ -241,24 +241,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     }
 }
 
-// Tile choice: the largest tile that still gives at least 1024 workgroups (4 per CU).
-// One 256-thread workgroup per CU leaves a single wave per SIMD and too few memory
-// requests in flight for the epilogue's output stream; at batch 4096 every product here
-// takes 64 x 64 tiles (measured: 163 us per training step against 186 us with 128 x 64).
-constexpr long kMinBlocks = 1024;
-static bool use_wide(int M, int N, int splits)
-{
-    return M % 128 == 0 && N % 128 == 0 && (long)(M / 128) * (N / 128) * splits >= kMinBlocks;
-}
-
-int gemm_tile_m(int M, int N, int splits)
-{
-    if (M <= 0 || N <= 0 || M % 64 || N % 64) return 0;
-    if (use_wide(M, N, splits)) return 128;
-    if (M % 128 == 0 && (long)(M / 128) * (N / 64) * splits >= kMinBlocks) return 128;
-    return 64;
-}
-
 template <int BM, int BN>
 static void launch_tile(int epi, const GemmArgs& g, int splits, hipStream_t st)
 {

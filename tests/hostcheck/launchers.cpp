@@ -1,0 +1,329 @@
+// Stand-ins of the kernel launchers for the host range check: each checks, against the
+// buffers the driver registered, every address range its kernel reads or writes, derived
+// from the launch arguments the way the kernel derives them.  The batch launcher records
+// its arguments so that a graph launch re-checks the per-tile accesses on the current
+// instance table.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "hip/hip_runtime.h"
+#include "mlp_launch.h"
+#include "mppi_device.h"
+#include "mppi_launch.h"
+#include "proposal_launch.h"
+
+struct Region {
+    const char* base;
+    size_t bytes;
+};
+static std::vector<Region> g_regions;
+int g_bad = 0;
+int g_batch_tiles = 0, g_prop_rows = 0;
+
+void range_register(const void* p, size_t bytes) { g_regions.push_back({(const char*)p, bytes}); }
+
+bool range_check(const void* p, size_t bytes, const char* what)
+{
+    for (const Region& r : g_regions)
+        if ((const char*)p >= r.base && (const char*)p + bytes <= r.base + r.bytes) return true;
+    std::printf("  OUT OF RANGE %s: %p + %zu\n", what, p, bytes);
+    ++g_bad;
+    return false;
+}
+#define CHK(p, n, what) \
+    do {                \
+        if (p) range_check(p, n, what); \
+    } while (0)
+
+static void fail(const char* what)
+{
+    std::printf("  INCONSISTENT %s\n", what);
+    ++g_bad;
+}
+
+// elements e[n * sn + d * sd] for n < K, d < D
+static size_t strided_span(int K, int D, int sn, int sd) { return (size_t)(K - 1) * sn + (size_t)(D - 1) * sd + 1; }
+
+namespace mppi {
+hipError_t launch_sample(const DevParams& P, int D, float* eps, uint32_t* raw, hipStream_t)
+{
+    CHK(eps, 4ull * P.K * D, "sample noise");
+    CHK(raw, 4ull * P.K * 4 * ((D + 3) / 4), "sample words");
+    return hipSuccess;
+}
+
+template <typename R>
+static void check_model_hf(const ModelT<R>& M, const float* hf, const char* what)
+{
+    if (M.scene == 1) range_check(hf, 4ull * M.hf_nx * M.hf_ny, what);
+}
+
+hipError_t launch_rollout(const DevModelF& Mf, const DevModelD& Md, int arith, const DevParams& P, const RolloutArgs& a,
+                          hipStream_t)
+{
+    const int D = 12 * P.nk;
+    if (P.K < 1 || P.H < 1 || P.nk < 2 || P.nk > kMaxKnots) fail("rollout shape");
+    range_check(a.B, 8ull * P.H * P.nk, "rollout basis");
+    range_check(a.mu, 4ull * D, "rollout nominal");
+    range_check(a.x0, 4ull * P.nx, "rollout state");
+    range_check(a.costs, 4ull * P.K, "rollout costs");
+    if (a.eps_in) range_check(a.eps_in, 4 * strided_span(P.K, D, a.eps_sn, a.eps_sd), "rollout given noise");
+    CHK(a.eps_out, 4ull * D * P.K, "rollout noise out");
+    CHK(a.traj, 4ull * P.K * (P.H + 1) * P.nx, "rollout trajectories");
+    if (arith == 1) check_model_hf(Mf, a.hf, "rollout heightfield");
+    else check_model_hf(Md, a.hf, "rollout heightfield");
+    return hipSuccess;
+}
+
+hipError_t launch_update(const DevParams& P, const UpdateArgs& a, hipStream_t)
+{
+    const int D = 12 * P.nk;
+    range_check(a.costs, 4ull * P.K, "update costs");
+    range_check(a.mu, 4ull * D, "update nominal");
+    range_check(a.S, 4ull * P.nk * P.nk, "update shift");
+    range_check(a.eps, 4 * strided_span(P.K, D, a.eps_sn, a.eps_sd), "update noise");
+    CHK(a.knots_out, 4ull * D, "update knots");
+    CHK(a.nominal_out, 4ull * D, "update shifted nominal");
+    CHK(a.u0_out, 48, "update first control");
+    CHK(a.weights_out, 4ull * P.K, "update weights");
+    range_check(a.status, 4, "update status");
+    return hipSuccess;
+}
+
+hipError_t launch_sim_step(const DevModelF& Mf, const DevModelD& Md, int arith, int n, int nx, const float* x,
+                           const float* u, float, float, float, float* xo, float* tau, const float* hf, hipStream_t)
+{
+    range_check(x, 4ull * n * nx, "plant state");
+    range_check(u, 48ull * n, "plant targets");
+    range_check(xo, 4ull * n * nx, "plant next state");
+    CHK(tau, 48ull * n, "plant torques");
+    if (arith == 1) check_model_hf(Mf, hf, "plant heightfield");
+    else check_model_hf(Md, hf, "plant heightfield");
+    return hipSuccess;
+}
+
+// what one persistent batch kernel touches for each tile of its scene's queue
+static void check_batch(int scene, const BatchArgs<double>& a)
+{
+    const int total = *a.total_tiles;
+    for (int t = 0; t < total; ++t) {
+        range_check(a.tile_map + t, 4, "tile map");
+        const int row = a.tile_map[t];
+        range_check(a.inst + row, sizeof(InstDesc), "instance row");
+        const InstDesc& I = a.inst[row];
+        const int K = I.P.K, D = 12 * I.P.nk, nx = I.P.nx;
+        if (I.scene != scene) fail("tile of another scene");
+        const int n0 = (t - I.tile0) * kTileSamples, n1 = std::min(K, n0 + kTileSamples);
+        if (n0 < 0 || n0 >= K) fail("tile outside its instance");
+        range_check(I.B, 8ull * I.P.H * I.P.nk, "batch basis");
+        range_check(I.S, 4ull * I.P.nk * I.P.nk, "batch shift");
+        range_check(I.x, 4ull * nx, "batch state");
+        range_check(I.mu, 4ull * D, "batch nominal");
+        for (int d = 0; d < D; ++d) range_check(I.eps + (size_t)d * K + n0, 4ull * (n1 - n0), "batch noise tile");
+        range_check(I.costs + n0, 4ull * (n1 - n0), "batch costs tile");
+        range_check(I.w, 4ull * K, "batch weights");
+        range_check(I.u0, 48, "batch first control");
+        range_check(I.cost_acc, 4, "batch running cost");
+        range_check(I.done, 4, "batch tile counter");
+        range_check(I.step, 4, "batch step counter");
+        CHK(I.rec, 4ull * I.rec_cap * (nx + D), "batch record rows");
+        if (I.hf_cells) range_check(I.hf, 4ull * I.hf_cells, "batch heightfield");
+        if (I.explicit_eps && I.P.sigma != 1.f) fail("given-noise row without unit scale");
+        ++g_batch_tiles;
+    }
+}
+
+struct Captured {
+    int scene;
+    BatchArgs<double> a;
+};
+static std::vector<Captured> g_captured;
+
+hipError_t launch_batch(int, int scene, const void* args, int grid, size_t lds, hipStream_t)
+{
+    if (grid < 1 || lds > 65536) fail("batch launch shape");
+    g_captured.push_back({scene, *static_cast<const BatchArgs<double>*>(args)});  // same layout for both types
+    return hipSuccess;
+}
+}  // namespace mppi
+
+void capture_begin() { mppi::g_captured.clear(); }
+void capture_replay()
+{
+    for (const auto& c : mppi::g_captured) mppi::check_batch(c.scene, c.a);
+}
+
+namespace prop {
+hipError_t launch_proposal_noise(int Kp, int D, float* e, const float* center, const float* sd, const float* nominal,
+                                 hipStream_t)
+{
+    range_check(e, 4ull * Kp * D, "proposal noise");
+    range_check(center, 4ull * D, "proposal centre");
+    range_check(sd, 4ull * D, "proposal std");
+    range_check(nominal, 4ull * D, "proposal nominal");
+    return hipSuccess;
+}
+
+hipError_t launch_features(const float* x, const float* co, float* f, hipStream_t)
+{
+    range_check(x, 4 * 37, "features state");
+    range_check(co, 4 * 5, "features command");
+    range_check(f, 4 * 40, "features");
+    return hipSuccess;
+}
+
+hipError_t launch_batch_features(int np, const mppi::InstDesc* table, const BatchPropRow* rows, float* feat,
+                                 hipStream_t)
+{
+    range_check(rows, sizeof(BatchPropRow) * np, "proposal rows");
+    range_check(feat, 160ull * np, "batch features");
+    for (int r = 0; r < np; ++r) {
+        range_check(table + rows[r].row, sizeof(mppi::InstDesc), "proposal table row");
+        range_check(table[rows[r].row].x, 4 * 37, "proposal state");
+        if (table[rows[r].row].P.nx != 37) fail("proposal state of another size");
+    }
+    g_prop_rows += np;
+    return hipSuccess;
+}
+
+hipError_t launch_batch_head_noise(int np, const mppi::InstDesc* table, const BatchPropRow* rows, const float* out,
+                                   const float* omean, const float* ostd, const float* rtab, float, hipStream_t)
+{
+    range_check(out, 576ull * np, "proposal network outputs");
+    range_check(omean, 4 * 72, "output mean");
+    range_check(ostd, 4 * 72, "output std");
+    for (int r = 0; r < np; ++r) {
+        const BatchPropRow& pr = rows[r];
+        const mppi::InstDesc& I = table[pr.row];
+        const int nk = pr.nk, D = 12 * nk, K = I.P.K;
+        if (nk != I.P.nk || nk < 2 || nk > 8) fail("proposal knots");
+        for (int i = 0; i < nk; ++i) range_check(rtab + (size_t)(nk * 8 + i) * 6, 24, "resampling row");
+        range_check(I.step, 4, "proposal step counter");
+        for (int cb = 0; cb < (D + 3) / 4; ++cb)
+            for (int q = 0; q < 4; ++q) {
+                const int d = 4 * cb + q;
+                if (d < D) range_check(I.eps + (size_t)d * K, 4ull * K, "proposal noise row");
+            }
+        range_check(I.mu, 4ull * D, "proposal nominal");
+        if (!I.explicit_eps || I.P.sigma != 1.f) fail("proposal row flags");
+        if (!std::isfinite(pr.log_hi)) fail("proposal std clamp");
+    }
+    return hipSuccess;
+}
+}  // namespace prop
+
+namespace mlp {
+static size_t span(long rows, long ld, long cols, size_t esz) { return ((rows - 1) * ld + cols) * esz; }
+
+hipError_t launch_gemm(int epi, const GemmArgs& g, int splits, hipStream_t)
+{
+    const int bm = gemm_tile_m(g.M, g.N, splits);
+    if (!bm || g.K % kGemmBK || splits < 1) {
+        fail("gemm shape");
+        return hipErrorInvalidValue;
+    }
+    range_check(g.A, span(g.M, g.lda, (long)g.K * splits, 2), "gemm A");
+    range_check(g.B, span(g.N, g.ldb, (long)g.K * splits, 2), "gemm B");
+    if (epi == EPI_SPLITK)
+        range_check(g.C, (size_t)(splits - 1) * g.c_split_stride * 4 + span(g.M, g.ldc, g.N, 4), "gemm partials");
+    if (epi == EPI_OUT) {
+        range_check(g.C, span(g.m_store, g.ldc, g.n_store, 4), "gemm output");
+        range_check(g.bias, 4ull * g.n_store, "gemm bias");
+    }
+    if (epi == EPI_HIDDEN) {
+        CHK(g.C, span(g.M, g.ldc, g.N, 4), "gemm pre-activation");
+        range_check(g.H, span(g.M, g.ldh, g.N, 2), "gemm activation");
+        CHK(g.Ht, span(g.N, g.ldht, g.M, 2), "gemm transposed activation");
+        range_check(g.bias, 4ull * g.N, "gemm bias");
+    }
+    if (epi == EPI_DACT) {
+        range_check(g.Zp, span(g.M, g.ldz, g.N, 4), "gemm stored pre-activation");
+        range_check(g.H, span(g.M, g.ldh, g.N, 2), "gemm error");
+        range_check(g.Ht, span(g.N, g.ldht, g.M, 2), "gemm transposed error");
+        range_check(g.colpart, (size_t)(g.M / bm) * g.N * 4, "gemm column partials");
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_prep(const PrepArgs& a, hipStream_t)
+{
+    if (!a.idx) range_check(a.X, 160ull * a.B, "input rows");
+    range_check(a.X0, 2ull * a.Bp * kInPad, "padded input");
+    range_check(a.X0t, 2ull * a.Bp * kInPad, "transposed input");
+    range_check(a.mean, 160, "input mean");
+    range_check(a.std, 160, "input std");
+    return hipSuccess;
+}
+
+int loss_rows_per_block() { return 32; }
+
+hipError_t launch_loss(const LossArgs& a, hipStream_t)
+{
+    if (a.Bp % 32) fail("loss rows");
+    range_check(a.out, 4ull * a.B * kOut, "loss outputs");
+    if (!a.idx) range_check(a.Y, 288ull * a.B, "loss targets");
+    range_check(a.dZ, 2ull * a.Bp * kOutPad, "loss error");
+    range_check(a.dZt, 2ull * kOutPad * a.Bp, "loss transposed error");
+    range_check(a.dbpart, 4ull * (a.Bp / 32) * kOutPad, "loss column partials");
+    range_check(a.lpart, 4ull * (a.Bp / 32), "loss partials");
+    return hipSuccess;
+}
+
+static void check_reduce(const ReduceArgs& a)
+{
+    for (int l = 0; l < kLayers; ++l) {
+        if (a.S[l] < 1 || a.S[l] > kMaxSplits) fail("split count");
+        range_check(a.wpart[l], 4ull * a.S[l] * a.g.fip[l] * a.g.fop[l], "weight partials");
+        range_check(a.bpart[l], 4ull * a.T[l] * a.g.fop[l], "bias partials");
+    }
+    range_check(a.lpart, 4ull * a.nl, "loss partials");
+    CHK(a.loss, 4, "loss");
+}
+
+static void check_adam(const AdamArgs& a, bool reads_gradient)
+{
+    const size_t n = a.g.off[kLayers];
+    range_check(a.P, 4 * n, "parameters");
+    if (a.update) {
+        range_check(a.m, 4 * n, "first moments");
+        range_check(a.v, 4 * n, "second moments");
+        if (reads_gradient) range_check(a.G, 4 * n, "gradient");
+    }
+    for (int l = 0; l < kLayers; ++l) {
+        range_check(a.Wt[l], 2ull * a.g.fop[l] * a.g.fip[l], "transposed weight copy");
+        CHK(a.Wn[l], 2ull * a.g.fip[l] * a.g.fop[l], "weight copy");
+    }
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t)
+{
+    check_reduce(a);
+    range_check(a.G, 4ull * a.g.off[kLayers], "gradient");
+    return hipSuccess;
+}
+
+hipError_t launch_adam(const AdamArgs& a, hipStream_t)
+{
+    check_adam(a, true);
+    return hipSuccess;
+}
+
+hipError_t launch_reduce_adam(const ReduceArgs& r, const AdamArgs& a, hipStream_t)
+{
+    check_reduce(r);
+    check_adam(a, false);
+    return hipSuccess;
+}
+
+hipError_t launch_head(const HeadArgs& a, hipStream_t)
+{
+    range_check(a.out, 4 * kOut, "head outputs");
+    range_check(a.omean, 4 * 72, "head mean");
+    range_check(a.ostd, 4 * 72, "head std");
+    range_check(a.center, 48ull * a.nk, "head centre");
+    range_check(a.sd, 48ull * a.nk, "head std out");
+    return hipSuccess;
+}
+}  // namespace mlp
