@@ -392,3 +392,31 @@ def test_rollout_costs_10_steps_lower_order_bases(B, basis):
     want = orc.rollout_batch(p, x0, mu, eps)
     rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6)
     assert rel.max() <= COST_TOL, (rel.max(), int(rel.argmax()))
+
+
+def test_closed_loop_resumes_bitwise_from_nominal_and_step(B):
+    """The controller's state is the nominal plan and the Philox step counter: a fresh
+    controller given both at step 5 continues the closed loop bit for bit."""
+    md, p, orc, model, ctl = _setup(B, W.TERRAIN_WALK, K=128, H=30)
+    x = _dev(W.initial_state(4, W.SCENE_HEIGHTFIELD))
+    ctl.set_nominal(_dev(W.stance_knots(p["nk"])))
+    ctl.set_step(0)
+    states, controls = [], []
+    saved = None
+    for s in range(10):
+        if s == 5:
+            saved = (x.clone(), ctl.get_nominal().clone(), ctl.step_counter)
+        u0 = ctl.step(x)
+        x = model.sim_step(x[None], u0[None].contiguous(), p["kp"], p["kd"], p["dt"])[0]
+        states.append(x.cpu().numpy())
+        controls.append(u0.cpu().numpy())
+    x, nominal, step = saved
+    assert step == 5
+    ctl2 = B.Controller(model, p)
+    ctl2.set_nominal(nominal)
+    ctl2.set_step(step)
+    for s in range(5, 10):
+        u0 = ctl2.step(x)
+        x = model.sim_step(x[None], u0[None].contiguous(), p["kp"], p["kd"], p["dt"])[0]
+        assert np.array_equal(u0.cpu().numpy(), controls[s]), s
+        assert np.array_equal(x.cpu().numpy(), states[s]), s

@@ -398,3 +398,27 @@ def test_trained_proposal_gains_over_plain_and_untrained_at_equal_samples(B):
     c = evb["controllers"]
     assert c["learned_K256"]["episode_cost"] < 0.8 * c["plain_K256"]["episode_cost"], c
     assert c["learned_K256"]["latency_ms"]["p99"] < c["plain_K1024"]["latency_ms"]["p99"], c
+
+
+def test_corrupted_proposal_falls_back_to_the_plain_step(B):
+    """A non-finite proposal centre fails the cost gate: the step is the plain step, bit
+    for bit, and the acceptance counter does not move."""
+    md, p, orc, ctl = _ctl(B, K=64, H=10)
+    D = 12 * p["nk"]
+    x0 = f32(W.initial_state(5))
+    mu = f32(W.stance_knots(p["nk"]))
+    center = mu.copy()
+    center[3] = np.nan
+    sd = np.full(D, 0.1, np.float32)
+    ctl.set_nominal(_dev(mu))
+    ctl.set_step(2)
+    u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), 16, gate="cost").cpu().numpy()
+    nominal = ctl.get_nominal().cpu().numpy()
+    acc, steps = ctl.proposal_stats()
+    assert (acc, steps) == (0, 1)
+    ref = B.Controller(B.Model(md), p)
+    ref.set_nominal(_dev(mu))
+    ref.set_step(2)
+    assert np.array_equal(u0, ref.step(_dev(x0)).cpu().numpy())
+    assert np.array_equal(nominal, ref.get_nominal().cpu().numpy())
+    assert ctl.step_counter == ref.step_counter == 3
