@@ -195,7 +195,7 @@ def main():
         x[0].copy_(x0s[e])
         cur["i"] = 0
 
-    def control_step(ev=None):
+    def control_step(ev=None, weights=None):
         i, ctl = cur["i"], cur["ctl"]
         xi, xo = x[i % 2], x[(i + 1) % 2]
         if ev:
@@ -203,7 +203,7 @@ def main():
         ctl.rollout_batch(xi, costs=costs)
         if ev:
             ev[1].record(stream)
-        ctl.update_shift(costs, u0)
+        ctl.update_shift(costs, u0, weights=weights)
         model.sim_step_into(xi.view(1, -1), u0.view(1, -1), p["kp"], p["kd"], p["dt"], xo.view(1, -1),
                             arith=args.arith)
         if ev:
@@ -222,17 +222,20 @@ def main():
         control_step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    wbuf = torch.empty((args.steps, K), dtype=torch.float32, device="cuda")  # each step's Eq. 1 weights
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         if k % args.episode_steps == 0:
             start_episode(k // args.episode_steps)
-        control_step(evs[k])
+        control_step(evs[k], wbuf[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
     roll_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     status = max(c.sync_status() for c in ctls)
+    w64 = wbuf.double()
+    ess = (w64.sum(1) ** 2 / (w64 ** 2).sum(1)).cpu().numpy()  # effective sample size per step
     xf = x[cur["i"] % 2].cpu().numpy()
 
     value = K * H * args.steps / elapsed
@@ -264,6 +267,8 @@ def main():
                      "flops_per_rollout_step": flops_per_rollout_step(wl["scene"], nk)},
         "counter_flops": counter_rate(counter_flops_from_profile(wl["name"], args.arith), roll_ms.mean(), peak),
         "hbm_gbs": hbm_rate(traffic_from_profile(wl["name"], args.arith), roll_ms.mean()),
+        "ess": {"mean": float(np.mean(ess)), "median": float(np.median(ess)), "min": float(np.min(ess)),
+                "of_K": K},
         "final_state_finite": bool(np.isfinite(xf).all()),
         "update_status": int(status),
     }
