@@ -106,6 +106,48 @@ int  orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t st
                             const double *center, const double *sd, int Kp, int gate, double *u0, double *costs_p,
                             double *costs, int *accepted, int nthreads);
 
+/* Eq. 3 / Eq. 4 tracking cost with a trotting gait reference (tracking_oracle.c).
+   The state error is e = [p - p_ref(t) (3), attitude (3), q - u_ref(t) (12),
+   v_w - (v_cmd, 0) (3), omega (3), qd (12)], where p_ref(t) = p_ref0 + (v_cmd t, 0) and the
+   attitude error is 2 sgn(qw) (qx, qy, qz) against upright with zero yaw. */
+typedef struct orc_tracking {
+    double Q[36];                 /* diagonal state weights on e */
+    double R[12];                 /* diagonal weights on u - u_ref(t) */
+    double p_ref0[3];
+    double v_cmd[2];              /* commanded world xy velocity */
+    double period, duty;          /* gait period (s) and stance fraction */
+    double swing_height;          /* foot lift at mid-swing (m) */
+    double stand_height;          /* hip-to-foot-centre height of the reference (m) */
+    double raibert_k;             /* gain on (v - v_cmd) in the foothold */
+    double box_w;                 /* Q_box of Eq. 4 (free-box scene) */
+    double box_goal[2];
+    int32_t gait;                 /* 0: standing pose at all times, 1: trot */
+    int32_t pad;
+} orc_tracking;
+
+/* leg IK: joint angles (abduction, flexion, knee) that put the foot centre at p (3),
+   given relative to the hip in the trunk frame; the reach is clamped to the leg's range */
+void orc_leg_ik(const orc_model *m, const double *p, double *q);
+/* foot target of leg `leg` relative to its hip at gait time t; v_h: the measured base
+   velocity in the heading frame (2) */
+void orc_gait_foot(const orc_tracking *c, int leg, double t, const double *v_h, const double *cmd_h, double *p);
+/* the joint reference u_ref(t) (12), the Raibert feedback taken from the state x0 */
+void orc_gait_reference(const orc_model *m, const orc_tracking *c, double t, const double *x0, double *u_ref);
+/* one stage term of Eq. 3 (+ Eq. 4): state x at time t_x with joint reference q_ref,
+   control u against u_ref */
+double orc_tracking_stage(const orc_model *m, const orc_tracking *c, double t_x, const double *x,
+                          const double *q_ref, const double *u, const double *u_ref);
+/* cost of a rollout trajectory (H+1 states) under controls u (H x 12) at control step
+   `step`: sum_k dt [stage(x_{k+1}, u_k)], references at t_k = (step + k) dt */
+double orc_tracking_cost(const orc_model *m, const orc_params *p, const orc_tracking *c, uint32_t step,
+                         const double *traj, const double *u);
+/* rollout of one knot vector with the tracking cost (the dynamics of orc_rollout) */
+double orc_rollout_tracking(const orc_model *m, const orc_params *p, const orc_tracking *c, uint32_t step,
+                            const double *x0, const double *theta, double *traj);
+/* Algorithm 1 with the tracking cost */
+int  orc_mppi_step_tracking(const orc_model *m, const orc_params *p, const orc_tracking *c, uint32_t step,
+                            const double *x0, double *mu, double *u0, double *costs, int nthreads);
+
 /* Learned proposal network (mlp_oracle.c). */
 int  orc_mlp_n_params(void);
 void orc_mlp_forward(const double *P, int B, const double *X, double *out, int bf);

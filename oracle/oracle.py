@@ -23,7 +23,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-shared", "-fPIC", "-o", tmp, SRC,
-                               os.path.join(HERE, "mlp_oracle.c"), "-lm"])
+                               os.path.join(HERE, "mlp_oracle.c"), os.path.join(HERE, "tracking_oracle.c"), "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -55,6 +55,31 @@ class Params(C.Structure):
     ]
 
 
+class Tracking(C.Structure):
+    """Eq. 3 / Eq. 4 tracking-cost parameters (orc_tracking)."""
+    _fields_ = [
+        ("Q", C.c_double * 36), ("R", C.c_double * 12), ("p_ref0", C.c_double * 3), ("v_cmd", C.c_double * 2),
+        ("period", C.c_double), ("duty", C.c_double), ("swing_height", C.c_double), ("stand_height", C.c_double),
+        ("raibert_k", C.c_double), ("box_w", C.c_double), ("box_goal", C.c_double * 2),
+        ("gait", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+def tracking(c: dict) -> Tracking:
+    """Build an orc_tracking from a dict with the same keys (arrays for Q, R, p_ref0,
+    v_cmd, box_goal)."""
+    s = Tracking()
+    s.Q[:] = [float(v) for v in c["Q"]]
+    s.R[:] = [float(v) for v in c["R"]]
+    s.p_ref0[:] = [float(v) for v in c["p_ref0"]]
+    s.v_cmd[:] = [float(v) for v in c["v_cmd"]]
+    for key in ("period", "duty", "swing_height", "stand_height", "raibert_k", "box_w"):
+        setattr(s, key, float(c[key]))
+    s.box_goal[:] = [float(v) for v in c.get("box_goal", (0.0, 0.0))]
+    s.gait = int(c["gait"])
+    return s
+
+
 _lib = None
 
 
@@ -66,7 +91,7 @@ def lib():
         L = C.CDLL(LIB)
         dp = C.POINTER(C.c_double)
         u32p = C.POINTER(C.c_uint32)
-        mp, pp = C.POINTER(Model), C.POINTER(Params)
+        mp, pp, tp = C.POINTER(Model), C.POINTER(Params), C.POINTER(Tracking)
         sig = {
             "orc_nx": (C.c_int, [mp]),
             "orc_philox4x32_10": (None, [u32p, u32p, u32p]),
@@ -101,6 +126,13 @@ def lib():
             "orc_mppi_step": (C.c_int, [mp, pp, C.c_uint32, dp, dp, dp, dp, C.c_int]),
             "orc_mppi_step_proposal": (C.c_int, [mp, pp, C.c_uint32, dp, dp, dp, dp, C.c_int, C.c_int, dp, dp, dp,
                                                  C.POINTER(C.c_int), C.c_int]),
+            "orc_leg_ik": (None, [mp, dp, dp]),
+            "orc_gait_foot": (None, [tp, C.c_int, C.c_double, dp, dp, dp]),
+            "orc_gait_reference": (None, [mp, tp, C.c_double, dp, dp]),
+            "orc_tracking_stage": (C.c_double, [mp, tp, C.c_double, dp, dp, dp, dp]),
+            "orc_tracking_cost": (C.c_double, [mp, pp, tp, C.c_uint32, dp, dp]),
+            "orc_rollout_tracking": (C.c_double, [mp, pp, tp, C.c_uint32, dp, dp, dp]),
+            "orc_mppi_step_tracking": (C.c_int, [mp, pp, tp, C.c_uint32, dp, dp, dp, dp, C.c_int]),
             "orc_policy_features": (None, [dp, dp, dp, dp, dp, dp]),
             "orc_policy_head": (None, [dp, dp, dp, C.c_int, C.c_double, dp, dp]),
             "orc_mlp_n_params": (C.c_int, []),
@@ -284,6 +316,47 @@ class Oracle:
                                            _dp(_f64(center, D)), _dp(_f64(sd, D)), int(Kp), int(gate), _dp(u0), _dp(cp),
                                            _dp(cf), C.byref(acc), int(nthreads))
         return u0, mu, cp, cf, bool(acc.value), rc
+
+    # ---- Eq. 3 / Eq. 4 tracking cost -------------------------------------
+    def leg_ik(self, p_hip):
+        q = np.zeros(3)
+        self.L.orc_leg_ik(C.byref(self.m), _dp(_f64(p_hip, 3)), _dp(q))
+        return q
+
+    def gait_reference(self, c: dict, t: float, x0):
+        u = np.zeros(12)
+        self.L.orc_gait_reference(C.byref(self.m), C.byref(tracking(c)), float(t), _dp(_f64(x0, self.nx)), _dp(u))
+        return u
+
+    def tracking_stage(self, c: dict, t_x, x, q_ref, u, u_ref):
+        return self.L.orc_tracking_stage(C.byref(self.m), C.byref(tracking(c)), float(t_x), _dp(_f64(x, self.nx)),
+                                         _dp(_f64(q_ref, 12)), _dp(_f64(u, 12)), _dp(_f64(u_ref, 12)))
+
+    def tracking_cost(self, p: dict, c: dict, step: int, traj, u):
+        """Cost of a trajectory ((H+1) x nx) under controls (H x 12) at control step `step`."""
+        H = p["H"]
+        return self.L.orc_tracking_cost(C.byref(self.m), C.byref(self.params(p)), C.byref(tracking(c)), int(step),
+                                        _dp(_f64(traj, (H + 1) * self.nx)), _dp(_f64(u, 12 * H)))
+
+    def rollout_tracking(self, p: dict, c: dict, step: int, x0, theta, traj=False):
+        tr = np.zeros((p["H"] + 1, self.nx)) if traj else None
+        L = self.L.orc_rollout_tracking(C.byref(self.m), C.byref(self.params(p)), C.byref(tracking(c)), int(step),
+                                        _dp(_f64(x0, self.nx)), _dp(_f64(theta, 12 * p["nk"])), _dp(tr))
+        return (L, tr) if traj else L
+
+    def mppi_step_tracking(self, p: dict, c: dict, step: int, x0, mu, nthreads=0):
+        mu = _f64(mu, 12 * p["nk"]).copy()
+        u0, costs = np.zeros(12), np.zeros(p["K"])
+        rc = self.L.orc_mppi_step_tracking(C.byref(self.m), C.byref(self.params(p)), C.byref(tracking(c)),
+                                           int(step), _dp(_f64(x0, self.nx)), _dp(mu), _dp(u0), _dp(costs),
+                                           int(nthreads))
+        return u0, mu, costs, rc
+
+
+def gait_foot(c: dict, leg: int, t: float, v_h, cmd_h):
+    out = np.zeros(3)
+    lib().orc_gait_foot(C.byref(tracking(c)), int(leg), float(t), _dp(_f64(v_h, 2)), _dp(_f64(cmd_h, 2)), _dp(out))
+    return out
 
 
 # ---- model-free pieces ---------------------------------------------------
