@@ -99,6 +99,7 @@ typedef struct mppi_params {
     uint32_t instance;
     int32_t arith;              /* MPPI_ARITH_FP64 (0, default) or MPPI_ARITH_FP32 */
     int32_t basis;              /* knot interpolation, MPPI_BASIS_* (0: cubic, the default) */
+    int32_t cost;               /* MPPI_COST_RUNNING (0, default) or MPPI_COST_TRACKING */
 } mppi_params;
 
 /* Interpolation of the knots into per-step joint targets (Sec. III-B uses the cubic
@@ -109,6 +110,43 @@ typedef struct mppi_params {
  * All three pass through the knots, so u0 is the first knot; the warm-start shift
  * evaluates the same interpolant one step later. */
 enum { MPPI_BASIS_CUBIC = 0, MPPI_BASIS_LINEAR = 1, MPPI_BASIS_ZERO = 2 };
+
+/* The sample cost.  RUNNING: the weights in mppi_params above, summed inside the rollout.
+ * TRACKING: Eq. 3 (Sec. IV-B) with the gait reference below, plus Eq. 4's l1 box term
+ * (Sec. IV-D) in the free-box scene, evaluated on the rollout trajectories; set its
+ * parameters with mppi_set_tracking_cost before the first rollout.  The workspace then
+ * holds the K x (H+1) x nx trajectories as well. */
+enum { MPPI_COST_RUNNING = 0, MPPI_COST_TRACKING = 1 };
+
+/* Eq. 3 / Eq. 4 cost.  For control step s, rollout step k applies u_k at gait time
+ * t_k = (s + k) dt and reaches x_{k+1} at t_{k+1}; the sample cost is
+ *   L = sum_{k=0}^{H-1} dt [ e(x_{k+1})^T diag(Q) e(x_{k+1})
+ *                            + (u_k - u_ref(t_k))^T diag(R) (u_k - u_ref(t_k))
+ *                            + box_weight |box_goal - box_xy(x_{k+1})|_1 ]   (box: free-box scene)
+ * with the state error e = [p - p_ref(t) (3), 2 sgn(qw) (qx, qy, qz) (3), q - u_ref(t) (12),
+ * v_world - (v_cmd, 0) (3), omega_body (3), qd (12)] and p_ref(t) = p_ref0 + (v_cmd t, 0).
+ * u_ref(t): joint targets of a gait.  gait 0 holds every foot stand_height below its hip.
+ * gait 1 trots: diagonal leg pairs (front-left with rear-right) half a period apart,
+ * stance for the first `duty` of each period.  In the heading frame of the rollout's start
+ * state, a foot lands at cmd T_st / 2 + raibert_gain (v - cmd) from its hip (T_st = duty
+ * period, v the start state's base velocity), sweeps back by cmd T_st during stance, and
+ * returns to the next foothold in swing along (1 - cos(pi s)) / 2 while lifted by
+ * swing_height sin(pi s).  Foot targets become joint targets by closed-form leg inverse
+ * kinematics (reach clamped to [0.05 (l1 + l2) + |l1 - l2|, 0.999 (l1 + l2)]). */
+typedef struct mppi_tracking_cost {
+    float Q[36];                 /* diagonal state weights, >= 0 */
+    float R[12];                 /* diagonal control weights, >= 0 */
+    float p_ref0[3];             /* base position reference at gait time 0 */
+    float v_cmd[2];              /* commanded world xy velocity */
+    float period, duty;          /* gait period (s, > 0) and stance fraction (0 < duty < 1) */
+    float swing_height;          /* foot lift at mid-swing (m, >= 0) */
+    float stand_height;          /* hip-to-foot-centre height of the reference (m, > 0) */
+    float raibert_gain;          /* foothold gain on the velocity error (s) */
+    float box_weight;            /* Q_box of Eq. 4 (free-box scene), >= 0 */
+    float box_goal[2];
+    int32_t gait;                /* 0: stand, 1: trot */
+    int32_t reserved;            /* must be 0 */
+} mppi_tracking_cost;
 
 typedef struct mppi_model mppi_model;
 typedef struct mppi_ctx mppi_ctx;
@@ -152,7 +190,9 @@ mppi_status mppi_sample(mppi_ctx *ctx, float *d_eps, uint32_t *d_raw);
 /* Rolls out all K samples from d_x0 (Algorithm 1 inner loops): spline targets, PD
  * torques, dynamics step, running cost.  d_eps: K x D noise, or NULL to draw it with
  * Philox for the current step (kept in the workspace for mppi_update).  d_costs: K
- * floats (+inf for a diverged sample).  d_traj: optional K x (H+1) x nx states. */
+ * floats (+inf for a diverged sample).  d_traj: optional K x (H+1) x nx states.  With
+ * MPPI_COST_TRACKING the costs are the Eq. 3 / Eq. 4 costs of the trajectories at the
+ * current step counter (ESTATE before mppi_set_tracking_cost). */
 mppi_status mppi_rollout_batch(mppi_ctx *ctx, const float *d_x0, const float *d_eps, float *d_costs,
                                float *d_traj);
 
@@ -174,6 +214,12 @@ mppi_status mppi_step(mppi_ctx *ctx, const float *d_x0, float *d_u0_out);
  * the first control into d_u0_out, shifts the nominal and advances the step counter.
  * mppi_step(ctx, x, u) is exactly rollout_batch(x, NULL, costs) + update_shift(costs, u). */
 mppi_status mppi_update_shift(mppi_ctx *ctx, const float *d_costs, float *d_u0_out, float *d_weights_out);
+
+/* Copies the Eq. 3 / Eq. 4 parameters into the controller (host pointer; nothing is
+ * launched).  EINVAL on a controller created with cost MPPI_COST_RUNNING, non-finite or
+ * negative weights, period <= 0, duty outside (0, 1), stand_height <= 0, an unknown gait
+ * or a non-zero reserved field. */
+mppi_status mppi_set_tracking_cost(mppi_ctx *ctx, const mppi_tracking_cost *cost);
 
 /* Synchronises the bound stream and returns the status of the last update. */
 mppi_status mppi_sync_status(mppi_ctx *ctx);
@@ -216,7 +262,8 @@ mppi_status mppi_batch_add_model(mppi_batch *b, const mppi_model *model, int *sl
 /* admits an instance with HOST initial state x0 (nx) and nominal mu (12 * n_knots);
  * MPPI_EBUDGET if it does not fit in the remaining pool or the table is full
  * (nothing is changed then; the caller may queue the request).  K <= 4096,
- * H <= max_horizon. */
+ * H <= max_horizon; batch instances use the running cost (EINVAL for
+ * MPPI_COST_TRACKING). */
 mppi_status mppi_batch_admit(mppi_batch *b, int model_slot, const mppi_params *params, const float *x0,
                              const float *mu, int *id_out);
 /* releases an instance; its memory is reused only by later stream-ordered admissions */

@@ -114,7 +114,8 @@ const char *mppi_policy_last_error(const mppi_policy *pol);
  * shifted and the step counter advances.  With MPPI_PROPOSAL_GATE_COST the two leading
  * costs are read on the host to choose the branch, so the call synchronises the bound
  * stream; MPPI_PROPOSAL_GATE_NONE always takes the proposal branch (the nominal still
- * competes as sample 1).  2 <= k_prop <= K. */
+ * competes as sample 1).  2 <= k_prop <= K.  The proposal steps use the running cost
+ * (EINVAL for a controller created with MPPI_COST_TRACKING). */
 enum {
     MPPI_PROPOSAL_GATE_COST = 0, /* proposal only if its centre's cost is finite and not above the nominal's */
     MPPI_PROPOSAL_GATE_NONE = 1  /* always the proposal's k_prop samples */
@@ -125,7 +126,7 @@ mppi_status mppi_step_proposal(mppi_ctx *ctx, const float *d_x0, const float *d_
  * command (host cmd[3]) relative to the host origin_xy[2], a forward pass, the head, and
  * mppi_step_proposal with k_prop samples and the given gate.  The policy's kernels then run on ctx's
  * stream; the policy must not be used on another stream meanwhile.  pol NULL switches
- * the proposal off.  Requires a 37-float state model. */
+ * the proposal off.  Requires a 37-float state model and the running cost. */
 mppi_status mppi_set_proposal(mppi_ctx *ctx, mppi_policy *pol, int k_prop, int gate, const float *cmd,
                               const float *origin_xy);
 /* How many proposal steps ran and how many were accepted (host counters). */

@@ -50,7 +50,21 @@ class Params(C.Structure):
         ("v_ref", C.c_float), ("w_torque", C.c_float), ("w_reach", C.c_float), ("w_box", C.c_float),
         ("goal", C.c_float * 2),
         ("seed", C.c_uint64), ("instance", C.c_uint32), ("arith", C.c_int32), ("basis", C.c_int32),
+        ("cost", C.c_int32),
     ]
+
+
+class TrackingCost(C.Structure):
+    """mppi_tracking_cost: Eq. 3 / Eq. 4 weights, references and gait constants."""
+    _fields_ = [
+        ("Q", C.c_float * 36), ("R", C.c_float * 12), ("p_ref0", C.c_float * 3), ("v_cmd", C.c_float * 2),
+        ("period", C.c_float), ("duty", C.c_float), ("swing_height", C.c_float), ("stand_height", C.c_float),
+        ("raibert_gain", C.c_float), ("box_weight", C.c_float), ("box_goal", C.c_float * 2),
+        ("gait", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+COST = {"running": 0, "tracking": 1}
 
 
 _lib = None
@@ -83,6 +97,7 @@ def lib():
             "mppi_step": (C.c_int, [vp, fp, fp]),
             "mppi_update_shift": (C.c_int, [vp, fp, fp, fp]),
             "mppi_sync_status": (C.c_int, [vp]),
+            "mppi_set_tracking_cost": (C.c_int, [vp, C.POINTER(TrackingCost)]),
             "mppi_sim_step": (C.c_int, [vp, C.c_int, C.c_int, fp, fp, C.c_float, C.c_float, C.c_float, fp, fp, fp,
                                         vp]),
             "mppi_status_str": (C.c_char_p, [C.c_int]),
@@ -173,6 +188,23 @@ def params_struct(p: dict) -> Params:
     s.instance = int(p.get("instance", 0))
     s.arith = ARITH[p.get("arith", "fp64")]
     s.basis = int(p.get("basis", 0))  # 0 cubic, 1 linear, 2 zeroth order
+    s.cost = COST[p.get("cost", "running")]
+    return s
+
+
+def tracking_struct(c: dict) -> TrackingCost:
+    """Marshal a tracking-cost dict (keys as in workloads.tracking_cost) into the C struct."""
+    s = TrackingCost()
+    s.Q[:] = [float(v) for v in c["Q"]]
+    s.R[:] = [float(v) for v in c["R"]]
+    s.p_ref0[:] = [float(v) for v in c["p_ref0"]]
+    s.v_cmd[:] = [float(v) for v in c["v_cmd"]]
+    s.period, s.duty = float(c["period"]), float(c["duty"])
+    s.swing_height, s.stand_height = float(c["swing_height"]), float(c["stand_height"])
+    s.raibert_gain, s.box_weight = float(c["raibert_k"]), float(c["box_w"])
+    s.box_goal[:] = [float(v) for v in c.get("box_goal", (0.0, 0.0))]
+    s.gait = int(c["gait"])
+    s.reserved = int(c.get("reserved", 0))
     return s
 
 
@@ -298,6 +330,10 @@ class Controller:
 
     def sync_status(self):
         return self._s(lib().mppi_sync_status(self.h))
+
+    def set_tracking_cost(self, c: dict):
+        """Eq. 3 / Eq. 4 cost parameters (controller created with cost="tracking")."""
+        self._s(lib().mppi_set_tracking_cost(self.h, C.byref(tracking_struct(c))))
 
     def step_proposal(self, x0, center, sd, k_prop, u0=None, gate="cost"):
         """One control step sampling k_prop knots around an explicit proposal (mean, std)."""

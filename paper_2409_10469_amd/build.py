@@ -9,8 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmppi.so")
-SOURCES = ["mppi_kernels.hip", "mlp_kernels.hip", "proposal_kernels.hip", "mppi_api.cpp", "mppi_batch.cpp",
-           "mppi_policy.cpp"]
+SOURCES = ["mppi_kernels.hip", "mlp_kernels.hip", "proposal_kernels.hip", "tracking_kernels.hip", "mppi_api.cpp",
+           "mppi_batch.cpp", "mppi_policy.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

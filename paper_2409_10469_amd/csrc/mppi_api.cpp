@@ -16,6 +16,7 @@
 #include "mppi_launch.h"
 #include "policy_internal.h"
 #include "proposal_launch.h"
+#include "tracking_launch.h"
 
 struct mppi_model {
     mppi_model_desc desc;
@@ -42,6 +43,11 @@ struct mppi_ctx {
     int k_prop = 0, prop_gate = 0;
     float cmd_origin[8] = {};
     int prop_accepted = 0, prop_steps = 0;
+    // Eq. 3 / Eq. 4 tracking cost (p.cost == MPPI_COST_TRACKING): parameters and the
+    // trajectory region the cost kernel reads
+    track::TrackDev track{};
+    bool track_set = false;
+    size_t off_traj = 0;
     std::string err;
 };
 
@@ -330,6 +336,8 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     if ((long)p->K * p->H > (1L << 31)) return fail(nullptr, MPPI_EINVAL, "K * H too large");
     if (p->basis < MPPI_BASIS_CUBIC || p->basis > MPPI_BASIS_ZERO)
         return fail(nullptr, MPPI_EINVAL, "basis must be MPPI_BASIS_CUBIC, _LINEAR or _ZERO");
+    if (p->cost != MPPI_COST_RUNNING && p->cost != MPPI_COST_TRACKING)
+        return fail(nullptr, MPPI_EINVAL, "cost must be MPPI_COST_RUNNING or MPPI_COST_TRACKING");
     mppi_ctx* c = new (std::nothrow) mppi_ctx();
     if (!c) return fail(nullptr, MPPI_ENOMEM, "host allocation failed");
     c->model = *model;
@@ -350,6 +358,10 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     c->off_sd = o; o = align256(o + sizeof(float) * c->D);
     c->off_costs_p = o; o = align256(o + sizeof(float) * p->K);
     c->off_eps_p = o; o = align256(o + sizeof(float) * (size_t)c->D * p->K);
+    if (p->cost == MPPI_COST_TRACKING) {
+        c->off_traj = o;
+        o = align256(o + sizeof(float) * (size_t)p->K * (p->H + 1) * model->nx);
+    }
     c->total = o;
     *out = c;
     return MPPI_OK;
@@ -431,6 +443,9 @@ mppi_status mppi_sample(mppi_ctx* c, float* d_eps, uint32_t* d_raw)
 
 static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, float* d_costs, float* d_traj)
 {
+    const bool tracking = c->p.cost == MPPI_COST_TRACKING;
+    if (tracking && !c->track_set) return fail(c, MPPI_ESTATE, "tracking cost not set (call mppi_set_tracking_cost)");
+    if (tracking && !d_traj) d_traj = wsf(c, c->off_traj);
     const mppi::DevParams P = dev_params(c);
     mppi::RolloutArgs a{};
     a.B = (const double*)wsf(c, c->off_B);
@@ -444,8 +459,28 @@ static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, f
     a.costs = d_costs;
     a.traj = d_traj;
     a.samples_per_block = 16;
-    return hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, P, a, c->stream),
-                     "rollout launch");
+    mppi_status s;
+    if ((s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, P, a, c->stream),
+                       "rollout launch")) ||
+        !tracking)
+        return s;
+    // Eq. 3 / Eq. 4 on the trajectories just written (replaces the running cost)
+    track::TrackArgs t{};
+    t.c = c->track;
+    t.traj = d_traj;
+    t.B = a.B;
+    t.mu = a.mu;
+    if (d_eps) {
+        t.eps = d_eps; t.eps_sn = c->D; t.eps_sd = 1;
+    } else {
+        t.eps = a.eps_out; t.eps_sn = 1; t.eps_sd = c->p.K;
+    }
+    t.sigma = c->p.sigma;
+    t.K = c->p.K; t.H = c->p.H; t.nk = c->p.n_knots; t.nx = c->model.nx;
+    t.dt = c->p.dt;
+    t.step = c->step;
+    t.costs = d_costs;
+    return hip_check(c, track::launch_tracking_cost(c->p.arith, t, c->stream), "tracking cost launch");
 }
 
 mppi_status mppi_rollout_batch(mppi_ctx* c, const float* d_x0, const float* d_eps, float* d_costs, float* d_traj)
@@ -581,6 +616,47 @@ mppi_status mppi_update_shift(mppi_ctx* c, const float* d_costs, float* d_u0_out
     return MPPI_OK;
 }
 
+mppi_status mppi_set_tracking_cost(mppi_ctx* c, const mppi_tracking_cost* t)
+{
+    if (!c || !t) return fail(c, MPPI_EINVAL, "null argument");
+    if (c->p.cost != MPPI_COST_TRACKING) return fail(c, MPPI_EINVAL, "controller created with the running cost");
+    auto nonneg = [](float v) { return std::isfinite(v) && v >= 0.f; };
+    for (float v : t->Q)
+        if (!nonneg(v)) return fail(c, MPPI_EINVAL, "Q must be finite and >= 0");
+    for (float v : t->R)
+        if (!nonneg(v)) return fail(c, MPPI_EINVAL, "R must be finite and >= 0");
+    const float fin[] = {t->p_ref0[0], t->p_ref0[1], t->p_ref0[2], t->v_cmd[0], t->v_cmd[1], t->raibert_gain,
+                         t->box_goal[0], t->box_goal[1]};
+    for (float v : fin)
+        if (!std::isfinite(v)) return fail(c, MPPI_EINVAL, "references and gains must be finite");
+    if (!finite_pos(t->period) || !(t->duty > 0.f && t->duty < 1.f))
+        return fail(c, MPPI_EINVAL, "period must be > 0 and duty in (0, 1)");
+    if (!finite_pos(t->stand_height) || !nonneg(t->swing_height) || !nonneg(t->box_weight))
+        return fail(c, MPPI_EINVAL, "stand_height must be > 0, swing_height and box_weight >= 0");
+    if ((t->gait != 0 && t->gait != 1) || t->reserved != 0)
+        return fail(c, MPPI_EINVAL, "gait must be 0 (stand) or 1 (trot), reserved 0");
+    track::TrackDev& g = c->track;
+    std::memcpy(g.Q, t->Q, sizeof(g.Q));
+    std::memcpy(g.R, t->R, sizeof(g.R));
+    for (int i = 0; i < 3; ++i) g.p_ref0[i] = t->p_ref0[i];
+    g.v_cmd[0] = t->v_cmd[0];
+    g.v_cmd[1] = t->v_cmd[1];
+    g.period = t->period;
+    g.duty = t->duty;
+    g.swing_h = t->swing_height;
+    g.stand_h = t->stand_height;
+    g.raibert_k = t->raibert_gain;
+    g.box_w = t->box_weight;
+    g.box_goal[0] = t->box_goal[0];
+    g.box_goal[1] = t->box_goal[1];
+    g.l1 = c->model.desc.thigh_len;
+    g.l2 = c->model.desc.calf_len;
+    g.gait = t->gait;
+    g.box = c->model.nx == 50;
+    c->track_set = true;
+    return MPPI_OK;
+}
+
 mppi_status mppi_sync_status(mppi_ctx* c)
 {
     mppi_status s;
@@ -601,6 +677,7 @@ mppi_status mppi_step_proposal(mppi_ctx* c, const float* d_x0, const float* d_ce
     if (!d_x0 || !d_center || !d_sd || !d_u0_out) return fail(c, MPPI_EINVAL, "null argument");
     if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
     if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE) return fail(c, MPPI_EINVAL, "unknown gate");
+    if (c->p.cost != MPPI_COST_RUNNING) return fail(c, MPPI_EINVAL, "the proposal step uses the running cost");
     return step_proposal(c, d_x0, d_center, d_sd, k_prop, gate, d_u0_out);
 }
 
@@ -614,6 +691,7 @@ mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, int gat
         return MPPI_OK;
     }
     if (c->model.nx != 37) return fail(c, MPPI_EINVAL, "the proposal needs a 37-float state model");
+    if (c->p.cost != MPPI_COST_RUNNING) return fail(c, MPPI_EINVAL, "the proposal step uses the running cost");
     if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
     if (!cmd || !origin_xy) return fail(c, MPPI_EINVAL, "null command or origin");
     if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE) return fail(c, MPPI_EINVAL, "unknown gate");

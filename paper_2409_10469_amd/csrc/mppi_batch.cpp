@@ -483,6 +483,7 @@ mppi_status mppi_batch_admit(mppi_batch* b, int slot, const mppi_params* p, cons
     if (p->n_knots < 2 || p->n_knots > MPPI_MAX_KNOTS) return bfail(b, MPPI_EINVAL, "n_knots must be in [2, 8]");
     if (!(p->dt > 0.f) || !(p->lambda > 0.f) || !(p->sigma >= 0.f)) return bfail(b, MPPI_EINVAL, "bad dt/lambda/sigma");
     if (p->basis < MPPI_BASIS_CUBIC || p->basis > MPPI_BASIS_ZERO) return bfail(b, MPPI_EINVAL, "unknown basis");
+    if (p->cost != MPPI_COST_RUNNING) return bfail(b, MPPI_EINVAL, "batch instances use the running cost");
     int id = -1;
     for (int i = 0; i < b->max_inst; ++i)
         if (!b->inst[i].live) {

@@ -48,12 +48,54 @@ static mppi_model_desc robot(int scene)
     return d;
 }
 
-static mppi_params params(int K, int H, int nk, int basis = 0, int arith = 0)
+static mppi_params params(int K, int H, int nk, int basis = 0, int arith = 0, int cost = MPPI_COST_RUNNING)
 {
     mppi_params p{};
     p.K = K; p.H = H; p.n_knots = nk; p.dt = 0.02f; p.sigma = 0.3f; p.lambda = 0.1f; p.kp = 40; p.kd = 1;
-    p.basis = basis; p.arith = arith;
+    p.basis = basis; p.arith = arith; p.cost = cost;
     return p;
+}
+
+// a controller with the Eq. 3 / Eq. 4 tracking cost: rollouts with and without caller
+// noise and trajectories, full steps, and the calls it refuses
+static void tracking(mppi_model* m, mppi_policy* pol, int nx, int K, int H, int nk, int arith)
+{
+    mppi_params p = params(K, H, nk, 0, arith, MPPI_COST_TRACKING);
+    mppi_ctx* c = nullptr;
+    if (OK(mppi_create(m, &p, &c)) < 0) return;
+    const size_t n = mppi_workspace_bytes(c);
+    OK(mppi_bind(c, dev(n), n, nullptr));
+    const int D = 12 * nk;
+    float *x = devf(nx), *u0 = devf(12), *costs = devf(K), *eps = devf((size_t)K * D);
+    float *traj = devf((size_t)K * (H + 1) * nx), *center = devf(D), *sd = devf(D);
+    REFUSED(mppi_rollout_batch(c, x, nullptr, costs, nullptr));  // parameters not set yet
+    mppi_tracking_cost t{};
+    for (float& q : t.Q) q = 1.f;
+    for (float& r : t.R) r = 0.5f;
+    t.period = 0.5f; t.duty = 0.5f; t.swing_height = 0.08f; t.stand_height = 0.25f; t.gait = 1;
+    t.box_weight = nx == 50 ? 2.f : 0.f;
+    mppi_tracking_cost bad = t;
+    bad.duty = 1.f;
+    REFUSED(mppi_set_tracking_cost(c, &bad));
+    bad = t;
+    bad.reserved = 1;
+    REFUSED(mppi_set_tracking_cost(c, &bad));
+    OK(mppi_set_tracking_cost(c, &t));
+    OK(mppi_rollout_batch(c, x, nullptr, costs, nullptr));
+    OK(mppi_rollout_batch(c, x, eps, costs, traj));
+    OK(mppi_rollout_batch(c, x, nullptr, costs, traj));
+    OK(mppi_step(c, x, u0));
+    OK(mppi_update_shift(c, costs, u0, nullptr));
+    if (K >= 2) REFUSED(mppi_step_proposal(c, x, center, sd, 2, MPPI_PROPOSAL_GATE_NONE, u0));
+    const float cmd[3] = {0.5f, 0, 0}, org[2] = {0, 0};
+    if (nx == 37) REFUSED(mppi_set_proposal(c, pol, 2, MPPI_PROPOSAL_GATE_NONE, cmd, org));
+    OK(mppi_sync_status(c));
+    mppi_destroy(c);
+    // a running-cost controller refuses tracking parameters
+    mppi_params q = params(K, H, nk);
+    if (OK(mppi_create(m, &q, &c)) < 0) return;
+    REFUSED(mppi_set_tracking_cost(c, &t));
+    mppi_destroy(c);
 }
 
 static void controller(mppi_model* m, mppi_policy* pol, int nx, int K, int H, int nk, int basis)
@@ -132,6 +174,9 @@ static void batch(mppi_model* flat, mppi_model* terrain, mppi_model* push, mppi_
         mppi_params p = params(s.K, s.H, s.nk, s.basis);
         std::vector<float> x0(50, 0.f), mu(96, 0.5f);
         int id = -1;
+        mppi_params pt = p;
+        pt.cost = MPPI_COST_TRACKING;
+        REFUSED(mppi_batch_admit(b, s.slot, &pt, x0.data(), mu.data(), &id));
         OK(mppi_batch_admit(b, s.slot, &p, x0.data(), mu.data(), &id));
         ids.push_back(id);
         if (s.prop) OK(mppi_batch_set_proposal(b, id, pol, cmd, org));
@@ -173,6 +218,10 @@ int main()
     controller(climb, pol, 37, 5, 3, 3, 2);
     controller(push, pol, 50, 257, 60, 8, 0);
     controller(flat, pol, 37, 1, 1, 2, 0);
+    tracking(flat, pol, 37, 64, 25, 4, 0);
+    tracking(terrain, pol, 37, 100, 50, 6, 1);
+    tracking(push, pol, 50, 257, 60, 8, 0);
+    tracking(flat, pol, 37, 1, 256, 8, 0);
     policy(pol);
     batch(flat, terrain, push, pol, 0);
     batch(flat, terrain, push, pol, 1);

@@ -167,3 +167,45 @@ def test_library_basis_and_shift_equal_the_oracle(basis, nk, H, dt):
     assert B.lib().mppi_get_basis(None, None, None) == B.EINVAL
     B.lib().mppi_destroy(h)
     B.lib().mppi_model_destroy(mh)
+
+
+def test_tracking_workspace_holds_the_trajectories():
+    rc, mh = _model_handle()
+    p = W.params_dict(W.FLAT_WALK, 0)
+    sizes = []
+    for extra in ({}, dict(cost="tracking")):
+        ps = B.params_struct(dict(p, **extra))
+        h = C.c_void_p()
+        assert B.lib().mppi_create(mh, C.byref(ps), C.byref(h)) == 0
+        sizes.append(B.lib().mppi_workspace_bytes(h))
+        B.lib().mppi_destroy(h)
+    assert sizes[1] - sizes[0] >= 4 * p["K"] * (p["H"] + 1) * 37
+    ps = B.params_struct(p)
+    ps.cost = 2
+    h = C.c_void_p()
+    assert B.lib().mppi_create(mh, C.byref(ps), C.byref(h)) == B.EINVAL
+    B.lib().mppi_model_destroy(mh)
+
+
+@pytest.mark.parametrize("bad", [dict(duty=1.0), dict(duty=0.0), dict(period=0.0), dict(stand_height=0.0),
+                                 dict(swing_height=-0.01), dict(box_w=-1.0), dict(gait=2), dict(reserved=1),
+                                 dict(Q=[1.0] * 35 + [-1.0]), dict(R=[float("nan")] + [1.0] * 11),
+                                 dict(v_cmd=(float("inf"), 0.0))])
+def test_tracking_cost_validation(bad):
+    rc, mh = _model_handle()
+    p = W.params_dict(W.FLAT_WALK, 0, cost="tracking")
+    ps = B.params_struct(p)
+    h = C.c_void_p()
+    assert B.lib().mppi_create(mh, C.byref(ps), C.byref(h)) == 0
+    good = W.tracking_cost()
+    assert B.lib().mppi_set_tracking_cost(h, C.byref(B.tracking_struct(good))) == 0
+    assert B.lib().mppi_set_tracking_cost(h, C.byref(B.tracking_struct(dict(good, **bad)))) == B.EINVAL
+    # unbound: the rollout refuses before launching
+    assert B.lib().mppi_rollout_batch(h, C.c_void_p(256), None, C.c_void_p(512), None) == B.ESTATE
+    B.lib().mppi_destroy(h)
+    # a running-cost controller refuses tracking parameters
+    ps = B.params_struct(W.params_dict(W.FLAT_WALK, 0))
+    assert B.lib().mppi_create(mh, C.byref(ps), C.byref(h)) == 0
+    assert B.lib().mppi_set_tracking_cost(h, C.byref(B.tracking_struct(good))) == B.EINVAL
+    B.lib().mppi_destroy(h)
+    B.lib().mppi_model_destroy(mh)

@@ -1,0 +1,183 @@
+"""GPU parity of the Eq. 3 / Eq. 4 tracking cost against the FP64 oracle, through the C ABI.
+
+  * the cost kernel on the GPU's own rollout trajectories against the oracle's cost of
+    those trajectories (both FP64: rounding-order agreement), Philox and explicit noise,
+    trot and standing references, with the box's l1 term, at several step counters;
+  * 10-step rollout costs against the oracle's own rollouts (1e-4 relative);
+  * full control steps against the oracle's tracking MPPI step (knots within 1e-3),
+    including the full heightfield launch shape (K=1024, H=50);
+  * the FP32-arithmetic cost kernel within 5e-5 relative of the oracle on the same
+    trajectories.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_10469_amd import workloads as W
+from tests.parity_utils import COST_TOL, KNOT_TOL, f32, round_model, round_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_10469_amd import binding
+    binding.lib()
+    return binding
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).cuda().contiguous()
+
+
+def round_tracking(c: dict) -> dict:
+    """Both sides consume the same FP32-representable parameters."""
+    out = dict(c)
+    for k, v in c.items():
+        if isinstance(v, float):
+            out[k] = float(np.float32(v))
+        elif isinstance(v, (list, tuple)) and v and isinstance(v[0], float):
+            out[k] = [float(np.float32(x)) for x in v]
+    return out
+
+
+def _setup(B, workload, seed=0, gait=1, arith="fp64", **pover):
+    md = round_model(W.model_dict(workload, seed))
+    p = round_params(W.params_dict(workload, seed, cost="tracking", arith=arith, **pover))
+    box = W.box_goal(seed) if workload["scene"] == W.SCENE_FREE_BOX else None
+    c = round_tracking(W.tracking_cost(gait=gait, box_goal_xy=box))
+    orc = O.Oracle(md)
+    model = B.Model(md)
+    ctl = B.Controller(model, p)
+    ctl.set_tracking_cost(c)
+    return md, p, c, orc, model, ctl
+
+
+def _controls(p, mu, eps):
+    """u_k of every sample (K x H x 12) from theta = mu + sigma eps (theta_0 = mu)."""
+    Bm = O.basis_matrix(p.get("basis", 0), p["nk"], p["H"], p["dt"])
+    th = mu[None, :] + p["sigma"] * eps
+    th[0] = mu
+    return np.einsum("hi,nji->nhj", Bm, th.reshape(-1, 12, p["nk"]))
+
+
+CASES = [
+    (W.FLAT_WALK, dict(K=64, H=25), 1, 3),
+    (W.TERRAIN_WALK, dict(K=100, H=50), 0, 0),
+    (W.TERRAIN_WALK, dict(K=33, H=70), 1, 41),
+    (W.BOX_PUSH, dict(K=64, H=30, nk=8), 1, 7),
+]
+
+
+@pytest.mark.parametrize("workload,over,gait,step", CASES)
+@pytest.mark.parametrize("explicit", [False, True])
+def test_cost_kernel_on_gpu_trajectories(B, workload, over, gait, step, explicit):
+    md, p, c, orc, model, ctl = _setup(B, workload, gait=gait, **over)
+    K, nk = p["K"], p["nk"]
+    x0 = f32(W.initial_state(step, workload["scene"]))
+    x0[19:21] = (0.2, -0.05)  # a velocity error for the Raibert term
+    x0 = f32(x0)
+    mu = f32(W.stance_knots(nk) + np.random.default_rng(step).uniform(-0.1, 0.1, 12 * nk))
+    ctl.set_nominal(_dev(mu))
+    ctl.set_step(step)
+    if explicit:
+        eps = f32(W.explicit_noise(11 + step, K, nk))
+        costs, traj = ctl.rollout_batch(_dev(x0), eps=_dev(eps), traj=True)
+    else:
+        # the rollout keeps its Philox noise as FP32; the oracle's double noise rounds to it
+        eps = f32(O.sample_eps(p, step))
+        costs, traj = ctl.rollout_batch(_dev(x0), traj=True)
+    got = costs.cpu().numpy().astype(np.float64)
+    tr = traj.cpu().numpy().astype(np.float64)
+    u = _controls(p, mu, eps)
+    want = np.array([orc.tracking_cost(p, c, step, tr[n], u[n]) for n in range(K)])
+    assert np.isfinite(want).all()
+    rel = np.abs(got - want) / np.abs(want)
+    tol = 2e-7 if explicit else 2e-6  # FP32 rounding of the stored cost; Philox noise rounding
+    assert rel.max() <= tol, (rel.max(), int(rel.argmax()))
+
+
+@pytest.mark.parametrize("workload,K,gait", [(W.FLAT_WALK, 48, 1), (W.TERRAIN_WALK, 40, 1), (W.BOX_PUSH, 24, 1),
+                                             (W.FLAT_WALK, 16, 0)])
+def test_rollout_costs_10_steps_match_oracle(B, workload, K, gait):
+    md, p, c, orc, model, ctl = _setup(B, workload, gait=gait, K=K, H=10)
+    nk = p["nk"]
+    x0 = f32(W.initial_state(2, workload["scene"]))
+    mu = f32(W.stance_knots(nk) + np.random.default_rng(4).uniform(-0.1, 0.1, 12 * nk))
+    eps = f32(W.explicit_noise(6, K, nk))
+    ctl.set_nominal(_dev(mu))
+    ctl.set_step(9)
+    got = ctl.rollout_batch(_dev(x0), eps=_dev(eps)).cpu().numpy().astype(np.float64)
+    want = np.array([orc.rollout_tracking(p, c, 9, x0, mu + (p["sigma"] * eps[n] if n else 0.0)) for n in range(K)])
+    rel = np.abs(got - want) / np.abs(want)
+    assert rel.max() <= COST_TOL, (rel.max(), int(rel.argmax()))
+
+
+@pytest.mark.parametrize("workload,over,gait", [(W.FLAT_WALK, dict(K=64, H=25), 1), (W.FLAT_WALK, dict(K=64, H=25), 0),
+                                                (W.BOX_PUSH, dict(K=128, H=30, nk=8), 1)])
+def test_mppi_step_with_tracking_matches_oracle(B, workload, over, gait):
+    md, p, c, orc, model, ctl = _setup(B, workload, gait=gait, **over)
+    for step in (0, 17):
+        x0 = f32(W.initial_state(step, workload["scene"]))
+        mu = f32(W.stance_knots(p["nk"]) + np.random.default_rng(step).uniform(-0.05, 0.05, 12 * p["nk"]))
+        ctl.set_nominal(_dev(mu))
+        ctl.set_step(step)
+        u0 = ctl.step(_dev(x0)).cpu().numpy()
+        nominal = ctl.get_nominal().cpu().numpy()
+        assert ctl.sync_status() == 0 and ctl.step_counter == step + 1
+        ou0, omu, _, rc = orc.mppi_step_tracking(p, c, step, x0, mu)
+        assert rc == 0
+        assert np.abs(u0 - ou0).max() <= KNOT_TOL, step
+        assert np.abs(nominal - omu).max() <= KNOT_TOL, step
+
+
+def test_full_size_heightfield_step_with_tracking(B):
+    """The heightfield launch shape (K=1024, H=50, 6 knots) with the trot reference:
+    one control step against the oracle's."""
+    md, p, c, orc, model, ctl = _setup(B, W.TERRAIN_WALK, gait=1)
+    x0 = f32(W.initial_state(1, W.SCENE_HEIGHTFIELD))
+    mu = f32(W.stance_knots(p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    ctl.set_step(3)
+    u0 = ctl.step(_dev(x0)).cpu().numpy()
+    nominal = ctl.get_nominal().cpu().numpy()
+    assert ctl.sync_status() == 0
+    ou0, omu, ocosts, _ = orc.mppi_step_tracking(p, c, 3, x0, mu)
+    assert np.isfinite(ocosts).all()
+    assert np.abs(u0 - ou0).max() <= KNOT_TOL
+    assert np.abs(nominal - omu).max() <= KNOT_TOL
+
+
+def test_fp32_cost_kernel_against_the_oracle(B):
+    md, p, c, orc, model, ctl = _setup(B, W.FLAT_WALK, gait=1, arith="fp32", K=64, H=25)
+    x0 = f32(W.initial_state(5))
+    mu = f32(W.stance_knots(p["nk"]))
+    eps = f32(W.explicit_noise(3, p["K"], p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    ctl.set_step(12)
+    costs, traj = ctl.rollout_batch(_dev(x0), eps=_dev(eps), traj=True)
+    got = costs.cpu().numpy().astype(np.float64)
+    tr = traj.cpu().numpy().astype(np.float64)
+    u = _controls(p, mu, eps)
+    want = np.array([orc.tracking_cost(p, c, 12, tr[n], u[n]) for n in range(p["K"])])
+    rel = np.abs(got - want) / np.abs(want)
+    assert rel.max() <= 5e-5, rel.max()  # FP32 sums and FP32 inverse kinematics
+
+
+def test_tracking_refuses_the_proposal_and_needs_its_parameters(B):
+    md = round_model(W.model_dict(W.FLAT_WALK, 0))
+    p = round_params(W.params_dict(W.FLAT_WALK, 0, cost="tracking"))
+    model = B.Model(md)
+    ctl = B.Controller(model, p)
+    x0 = _dev(W.initial_state(0))
+    with pytest.raises(B.MppiError):
+        ctl.step(x0)  # no parameters yet
+    ctl.set_tracking_cost(W.tracking_cost())
+    D = 12 * p["nk"]
+    with pytest.raises(B.MppiError):
+        ctl.step_proposal(x0, _dev(np.zeros(D)), _dev(np.full(D, 0.1)), 16)
+    ctl.step(x0)
+    assert ctl.sync_status() == 0
