@@ -135,7 +135,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="heightfield_walk",
                     help="heightfield_walk (default), flat_walk, box_push, box_climb, batched_serving, "
-                         "proposal_training or ablations")
+                         "proposal_training, ablations or tracking")
     ap.add_argument("--arith", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -167,6 +167,8 @@ def main():
         return bench_serving(args)
     if args.workload == "proposal_training":
         return bench_proposal(args)
+    if args.workload == "tracking":
+        return bench_tracking(args)
     if args.workload == "ablations":
         return bench_ablation(args)
     wl = W.WORKLOADS[args.workload]
@@ -419,6 +421,56 @@ def bench_ablation(args):
            "config": {"workload": "ablations", "seeds": [args.seed, args.seed + args.eval_seeds - 1],
                       "episode_steps": args.eval_steps},
            "tasks": res, "sweeps": sweeps, "seconds": time.perf_counter() - t0}
+    print(json.dumps(out), flush=True)
+
+
+def bench_tracking(args):
+    """Eq. 3 / Eq. 4 (the tracking cost) against the running cost in closed loop: walking on
+    flat ground and on the heightfield with the standing and the trotting joint reference,
+    the box push with the l1 box term, and the control-step latency the cost kernel adds
+    at the heightfield launch shape (K 1024, H 50)."""
+    import numpy as np
+    import torch
+    from paper_2409_10469_amd import ablations as AB
+    from paper_2409_10469_amd import binding as Bd
+    from paper_2409_10469_amd import workloads as W
+    log = lambda m: print(m, flush=True)
+    t0 = time.perf_counter()
+    seeds = range(args.seed, args.seed + args.eval_seeds)
+    walk = AB.tracking_ablation(seeds=seeds, steps=300, arith=args.arith, log=log)
+    push = AB.push_ablation(seeds=seeds, steps=400, arith=args.arith, log=log)
+    # latency of a control step with each cost (events on the controller's stream)
+    wl = W.TERRAIN_WALK
+    model = Bd.Model(W.model_dict(wl, 0))
+    lat = {}
+    for name in ("running", "tracking"):
+        p = dict(W.params_dict(wl, 0), arith=args.arith, cost=name)
+        ctl = Bd.Controller(model, p)
+        if name == "tracking":
+            ctl.set_tracking_cost(W.tracking_cost())
+        x = torch.tensor(W.initial_state(0, wl["scene"]), dtype=torch.float32, device="cuda")
+        u0 = torch.empty(12, dtype=torch.float32, device="cuda")
+        ctl.set_nominal(torch.tensor(W.stance_knots(p["nk"]), dtype=torch.float32, device="cuda"))
+        for _ in range(10):
+            ctl.step(x, u0)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(200)]
+        for a, b in ev:
+            a.record()
+            ctl.step(x, u0)
+            b.record()
+        torch.cuda.synchronize()
+        v = [a.elapsed_time(b) for a, b in ev]
+        lat[name] = dict(p50=float(np.percentile(v, 50)), p99=float(np.percentile(v, 99)))
+        log(f"  control step with the {name} cost: p50 {lat[name]['p50']:.3f} ms, p99 {lat[name]['p99']:.3f} ms")
+    trot = walk["heightfield"]["eq3_trot"]
+    out = {"metric": "closed-loop forward-velocity error with the Eq. 3 trotting reference (heightfield)",
+           "value": trot["v_err"], "unit": "m/s", "n_gpus": 1, "steps": 300, "warmup": 0,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.arith == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": "tracking", "seeds": [args.seed, args.seed + args.eval_seeds - 1],
+                      "walk_steps": 300, "push_steps": 400, "controller": "K 1024, H 50, dt 0.01, 6 knots (walk); "
+                      "K 4096, H 60, 8 knots (push)"},
+           "walk": walk, "push": push, "step_latency_ms": lat, "seconds": time.perf_counter() - t0}
     print(json.dumps(out), flush=True)
 
 

@@ -76,6 +76,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is not built (run __graft_entry__.build())")
+        # torch ships its own HIP runtime under the same soname; loading torch first makes
+        # the library bind to that one, so the process has a single runtime for the
+        # workspace, the streams and the kernels
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, fp, u32p = C.c_void_p, C.c_void_p, C.c_void_p
         sig = {

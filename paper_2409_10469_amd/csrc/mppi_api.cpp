@@ -47,7 +47,7 @@ struct mppi_ctx {
     // trajectory region the cost kernel reads
     track::TrackDev track{};
     bool track_set = false;
-    size_t off_traj = 0;
+    size_t off_traj = 0, off_uref = 0;
     std::string err;
 };
 
@@ -361,6 +361,8 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     if (p->cost == MPPI_COST_TRACKING) {
         c->off_traj = o;
         o = align256(o + sizeof(float) * (size_t)p->K * (p->H + 1) * model->nx);
+        c->off_uref = o;
+        o = align256(o + track::tracking_table_bytes(p->H));
     }
     c->total = o;
     *out = c;
@@ -480,7 +482,8 @@ static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, f
     t.dt = c->p.dt;
     t.step = c->step;
     t.costs = d_costs;
-    return hip_check(c, track::launch_tracking_cost(c->p.arith, t, c->stream), "tracking cost launch");
+    return hip_check(c, track::launch_tracking_cost(c->p.arith, t, d_x0, wsf(c, c->off_uref), c->stream),
+                     "tracking cost launch");
 }
 
 mppi_status mppi_rollout_batch(mppi_ctx* c, const float* d_x0, const float* d_eps, float* d_costs, float* d_traj)

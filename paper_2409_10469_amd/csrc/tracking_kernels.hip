@@ -1,15 +1,14 @@
 // Eq. 3 / Eq. 4 sample cost on rollout trajectories (gfx950).
 //
-// One 64-lane workgroup per sample.  The lanes first build, in LDS, the joint reference
-// u_ref(t_k) of the trotting gait for every rollout time (Sec. IV-B names a Raibert-
-// heuristic gait; its footholds and arcs are the library's reading), the knot
-// interpolation matrix and the sample's knots theta = mu + sigma eps.  Each lane then
-// takes the stages k = lane, lane + 64, ... of the horizon: the post-step state x_{k+1}
-// (one contiguous row of the trajectory, so the workgroup's loads are coalesced), the
-// interpolated control u_k, and the weighted squared deviations of Eq. 3 plus Eq. 4's l1
-// box distance.  A fixed-order butterfly sums the lanes.  Work per sample is H x (36 + 12
-// + 12 nk) multiply-adds next to a rollout of H full dynamics steps, and the trajectory
-// is read once, so the kernel is a small HBM stream after the rollout.
+// gait_table_kernel builds the joint reference u_ref(t_k) of the gait for every rollout
+// time once per control step (Sec. IV-B names a Raibert-heuristic trotting gait; its
+// footholds and arcs are the library's reading); every sample shares it.
+// tracking_cost_kernel: one 64-lane workgroup per sample, its knots theta = mu + sigma eps
+// in LDS.  Each lane then takes the stages k = lane, lane + 64, ... of the horizon: the state
+// x_{k+1}, the interpolated control u_k, and the weighted squared deviations of Eq. 3 plus
+// Eq. 4's l1 box distance.  A fixed-order butterfly sums the lanes.  The trajectory is
+// read once, so the kernel is an HBM stream after the rollout (H x nx x 4 bytes per
+// sample).
 #include <hip/hip_runtime.h>
 
 #include "tracking_launch.h"
@@ -17,6 +16,7 @@
 namespace track {
 
 constexpr int kLanes = 64;
+constexpr int kTableLanes = 256;
 constexpr int kMaxKnots = 8;
 
 template <typename R>
@@ -99,44 +99,51 @@ __device__ void gait_foot(const TrackDev& g, int leg, R t, const R v[2], const R
     p[2] = -R(g.stand_h) + lift;
 }
 
+// joint reference u_ref(t_k), k = 0..H, of the gait in the heading frame of the start
+// state x0: one workgroup, one (time, leg) pair per lane, written to uref[(H+1) x 12]
 template <typename R>
-__global__ __launch_bounds__(kLanes) void tracking_cost_kernel(TrackArgs a)
+__global__ __launch_bounds__(kTableLanes) void gait_table_kernel(TrackArgs a, const float* __restrict__ x0,
+                                                                 R* __restrict__ uref)
 {
     using M = Math<R>;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int H = a.H, nk = a.nk, nx = a.nx, D = 12 * nk;
-    R* sRef = reinterpret_cast<R*>(lds_raw);  // (H + 1) x 12
-    R* sB = sRef + (size_t)(H + 1) * 12;      // H x nk
-    R* sTh = sB + (size_t)H * nk;             // 12 x nk
-    const int n = blockIdx.x, lane = threadIdx.x;
-    const float* tr = a.traj + (size_t)n * (H + 1) * nx;
-
-    // heading frame of the start state (row 0, the same for every sample)
-    const R qw = tr[3], qx = tr[4], qy = tr[5], qz = tr[6];
+    const R qw = x0[3], qx = x0[4], qy = x0[5], qz = x0[6];
     const R psi = M::atan2_(R(2) * (qw * qz + qx * qy), R(1) - R(2) * (qy * qy + qz * qz));
     const R cs = M::cos_(psi), sn = M::sin_(psi);
-    const R vx = tr[19], vy = tr[20];
+    const R vx = x0[19], vy = x0[20];
     const R vh[2] = {cs * vx + sn * vy, -sn * vx + cs * vy};
     const R ch[2] = {cs * R(a.c.v_cmd[0]) + sn * R(a.c.v_cmd[1]), -sn * R(a.c.v_cmd[0]) + cs * R(a.c.v_cmd[1])};
-    for (int i = lane; i < (H + 1) * 4; i += kLanes) {
+    for (int i = threadIdx.x; i < (a.H + 1) * 4; i += kTableLanes) {
         const int k = i >> 2, leg = i & 3;
         const R t = R(a.step + (uint32_t)k) * R(a.dt);
         R p[3], q[3];
         gait_foot<R>(a.c, leg, t, vh, ch, p);
         leg_ik<R>(R(a.c.l1), R(a.c.l2), p, q);
-        for (int j = 0; j < 3; ++j) sRef[k * 12 + 3 * leg + j] = q[j];
+        for (int j = 0; j < 3; ++j) uref[k * 12 + 3 * leg + j] = q[j];
     }
-    for (int i = lane; i < H * nk; i += kLanes) sB[i] = R(a.B[i]);
+}
+
+// one sample per workgroup: its knots theta go to LDS; lane k then loads its post-step
+// state row straight from the trajectory (independent loads, so a lane waits for one
+// memory round trip, not one per element), and reads the shared gait table and
+// interpolation rows (L2-resident)
+template <typename R>
+__global__ __launch_bounds__(kLanes) void tracking_cost_kernel(TrackArgs a, const R* __restrict__ uref)
+{
+    using M = Math<R>;
+    __shared__ R sTh[kMaxKnots * 12];
+    const int H = a.H, nk = a.nk, nx = a.nx, D = 12 * nk;
+    const int n = blockIdx.x, lane = threadIdx.x;
+    const float* tr = a.traj + (size_t)n * (H + 1) * nx + nx;  // rows 1..H
     for (int d = lane; d < D; d += kLanes)
         sTh[d] = R(a.mu[d]) + (n ? R(a.sigma) * R(a.eps[(size_t)n * a.eps_sn + (size_t)d * a.eps_sd]) : R(0));
     __syncthreads();
 
     R acc = R(0);
     for (int k = lane; k < H; k += kLanes) {
-        const float* x = tr + (size_t)(k + 1) * nx;
+        const float* x = tr + (size_t)k * nx;  // x_{k+1}
         const R tx = R(a.step + (uint32_t)(k + 1)) * R(a.dt);
-        const R* qref = sRef + (k + 1) * 12;
-        const R* uref = sRef + k * 12;
+        const R* qref = uref + (k + 1) * 12;
+        const R* ur = uref + k * 12;
         // weighted squares of the state error, in the order of the error vector
         R l = R(0);
         auto add = [&](int i, R e) { l += R(a.c.Q[i]) * e * e; };
@@ -151,11 +158,12 @@ __global__ __launch_bounds__(kLanes) void tracking_cost_kernel(TrackArgs a)
         add(20, R(x[21]));
         for (int i = 0; i < 3; ++i) add(21 + i, R(x[22 + i]));
         for (int j = 0; j < 12; ++j) add(24 + j, R(x[25 + j]));
+        const double* Bk = a.B + (size_t)k * nk;
         for (int j = 0; j < 12; ++j) {
             R u = R(0);
             for (int i = 0; i < kMaxKnots; ++i)
-                if (i < nk) u += sB[k * nk + i] * sTh[j * nk + i];
-            const R du = u - uref[j];
+                if (i < nk) u += R(Bk[i]) * sTh[j * nk + i];
+            const R du = u - ur[j];
             l += R(a.c.R[j]) * du * du;
         }
         if (a.c.box)
@@ -170,20 +178,24 @@ __global__ __launch_bounds__(kLanes) void tracking_cost_kernel(TrackArgs a)
     }
 }
 
-size_t tracking_lds_bytes(int arith, int H, int nk)
+size_t tracking_lds_bytes(int arith, int H, int nk, int nx)
 {
-    const size_t r = arith == 0 ? sizeof(double) : sizeof(float);
-    return r * ((size_t)(H + 1) * 12 + (size_t)H * nk + 12 * (size_t)nk);
+    (void)H; (void)nk; (void)nx;
+    return (arith == 0 ? sizeof(double) : sizeof(float)) * kMaxKnots * 12;  // static: theta
 }
 
-hipError_t launch_tracking_cost(int arith, const TrackArgs& a, hipStream_t st)
+size_t tracking_table_bytes(int H) { return sizeof(double) * (size_t)(H + 1) * 12; }
+
+hipError_t launch_tracking_cost(int arith, const TrackArgs& a, const float* x0, void* table, hipStream_t st)
 {
     if (a.K <= 0) return hipSuccess;
-    const size_t lds = tracking_lds_bytes(arith, a.H, a.nk);
-    if (arith == 0)
-        hipLaunchKernelGGL(tracking_cost_kernel<double>, dim3(a.K), dim3(kLanes), lds, st, a);
-    else
-        hipLaunchKernelGGL(tracking_cost_kernel<float>, dim3(a.K), dim3(kLanes), lds, st, a);
+    if (arith == 0) {
+        hipLaunchKernelGGL(gait_table_kernel<double>, dim3(1), dim3(kTableLanes), 0, st, a, x0, (double*)table);
+        hipLaunchKernelGGL(tracking_cost_kernel<double>, dim3(a.K), dim3(kLanes), 0, st, a, (const double*)table);
+    } else {
+        hipLaunchKernelGGL(gait_table_kernel<float>, dim3(1), dim3(kTableLanes), 0, st, a, x0, (float*)table);
+        hipLaunchKernelGGL(tracking_cost_kernel<float>, dim3(a.K), dim3(kLanes), 0, st, a, (const float*)table);
+    }
     return hipGetLastError();
 }
 

@@ -30,8 +30,11 @@ struct TrackArgs {
     float* costs;          // K sample costs (+inf when not finite)
 };
 
-// one 64-lane workgroup per sample; arith 0 evaluates in FP64, 1 in FP32
-hipError_t launch_tracking_cost(int arith, const TrackArgs& a, hipStream_t st);
-size_t tracking_lds_bytes(int arith, int H, int nk);
+// the gait table from the start state x0 (one workgroup) into `table`
+// (tracking_table_bytes(H), 256-byte aligned device memory), then the cost with one 64-lane
+// workgroup per sample; arith 0 evaluates in FP64, 1 in FP32
+hipError_t launch_tracking_cost(int arith, const TrackArgs& a, const float* x0, void* table, hipStream_t st);
+size_t tracking_lds_bytes(int arith, int H, int nk, int nx);
+size_t tracking_table_bytes(int H);
 
 }  // namespace track

@@ -148,11 +148,11 @@ def scene_extras(workload: dict, seed: int) -> dict:
 def tracking_cost(gait: int = 1, v_cmd=(0.5, 0.0), origin=(0.0, 0.0), box_goal_xy=None, **override) -> dict:
     """Parameters of the Eq. 3 / Eq. 4 tracking cost (shared keys for the library and the
     oracle).  Q is diagonal over the state error [p(3), attitude(3), q(12), v(3), w(3),
-    qd(12)], R over the joint targets.  gait 1 trots (period 0.5 s, half stance, 8 cm
+    qd(12)], R over the joint targets.  gait 1 trots (period 0.4 s, half stance, 8 cm
     foot lift); gait 0 holds the standing pose."""
     Q = ([1.0, 1.0, 100.0] + [10.0, 10.0, 1.0] + [0.1] * 12 + [1.0, 1.0, 0.1] + [0.1, 0.1, 0.1] + [1.0e-3] * 12)
     c = dict(Q=Q, R=[0.5] * 12, p_ref0=(origin[0], origin[1], WALK_COST["h_ref"]), v_cmd=tuple(v_cmd),
-             period=0.5, duty=0.5, swing_height=0.08, stand_height=WALK_COST["h_ref"] - ROBOT["foot_r"],
+             period=0.4, duty=0.5, swing_height=0.08, stand_height=WALK_COST["h_ref"] - ROBOT["foot_r"],
              raibert_k=0.1, box_w=0.0, box_goal=(0.0, 0.0), gait=int(gait))
     if box_goal_xy is not None:
         c.update(box_w=2.0, box_goal=tuple(box_goal_xy))

@@ -5,6 +5,7 @@
 // instance table.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <vector>
 
@@ -216,25 +217,29 @@ hipError_t launch_batch_head_noise(int np, const mppi::InstDesc* table, const Ba
 }  // namespace prop
 
 namespace track {
-hipError_t launch_tracking_cost(int arith, const TrackArgs& a, hipStream_t)
+hipError_t launch_tracking_cost(int arith, const TrackArgs& a, const float* x0, void* table, hipStream_t)
 {
     const int D = 12 * a.nk;
     if (a.K < 1 || a.H < 1 || a.nk < 2 || a.nk > 8 || (a.nx != 37 && a.nx != 50) || (arith != 0 && arith != 1))
         fail("tracking shape");
     if (a.c.box != (a.nx == 50)) fail("tracking box flag");
+    range_check(x0, 4ull * a.nx, "tracking start state");
+    range_check(table, tracking_table_bytes(a.H), "tracking gait table");
+    if (((uintptr_t)table & 7) != 0) fail("tracking table alignment");
     range_check(a.traj, 4ull * a.K * (a.H + 1) * a.nx, "tracking trajectories");
     range_check(a.B, 8ull * a.H * a.nk, "tracking basis");
     range_check(a.mu, 4ull * D, "tracking nominal");
     range_check(a.eps, 4 * strided_span(a.K, D, a.eps_sn, a.eps_sd), "tracking noise");
     range_check(a.costs, 4ull * a.K, "tracking costs");
-    if (tracking_lds_bytes(arith, a.H, a.nk) > 65536) fail("tracking LDS");
+    if (tracking_lds_bytes(arith, a.H, a.nk, a.nx) > 65536) fail("tracking LDS");
     return hipSuccess;
 }
-size_t tracking_lds_bytes(int arith, int H, int nk)
+size_t tracking_lds_bytes(int arith, int H, int nk, int nx)
 {
-    const size_t r = arith == 0 ? sizeof(double) : sizeof(float);
-    return r * ((size_t)(H + 1) * 12 + (size_t)H * nk + 12 * (size_t)nk);
+    (void)H; (void)nk; (void)nx;
+    return (arith == 0 ? sizeof(double) : sizeof(float)) * 8 * 12;
 }
+size_t tracking_table_bytes(int H) { return sizeof(double) * (size_t)(H + 1) * 12; }
 }  // namespace track
 
 namespace mlp {
