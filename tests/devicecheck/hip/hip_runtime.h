@@ -1,0 +1,108 @@
+// CPU emulation of the HIP device model for the device-code check (tests/devicecheck):
+// a kernel launch runs its workgroups one after another, each workgroup as one host
+// thread per lane.  __syncthreads is a workgroup barrier, DPP quad permutes exchange
+// values inside a quad of lanes and __shfl_xor inside a 64-lane wave, each through a
+// barrier, so every exchange needs all participating lanes to arrive (a lane that never
+// arrives is reported as divergence after a timeout).  Device memory is host memory.
+// Not a GPU build: it lets the sanitizers watch every load and store of the kernels.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+
+#define __device__
+#define __host__
+#define __global__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+#define EMU_DYNAMIC_SHARED extern
+#define __align__(n) alignas(n)
+
+struct dim3 {
+    unsigned x, y, z;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+extern thread_local dim3 threadIdx, blockIdx;
+extern dim3 blockDim, gridDim;
+constexpr size_t kEmuLdsBytes = 160 * 1024;
+extern alignas(16) unsigned char lds_raw[kEmuLdsBytes];
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+typedef void* hipStream_t;
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t)
+{
+    std::memmove(d, s, n);
+    return hipSuccess;
+}
+inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind k) { return hipMemcpyAsync(d, s, n, k, 0); }
+inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t)
+{
+    std::memset(d, v, n);
+    return hipSuccess;
+}
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline const char* hipGetErrorString(hipError_t) { return "emulation"; }
+hipError_t hipGetLastError();
+
+// ---- device built-ins --------------------------------------------------------------
+void __syncthreads();
+inline void __threadfence() { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
+int emu_quad_exchange(int v, int src_lane);
+uint64_t emu_wave_exchange(uint64_t v, int src_lane);
+// quad_perm control (the only DPP form the kernels use): lane i of a quad reads lane
+// (ctrl >> 2i) & 3
+inline int __builtin_amdgcn_update_dpp(int, int v, int ctrl, int row_mask, int bank_mask, bool)
+{
+    if (ctrl > 0xFF || row_mask != 0xF || bank_mask != 0xF) {
+        std::fprintf(stderr, "emulation: unsupported DPP control 0x%x\n", ctrl);
+        std::abort();
+    }
+    return emu_quad_exchange(v, (ctrl >> (2 * (threadIdx.x & 3))) & 3);
+}
+template <typename T>
+inline T __shfl_xor(T v, int mask, int width = 64)
+{
+    static_assert(sizeof(T) <= 8, "shuffle of up to 8 bytes");
+    if (width != 64) std::abort();
+    uint64_t b = 0;
+    std::memcpy(&b, &v, sizeof(T));
+    b = emu_wave_exchange(b, (int)((threadIdx.x & 63) ^ (unsigned)mask));
+    T r;
+    std::memcpy(&r, &b, sizeof(T));
+    return r;
+}
+inline int __builtin_amdgcn_readfirstlane(int v) { return v; }  // only in the batch kernel (not run here)
+inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
+inline float __int_as_float(int i) { float f; std::memcpy(&f, &i, 4); return f; }
+inline int __float_as_int(float f) { int i; std::memcpy(&i, &f, 4); return i; }
+inline int __double2loint(double d) { int64_t i; std::memcpy(&i, &d, 8); return (int)(i & 0xffffffff); }
+inline int __double2hiint(double d) { int64_t i; std::memcpy(&i, &d, 8); return (int)(i >> 32); }
+inline double __hiloint2double(int hi, int lo)
+{
+    const int64_t i = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    double d;
+    std::memcpy(&d, &i, 8);
+    return d;
+}
+inline void sincospif(float x, float* s, float* c) { *s = sinf((float)M_PI * x); *c = cosf((float)M_PI * x); }
+inline void sincospi(double x, double* s, double* c) { *s = sin(M_PI * x); *c = cos(M_PI * x); }
+using std::max;
+using std::min;
+
+// ---- launch: workgroups in sequence, one host thread per lane -----------------------
+void emu_run_grid(dim3 grid, dim3 block, size_t lds, const std::function<void()>& body);
+template <typename K, typename... A>
+void emu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... args)
+{
+    emu_run_grid(grid, block, lds, [=]() { kernel(args...); });
+}
+#define hipLaunchKernelGGL(kernel, grid, block, lds, stream, ...) emu_launch(kernel, grid, block, lds, __VA_ARGS__)
