@@ -22,7 +22,10 @@
 
 thread_local dim3 threadIdx, blockIdx;
 dim3 blockDim, gridDim;
+namespace mppi {
 alignas(16) unsigned char lds_raw[kEmuLdsBytes];
+}
+using mppi::lds_raw;
 
 hipError_t hipGetLastError() { return hipSuccess; }
 

@@ -15,6 +15,10 @@
 #include <cstring>
 #include <functional>
 
+#ifndef __clang__
+typedef unsigned short __bf16;  // the network headers name the type; no network kernel is built here
+#endif
+
 #define __device__
 #define __host__
 #define __global__
@@ -22,7 +26,7 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define EMU_DYNAMIC_SHARED extern
-#define __align__(n) alignas(n)
+#define __align__(n)  // the LDS definition in emu.cpp carries the alignment
 
 struct dim3 {
     unsigned x, y, z;
@@ -31,7 +35,10 @@ struct dim3 {
 extern thread_local dim3 threadIdx, blockIdx;
 extern dim3 blockDim, gridDim;
 constexpr size_t kEmuLdsBytes = 160 * 1024;
-extern alignas(16) unsigned char lds_raw[kEmuLdsBytes];
+// the dynamic LDS of the kernels (declared inside the kernels of namespace mppi)
+namespace mppi {
+extern unsigned char lds_raw[kEmuLdsBytes];
+}
 
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
