@@ -181,3 +181,26 @@ def test_tracking_refuses_the_proposal_and_needs_its_parameters(B):
         ctl.step_proposal(x0, _dev(np.zeros(D)), _dev(np.full(D, 0.1)), 16)
     ctl.step(x0)
     assert ctl.sync_status() == 0
+
+
+@pytest.mark.parametrize("K,H,nk,basis", [(1, 1, 2, 0), (3, 256, 8, 0), (5, 7, 3, 2), (70, 64, 5, 1)])
+def test_tracking_edges_of_horizon_samples_and_knots(B, K, H, nk, basis):
+    """One sample or a few, the one-step and the longest horizon (four stages per lane),
+    ragged knot counts and the lower-order bases: the cost kernel on the GPU's
+    trajectories against the oracle."""
+    md, p, c, orc, model, ctl = _setup(B, W.FLAT_WALK, gait=1, K=K, H=H, nk=nk, basis=basis, dt=0.01)
+    x0 = f32(W.initial_state(4))
+    mu = f32(W.stance_knots(nk) + np.random.default_rng(K).uniform(-0.05, 0.05, 12 * nk))
+    eps = f32(W.explicit_noise(9, K, nk))
+    ctl.set_nominal(_dev(mu))
+    ctl.set_step(33)
+    costs, traj = ctl.rollout_batch(_dev(x0), eps=_dev(eps), traj=True)
+    got = costs.cpu().numpy().astype(np.float64)
+    tr = traj.cpu().numpy().astype(np.float64)
+    u = _controls(p, mu, eps)
+    want = np.array([orc.tracking_cost(p, c, 33, tr[n], u[n]) for n in range(K)])
+    fin = np.isfinite(want)
+    assert fin.any()
+    assert np.array_equal(np.isfinite(got), fin)  # a diverged long rollout costs +inf on both sides
+    rel = np.abs(got[fin] - want[fin]) / np.abs(want[fin])
+    assert rel.max() <= 2e-7, (rel.max(), int(rel.argmax()))
