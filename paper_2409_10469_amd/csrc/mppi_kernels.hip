@@ -147,22 +147,35 @@ __global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, 
 }
 
 // ---------------------------------------------------------------------------------
-// Update: block j (one per joint) recomputes L_min and sum exp over all K costs with
-// fixed-order tree reductions, then the weighted noise sums for its nk knots.
+// Update: block j (one per joint, 1024 lanes) recomputes L_min and sum exp over all K
+// costs, then the weighted noise sums for its nk knots.  Every reduction is a wave
+// butterfly (its result is the same in every lane, since each pairwise sum is
+// commutative) followed by the 16 per-wave values added in wave order, so the result is
+// deterministic.  The lane count keeps the walks over K short (one pass at K = 1024,
+// four at 4096): the kernel is bound by the latency of those passes, not by bandwidth.
 // ---------------------------------------------------------------------------------
-constexpr int kUpdThreads = 256;
+constexpr int kUpdThreads = 1024;
+constexpr int kUpdWaves = kUpdThreads / 64;
 
+__device__ __forceinline__ float wave_reduce(float v, bool is_min)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float u = __shfl_xor(v, o, 64);
+        v = is_min ? fminf(v, u) : v + u;
+    }
+    return v;
+}
+
+// all lanes return the block's reduction (sh: kUpdWaves floats)
 __device__ __forceinline__ float block_reduce(float v, float* sh, bool is_min)
 {
-    const int t = threadIdx.x;
-    sh[t] = v;
+    v = wave_reduce(v, is_min);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
+    float r = sh[0];
 #pragma unroll
-    for (int s = kUpdThreads / 2; s > 0; s >>= 1) {
-        if (t < s) sh[t] = is_min ? fminf(sh[t], sh[t + s]) : sh[t] + sh[t + s];
-        __syncthreads();
-    }
-    const float r = sh[0];
+    for (int w = 1; w < kUpdWaves; ++w) r = is_min ? fminf(r, sh[w]) : r + sh[w];
     __syncthreads();
     return r;
 }
@@ -173,8 +186,8 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, const 
                                                              float* knots_out, float* nominal_out, float* u0_out,
                                                              float* __restrict__ weights_out, int* status)
 {
-    __shared__ float sh[kUpdThreads];
-    __shared__ float acc_sh[kMaxKnots][kUpdThreads];
+    __shared__ float sh[kUpdWaves];
+    __shared__ float acc_w[kMaxKnots][kUpdWaves];
     __shared__ float mup[kMaxKnots];
     const int j = blockIdx.x, t = threadIdx.x, nk = P.nk, K = P.K;
     float lmin = __int_as_float(0x7f800000);
@@ -202,17 +215,16 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, const 
     }
     s = block_reduce(s, sh, false);
 #pragma unroll
-    for (int i = 0; i < kMaxKnots; ++i) acc_sh[i][t] = acc[i];
-    __syncthreads();
-    for (int st = kUpdThreads / 2; st > 0; st >>= 1) {
-        if (t < st)
-#pragma unroll
-            for (int i = 0; i < kMaxKnots; ++i) acc_sh[i][t] += acc_sh[i][t + st];
-        __syncthreads();
+    for (int i = 0; i < kMaxKnots; ++i) {
+        const float a = wave_reduce(acc[i], false);
+        if ((t & 63) == 0) acc_w[i][t >> 6] = a;
     }
+    __syncthreads();
     if (t < nk) {
+        float a = acc_w[t][0];
+        for (int w = 1; w < kUpdWaves; ++w) a += acc_w[t][w];
         const float m = mu[j * nk + t];
-        mup[t] = none ? m : m + P.sigma * (acc_sh[t][0] / s);
+        mup[t] = none ? m : m + P.sigma * (a / s);
     }
     __syncthreads();
     if (t < nk) {
