@@ -391,8 +391,9 @@ def bench_proposal(args):
                             "smallest_plain_K_matching": ev["learned_" + g]["smallest_plain_K_matching"],
                             "sample_ratio": ev["learned_" + g]["sample_ratio"]}
                         for g in ("cost", "none")},
-            "gates": "cost: proposal only when its centre costs no more than the nominal (plain K otherwise); "
-                     "none: always the K/4 proposal samples, nominal kept as sample 1"},
+            "gates": "cost: the proposal's K/4 samples and the plain step's K samples are rolled out side by side "
+                     "(two streams) and the update uses the proposal only when its centre costs no more than the "
+                     "nominal; none: always the K/4 proposal samples alone, nominal kept as sample 1"},
         "batched_equal_cost": evb,
         "epoch_seconds": train_s / max(len(hist), 1), "train_steps": train_steps,
         "generation": {"seconds": gen_s, "batch_seconds": st["seconds"], "episodes": st["episodes"],

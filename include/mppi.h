@@ -172,7 +172,9 @@ size_t mppi_workspace_bytes(const mppi_ctx *ctx);
  * Launches nothing; needs no workspace. */
 mppi_status mppi_get_basis(const mppi_ctx *ctx, double *B_out, float *S_out);
 /* Binds a caller-owned device workspace and stream; uploads model data, spline basis and
- * shift matrix, and sets the nominal to zero.  The step counter is reset to 0. */
+ * shift matrix, and sets the nominal to zero.  The step counter is reset to 0.  Also
+ * creates the internal stream and two events of the gated proposal step (default
+ * priority), released by the next bind or mppi_destroy. */
 mppi_status mppi_bind(mppi_ctx *ctx, void *d_workspace, size_t bytes, void *hip_stream);
 /* nominal knots mu (12 * n_knots floats, device) in/out */
 mppi_status mppi_set_nominal(mppi_ctx *ctx, const float *d_knots);

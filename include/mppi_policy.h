@@ -111,10 +111,12 @@ const char *mppi_policy_last_error(const mppi_policy *pol);
  * If the rollout cost of the centre is finite and not above the nominal's, Eq. 1 and
  * Eq. 2 run over these k_prop samples; otherwise the step is a plain step with K
  * samples.  Then, as in mppi_step, the first control goes to d_u0_out, the nominal is
- * shifted and the step counter advances.  With MPPI_PROPOSAL_GATE_COST the two leading
- * costs are read on the host to choose the branch, so the call synchronises the bound
- * stream; MPPI_PROPOSAL_GATE_NONE always takes the proposal branch (the nominal still
- * competes as sample 1).  2 <= k_prop <= K.  The proposal steps use the running cost
+ * shifted and the step counter advances.  With MPPI_PROPOSAL_GATE_COST the plain step's
+ * rollout runs beside the proposal rollout (the proposal on an internal stream that
+ * mppi_bind creates, the plain one on the bound stream) and the update chooses the branch
+ * on the device from the two leading proposal costs, so the call does not synchronise;
+ * MPPI_PROPOSAL_GATE_NONE always takes the proposal branch (the nominal still competes as
+ * sample 1) and rolls out only the proposal.  2 <= k_prop <= K.  The proposal steps use the running cost
  * (EINVAL for a controller created with MPPI_COST_TRACKING). */
 enum {
     MPPI_PROPOSAL_GATE_COST = 0, /* proposal only if its centre's cost is finite and not above the nominal's */
@@ -129,7 +131,8 @@ mppi_status mppi_step_proposal(mppi_ctx *ctx, const float *d_x0, const float *d_
  * the proposal off.  Requires a 37-float state model and the running cost. */
 mppi_status mppi_set_proposal(mppi_ctx *ctx, mppi_policy *pol, int k_prop, int gate, const float *cmd,
                               const float *origin_xy);
-/* How many proposal steps ran and how many were accepted (host counters). */
+/* How many proposal steps ran and how many were accepted: device counters (reset by
+ * mppi_bind), read back with a synchronisation of the bound stream. */
 mppi_status mppi_proposal_stats(mppi_ctx *ctx, int *accepted, int *steps);
 
 /* ---- batched serving side ---------------------------------------------------------

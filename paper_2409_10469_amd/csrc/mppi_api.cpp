@@ -42,7 +42,12 @@ struct mppi_ctx {
     mppi_policy* policy = nullptr;
     int k_prop = 0, prop_gate = 0;
     float cmd_origin[8] = {};
-    int prop_accepted = 0, prop_steps = 0;
+    // the gated proposal step runs the proposal rollout on `side` beside the plain
+    // rollout on the bound stream (fork and join through the two events); the counters of
+    // accepted and all proposal steps are device ints (off_pstats)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    size_t off_pstats = 0;
     // Eq. 3 / Eq. 4 tracking cost (p.cost == MPPI_COST_TRACKING): parameters and the
     // trajectory region the cost kernel reads
     track::TrackDev track{};
@@ -358,6 +363,7 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     c->off_sd = o; o = align256(o + sizeof(float) * c->D);
     c->off_costs_p = o; o = align256(o + sizeof(float) * p->K);
     c->off_eps_p = o; o = align256(o + sizeof(float) * (size_t)c->D * p->K);
+    c->off_pstats = o; o = align256(o + sizeof(int) * 2);
     if (p->cost == MPPI_COST_TRACKING) {
         c->off_traj = o;
         o = align256(o + sizeof(float) * (size_t)p->K * (p->H + 1) * model->nx);
@@ -369,7 +375,22 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     return MPPI_OK;
 }
 
-void mppi_destroy(mppi_ctx* c) { delete c; }
+static void release_side(mppi_ctx* c)
+{
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    c->ev_fork = c->ev_join = nullptr;
+    c->side = nullptr;
+}
+
+void mppi_destroy(mppi_ctx* c)
+{
+    if (!c) return;
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    release_side(c);
+    delete c;
+}
 
 size_t mppi_workspace_bytes(const mppi_ctx* c) { return c ? c->total : 0; }
 
@@ -404,6 +425,16 @@ mppi_status mppi_bind(mppi_ctx* c, void* ws, size_t bytes, void* stream)
         return s;
     if ((s = hip_check(c, hipMemsetAsync(wsf(c, c->off_mu), 0, sizeof(float) * c->D, st), "clear nominal"))) return s;
     if ((s = hip_check(c, hipMemsetAsync(wsf(c, c->off_status), 0, sizeof(int) * 16, st), "clear status"))) return s;
+    if ((s = hip_check(c, hipMemsetAsync(wsf(c, c->off_pstats), 0, sizeof(int) * 2, st), "clear proposal counters")))
+        return s;
+    // the stream and events of the gated proposal step (default priority)
+    release_side(c);
+    if ((s = hip_check(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "create side stream")) ||
+        (s = hip_check(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "create event")) ||
+        (s = hip_check(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "create event"))) {
+        release_side(c);
+        return s;
+    }
     return hip_check(c, hipStreamSynchronize(st), "bind synchronise");
 }
 
@@ -526,10 +557,13 @@ mppi_status mppi_update(mppi_ctx* c, const float* d_costs, const float* d_eps, f
 
 // Proposal step on the plain kernels: the k_prop samples theta_n = c + e_n are rolled out
 // through the explicit-noise path with unit scale, where e holds Philox noise scaled by
-// sd for n >= 2, zero for the centre (n = 0) and nominal - c for n = 1.  The gate reads
-// the two leading costs on the host.  Accepted: the update with centre c and unit scale
-// gives mu' = c + sum w_n e_n / sum w_n, the weighted mean of theta.  Otherwise the plain
-// step runs.
+// sd for n >= 2, zero for the centre (n = 0) and nominal - c for n = 1.  With the cost
+// gate the plain rollout of the step (K Philox samples around the nominal) runs at the
+// same time on the bound stream while the proposal rollout runs on the side stream; the
+// update kernel then reads the two leading proposal costs and updates over whichever set
+// the gate picks, so the step needs no host round trip.  Accepted: mu' = c + sum w_n e_n /
+// sum w_n, the weighted mean of theta (centre c, unit scale).  Ungated: the proposal
+// rollout alone.
 static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int kp,
                                  int gate, float* d_u0_out)
 {
@@ -553,38 +587,43 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
     a.eps_sd = 1;
     a.costs = costs_p;
     a.samples_per_block = 16;
-    if ((s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, Pp, a, c->stream),
-                       "proposal rollout launch")))
-        return s;
-    bool accepted = true;
-    if (gate == MPPI_PROPOSAL_GATE_COST) {
-        float head[2];
-        if ((s = hip_check(c, hipMemcpyAsync(head, costs_p, sizeof(head), hipMemcpyDeviceToHost, c->stream),
-                           "gate read")) ||
-            (s = hip_check(c, hipStreamSynchronize(c->stream), "gate synchronise")))
-            return s;
-        accepted = std::isfinite(head[0]) && head[0] <= head[1];
-    }
-    c->prop_steps += 1;
-    if (accepted) {
-        c->prop_accepted += 1;
-        mppi::UpdateArgs u{};
-        u.costs = costs_p;
-        u.eps = e;
-        u.eps_sn = c->D;
-        u.eps_sd = 1;
-        u.mu = d_center;
-        u.S = wsf(c, c->off_S);
-        u.nominal_out = wsf(c, c->off_mu);
-        u.u0_out = d_u0_out;
-        u.status = (int*)wsf(c, c->off_status);
-        if ((s = hip_check(c, mppi::launch_update(Pp, u, c->stream), "proposal update launch"))) return s;
-        c->step += 1;
-        return MPPI_OK;
-    }
+    const bool gated = gate == MPPI_PROPOSAL_GATE_COST;
     float* costs = wsf(c, c->off_costs);
-    if ((s = rollout(c, d_x0, nullptr, costs, nullptr))) return s;
-    if ((s = update(c, costs, nullptr, nullptr, wsf(c, c->off_mu), d_u0_out, nullptr))) return s;
+    if (gated) {
+        if (!c->side) return fail(c, MPPI_ESTATE, "no side stream (bind the controller again)");
+        if ((s = hip_check(c, hipEventRecord(c->ev_fork, c->stream), "fork record")) ||
+            (s = hip_check(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "fork wait")) ||
+            (s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, Pp, a, c->side),
+                           "proposal rollout launch")) ||
+            (s = hip_check(c, hipEventRecord(c->ev_join, c->side), "join record")))
+            return s;
+        mppi_status rs = rollout(c, d_x0, nullptr, costs, nullptr);
+        // join before returning, also after a failed launch, so that no work is left on the side stream
+        if ((s = hip_check(c, hipStreamWaitEvent(c->stream, c->ev_join, 0), "join wait"))) return s;
+        if (rs) return rs;
+    } else if ((s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, Pp, a, c->stream),
+                              "proposal rollout launch"))) {
+        return s;
+    }
+    const mppi::DevParams P = dev_params(c);
+    mppi::UpdateArgs u{};
+    u.costs = costs;  // the plain step (read only when the gate rejects)
+    u.eps = wsf(c, c->off_eps);
+    u.eps_sn = 1;
+    u.eps_sd = c->p.K;
+    u.mu = wsf(c, c->off_mu);
+    u.prop = 1;
+    u.Kp = kp;
+    u.gate = gated ? costs_p : nullptr;
+    u.costs_p = costs_p;
+    u.eps_p = e;
+    u.mu_p = d_center;
+    u.pstats = (int*)wsf(c, c->off_pstats);
+    u.S = wsf(c, c->off_S);
+    u.nominal_out = wsf(c, c->off_mu);
+    u.u0_out = d_u0_out;
+    u.status = (int*)wsf(c, c->off_status);
+    if ((s = hip_check(c, mppi::launch_update(P, u, c->stream), "proposal update launch"))) return s;
     c->step += 1;
     return MPPI_OK;
 }
@@ -715,8 +754,16 @@ mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, int gat
 mppi_status mppi_proposal_stats(mppi_ctx* c, int* accepted, int* steps)
 {
     if (!c) return fail(nullptr, MPPI_EINVAL, "null context");
-    if (accepted) *accepted = c->prop_accepted;
-    if (steps) *steps = c->prop_steps;
+    int st[2] = {0, 0};
+    if (c->ws) {
+        mppi_status s;
+        if ((s = hip_check(c, hipMemcpyAsync(st, wsf(c, c->off_pstats), sizeof(st), hipMemcpyDeviceToHost, c->stream),
+                           "read proposal counters")) ||
+            (s = hip_check(c, hipStreamSynchronize(c->stream), "synchronise")))
+            return s;
+    }
+    if (accepted) *accepted = st[0];
+    if (steps) *steps = st[1];
     return MPPI_OK;
 }
 

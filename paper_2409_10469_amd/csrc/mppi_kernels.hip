@@ -180,16 +180,20 @@ __device__ __forceinline__ float block_reduce(float v, float* sh, bool is_min)
     return r;
 }
 
-__global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, const float* __restrict__ costs,
-                                                             const float* __restrict__ eps, int eps_sn, int eps_sd,
-                                                             const float* mu, const float* __restrict__ Sshift,
-                                                             float* knots_out, float* nominal_out, float* u0_out,
-                                                             float* __restrict__ weights_out, int* status)
+__global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, UpdateArgs a)
 {
     __shared__ float sh[kUpdWaves];
     __shared__ float acc_w[kMaxKnots][kUpdWaves];
     __shared__ float mup[kMaxKnots];
-    const int j = blockIdx.x, t = threadIdx.x, nk = P.nk, K = P.K;
+    const int j = blockIdx.x, t = threadIdx.x, nk = P.nk;
+    // a proposal step whose gate accepts updates over the proposal's samples
+    const bool prop = a.prop && (!a.gate || (fabsf(a.gate[0]) <= 3.0e38f && a.gate[0] <= a.gate[1]));
+    const int K = prop ? a.Kp : P.K;
+    const float* __restrict__ costs = prop ? a.costs_p : a.costs;
+    const float* __restrict__ eps = prop ? a.eps_p : a.eps;
+    const int eps_sn = prop ? 12 * nk : a.eps_sn, eps_sd = prop ? 1 : a.eps_sd;
+    const float* mu = prop ? a.mu_p : a.mu;
+    const float sigma = prop ? 1.f : P.sigma;
     float lmin = __int_as_float(0x7f800000);
     for (int n = t; n < K; n += kUpdThreads) {
         const float c = costs[n];
@@ -216,34 +220,40 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, const 
     s = block_reduce(s, sh, false);
 #pragma unroll
     for (int i = 0; i < kMaxKnots; ++i) {
-        const float a = wave_reduce(acc[i], false);
-        if ((t & 63) == 0) acc_w[i][t >> 6] = a;
+        const float r = wave_reduce(acc[i], false);
+        if ((t & 63) == 0) acc_w[i][t >> 6] = r;
     }
     __syncthreads();
     if (t < nk) {
-        float a = acc_w[t][0];
-        for (int w = 1; w < kUpdWaves; ++w) a += acc_w[t][w];
+        float acc_t = acc_w[t][0];
+        for (int w = 1; w < kUpdWaves; ++w) acc_t += acc_w[t][w];
         const float m = mu[j * nk + t];
-        mup[t] = none ? m : m + P.sigma * (a / s);
+        mup[t] = none ? m : m + sigma * (acc_t / s);
     }
     __syncthreads();
     if (t < nk) {
-        if (knots_out) knots_out[j * nk + t] = mup[t];
-        if (nominal_out) {
+        if (a.knots_out) a.knots_out[j * nk + t] = mup[t];
+        if (a.nominal_out) {
             float v = 0.f;
-            for (int l = 0; l < nk; ++l) v += Sshift[t * nk + l] * mup[l];
-            nominal_out[j * nk + t] = v;
+            for (int l = 0; l < nk; ++l) v += a.S[t * nk + l] * mup[l];
+            a.nominal_out[j * nk + t] = v;
         }
     }
-    if (t == 0 && u0_out) u0_out[j] = mup[0];
-    if (j == 0 && weights_out) {
+    if (t == 0 && a.u0_out) a.u0_out[j] = mup[0];
+    if (j == 0 && a.weights_out) {
         const float is = none ? 0.f : 1.f / s;
         for (int n = t; n < K; n += kUpdThreads) {
             const float c = costs[n];
-            weights_out[n] = (!none && fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) * is : 0.f;
+            a.weights_out[n] = (!none && fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) * is : 0.f;
         }
     }
-    if (j == 0 && t == 0 && status) status[0] = none ? 1 : 0;
+    if (j == 0 && t == 0) {
+        if (a.status) a.status[0] = none ? 1 : 0;
+        if (a.prop && a.pstats) {
+            a.pstats[0] += prop ? 1 : 0;
+            a.pstats[1] += 1;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -478,8 +488,7 @@ hipError_t launch_rollout(const DevModelF& Mf, const DevModelD& Md, int arith, c
 
 hipError_t launch_update(const DevParams& P, const UpdateArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(update_kernel, dim3(12), dim3(kUpdThreads), 0, st, P, a.costs, a.eps, a.eps_sn, a.eps_sd, a.mu,
-                       a.S, a.knots_out, a.nominal_out, a.u0_out, a.weights_out, a.status);
+    hipLaunchKernelGGL(update_kernel, dim3(12), dim3(kUpdThreads), 0, st, P, a);
     return hipGetLastError();
 }
 

@@ -42,6 +42,18 @@ struct UpdateArgs {
     float* u0_out;         // first control (12) or null
     float* weights_out;    // K or null
     int* status;           // 1 if no finite cost
+    // learned-proposal step (prop = 1): when the gate accepts, the update runs over the
+    // proposal's Kp samples instead (costs_p, noise eps_p[n * D + d], centre mu_p, unit
+    // scale); the gate accepts when gate is null (ungated) or gate[0] (the centre's cost)
+    // is finite and not above gate[1] (the nominal's).  pstats, if set, counts
+    // [accepted, proposal steps].
+    int prop;
+    int Kp;
+    const float* gate;
+    const float* costs_p;
+    const float* eps_p;
+    const float* mu_p;
+    int* pstats;
 };
 
 hipError_t launch_sample(const DevParams& P, int D, float* eps, uint32_t* raw, hipStream_t st);

@@ -272,7 +272,9 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024, 2048, 4096), K_learned=10
         costs = [r[0] for r in res]
         acc = sum(r[2] for r in res)
         n = sum(r[3] for r in res)
-        samples = (n * kp + (n - acc) * K_learned) / max(n, 1)
+        # the gated step rolls out the proposal and the plain step's K samples side by side
+        # and lets the update pick one set; the ungated step rolls out the proposal only
+        samples = float(kp + K_learned) if gate == "cost" else float(kp)
         out["learned_" + gate] = dict(mean=float(np.mean(costs)), ci95=ci95(costs), costs=costs, k_prop=kp,
                                       K_fallback=K_learned,
                                       accepted=acc, steps=n, acceptance=acc / max(n, 1), samples_per_step=samples,

@@ -91,6 +91,14 @@ hipError_t launch_update(const DevParams& P, const UpdateArgs& a, hipStream_t)
     CHK(a.u0_out, 48, "update first control");
     CHK(a.weights_out, 4ull * P.K, "update weights");
     range_check(a.status, 4, "update status");
+    if (a.prop) {
+        if (a.Kp < 2 || a.Kp > P.K) fail("proposal sample count");
+        range_check(a.costs_p, 4ull * a.Kp, "update proposal costs");
+        range_check(a.eps_p, 4ull * a.Kp * D, "update proposal noise");
+        range_check(a.mu_p, 4ull * D, "update proposal centre");
+        CHK(a.gate, 8, "update gate costs");
+        CHK(a.pstats, 8, "update proposal counters");
+    }
     return hipSuccess;
 }
 
