@@ -204,8 +204,8 @@ def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="co
     from the seeded stance; returns the
     episode cost sum dt * l, the final state and the proposal counters.  With a list
     `lat`, appends each control step's latency in ms: stream events around the step, so
-    the time runs from the moment the plant state is on the device to the first control,
-    including any host round trip of the cost gate."""
+    the time runs from the moment the plant state is on the device to the first control
+    (with the cost gate: both rollouts, side by side, and the gated update)."""
     import torch
     from . import binding as Bd
     ctl = Bd.Controller(model, dict(p, seed=seed, arith=arith))
