@@ -340,7 +340,10 @@ class Controller:
         self._s(lib().mppi_set_tracking_cost(self.h, C.byref(tracking_struct(c))))
 
     def step_proposal(self, x0, center, sd, k_prop, u0=None, gate="cost"):
-        """One control step sampling k_prop knots around an explicit proposal (mean, std)."""
+        """One control step sampling k_prop knots around an explicit proposal (mean, std).
+        gate "cost": the plain step's K samples are rolled out beside the proposal's and the
+        update keeps the proposal only if its centre costs no more than the nominal (decided
+        on the device); "none": the proposal's samples alone."""
         import torch
         u0 = u0 if u0 is not None else torch.empty(12, dtype=torch.float32, device="cuda")
         self._s(lib().mppi_step_proposal(self.h, _ptr(x0), _ptr(center), _ptr(sd), int(k_prop), GATE[gate],
@@ -356,6 +359,7 @@ class Controller:
         self._policy = policy  # keep alive while in use
 
     def proposal_stats(self):
+        """(accepted, proposal steps): device counters, read with a synchronisation."""
         a, n = C.c_int(), C.c_int()
         self._s(lib().mppi_proposal_stats(self.h, C.byref(a), C.byref(n)))
         return a.value, n.value
