@@ -335,6 +335,40 @@ def test_proposal_step_on_plain_kernels_matches_oracle(B, accept, gate):
     assert np.abs(nom - onom).max() <= KNOT_TOL
 
 
+@pytest.mark.parametrize("accept", [True, False])
+def test_gated_step_is_bitwise_the_chosen_branch(B, accept):
+    """The cost gate is decided on the device after both rollouts ran side by side (the
+    proposal's on an internal stream): an accepted gated step equals the ungated step bit
+    for bit, a rejected one equals the plain step bit for bit, and a second gated step
+    repeats the first exactly."""
+    md, p, orc, ctl = _ctl(B)
+    D = 12 * p["nk"]
+    rng = np.random.default_rng(2)
+    mu = f32(W.stance_knots(p["nk"]))
+    x0 = _dev(W.initial_state(3))
+    if accept:
+        nominal = f32(mu + 0.5)
+        center = f32(mu + 0.02 * rng.normal(size=D))
+    else:
+        nominal = mu
+        center = f32(mu + 0.8)
+    sd = _dev(rng.uniform(0.05, 0.2, D))
+    c = _dev(center)
+    runs = []
+    for mode in ("cost", "cost", "ref"):
+        ctl.set_nominal(_dev(nominal))
+        ctl.set_step(5)
+        if mode == "ref":
+            u0 = ctl.step_proposal(x0, c, sd, 16, gate="none") if accept else ctl.step(x0)
+        else:
+            u0 = ctl.step_proposal(x0, c, sd, 16, gate="cost")
+        runs.append((u0.cpu().numpy(), ctl.get_nominal().cpu().numpy()))
+    acc, steps = ctl.proposal_stats()
+    assert steps == (3 if accept else 2) and acc == (3 if accept else 0)
+    for u, n in runs[1:]:
+        assert np.array_equal(u, runs[0][0]) and np.array_equal(n, runs[0][1])
+
+
 def test_learned_step_on_plain_kernels_matches_oracle_chain(B):
     """mppi_step through the policy: features, BF16 forward, head and proposal step against
     the oracle's features, BF16-operand forward, head and proposal step."""
