@@ -309,6 +309,7 @@ def bench_serving(args):
         "queueing_delay_steps": {"mean": float(qd.mean()) if qd.size else 0.0,
                                  "p99": float(np.percentile(qd, 99)) if qd.size else 0.0},
         "autotune": {"blocks_per_cu": r["tune"][0], "order": "longest_first" if r["tune"][1] else "admission",
+                     "launch": "one kernel for every scene" if r["tune"][3] else "one kernel per scene",
                      "ms": r["tune"][2]} if r["tune"] else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None},

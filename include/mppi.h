@@ -280,8 +280,18 @@ mppi_status mppi_batch_record(mppi_batch *b, int id, float *d_rec, int cap);
 mppi_status mppi_batch_step(mppi_batch *b);
 /* persistent grid = blocks_per_cu x compute units; order 1 = longest horizon first */
 mppi_status mppi_batch_set_tuning(mppi_batch *b, int blocks_per_cu, int order);
-/* times `steps` control steps for each candidate tuning on the current instances and
- * keeps the fastest (advances every instance by the steps it runs) */
+/* launch shape of the step's graph: mode 0 runs one persistent kernel per scene in use,
+ * one after another; mode 1 runs a single persistent kernel over one queue that holds
+ * every scene's tiles (each tile branches to its scene's code), so no scene's tail of
+ * partly idle compute units is paid separately.  Results are the same in both modes.
+ * EINVAL for another mode; takes effect at the next step (the graph is re-captured). */
+mppi_status mppi_batch_set_launch_mode(mppi_batch *b, int mode);
+/* the current blocks_per_cu, order and launch mode (NULL to skip) */
+mppi_status mppi_batch_get_tuning(mppi_batch *b, int *blocks_per_cu, int *order, int *mode);
+/* times `steps` control steps (after one untimed step) for each of the 16 candidate
+ * tunings, blocks_per_cu in {2, 4, 8, 16} x order x launch mode, on the current instances
+ * and keeps the fastest (advances every instance by the 16 (steps + 1) steps it runs);
+ * the chosen launch mode is read back with mppi_batch_get_tuning */
 mppi_status mppi_batch_autotune(mppi_batch *b, int steps, int *best_blocks_per_cu, int *best_order, float *best_ms);
 /* synchronises and copies one instance's state, first control, nominal, accumulated
  * cost and step counter to HOST memory (NULL to skip) */

@@ -487,6 +487,8 @@ class Batch:
                 "mppi_batch_step": (C.c_int, [vp]),
                 "mppi_batch_record": (C.c_int, [vp, C.c_int, vp, C.c_int]),
                 "mppi_batch_set_tuning": (C.c_int, [vp, C.c_int, C.c_int]),
+                "mppi_batch_set_launch_mode": (C.c_int, [vp, C.c_int]),
+                "mppi_batch_get_tuning": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
                 "mppi_batch_autotune": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                                   C.POINTER(C.c_float)]),
                 "mppi_batch_read": (C.c_int, [vp, C.c_int, vp, vp, vp, vp, vp]),
@@ -573,7 +575,19 @@ class Batch:
     def set_tuning(self, blocks_per_cu, order):
         self._chk(self.L.mppi_batch_set_tuning(self.h, blocks_per_cu, order))
 
+    def set_launch_mode(self, mode):
+        """0: one persistent kernel per scene; 1: one kernel over a queue of every scene's tiles."""
+        self._chk(self.L.mppi_batch_set_launch_mode(self.h, int(mode)))
+
+    def tuning(self):
+        """(blocks_per_cu, order, launch mode) now in effect."""
+        bb, bo, bm = C.c_int(), C.c_int(), C.c_int()
+        self._chk(self.L.mppi_batch_get_tuning(self.h, C.byref(bb), C.byref(bo), C.byref(bm)))
+        return bb.value, bo.value, bm.value
+
     def autotune(self, steps=3):
+        """Times the 16 candidate tunings (the launch mode too) and keeps the fastest;
+        returns (blocks_per_cu, order, ms per step); tuning() also gives the mode."""
         bb, bo, ms = C.c_int(), C.c_int(), C.c_float()
         self._chk(self.L.mppi_batch_autotune(self.h, steps, C.byref(bb), C.byref(bo), C.byref(ms)))
         return bb.value, bo.value, ms.value

@@ -44,6 +44,7 @@ void spline_matrices(int nk, int H, double dt, int basis, std::vector<double>& B
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kQueues = 5;  // four scene queues and the combined one
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // first-fit allocator over [base, base + size)
@@ -119,7 +120,8 @@ struct mppi_batch {
     hipStream_t cap_stream = nullptr;  // used only to capture the graph
     size_t o_table, o_models, o_pool;
     size_t o_prows, o_feat, o_pout, o_rtab;  // proposal rows, features, network outputs, resampling
-    size_t o_tiles[4], o_total[4], o_head[4], o_exited[4];  // one work queue per scene
+    // one work queue per scene, then the combined queue of the single-launch mode
+    size_t o_tiles[kQueues], o_total[kQueues], o_head[kQueues], o_exited[kQueues];
     int scene_tiles[4] = {0, 0, 0, 0};
     bool scene_used[4] = {false, false, false, false};
     Arena arena;
@@ -132,6 +134,7 @@ struct mppi_batch {
     bool dirty = true, upload_pending = false;
     int total_tiles = 0, n_live = 0;
     int grid = 0, blocks_per_cu = 4, order = 1;
+    int mode = 0;  // 0: one persistent kernel per scene in use; 1: one kernel for every scene
     mppi_policy* policy = nullptr;  // shared by every proposal instance
     prop::BatchPropRow* h_prows = nullptr;
     int n_prop = 0;
@@ -189,6 +192,7 @@ mppi_status upload_table(mppi_batch* b)
     if (b->upload_pending && (s = bhip(b, hipEventSynchronize(b->upload_done), "wait upload"))) return s;
     const int tiles_per_scene = b->max_inst * (4096 / mppi::kTileSamples);
     int row = 0, all_tiles = 0, np = 0;
+    std::vector<int> row_inst;  // admission index of each table row
     for (int sc = 0; sc < 4; ++sc) {
         std::vector<int> ids;
         for (int i = 0; i < b->max_inst; ++i)
@@ -240,11 +244,28 @@ mppi_status upload_table(mppi_batch* b)
             }
             for (int k = 0; k < d.ntiles; ++k) map[tile + k] = row;
             tile += d.ntiles;
+            row_inst.push_back(i);
             ++row;
         }
         map[tiles_per_scene] = tile;  // the count, staged after the map
         b->scene_tiles[sc] = tile;
         all_tiles += tile;
+    }
+    // the combined queue: every tile of every row as (row << 8 | tile of the row), rows in
+    // admission order or longest horizon first over all scenes (K <= 4096 keeps the tile
+    // index below 256)
+    int* all_map = b->h_tiles + 4 * (tiles_per_scene + 1);
+    {
+        std::vector<int> rows(row);
+        for (int r = 0; r < row; ++r) rows[r] = r;
+        std::sort(rows.begin(), rows.end(), [&](int x, int y) {
+            if (b->order == 1 && b->h_table[x].P.H != b->h_table[y].P.H) return b->h_table[x].P.H > b->h_table[y].P.H;
+            return row_inst[x] < row_inst[y];
+        });
+        int tile = 0;
+        for (int r : rows)
+            for (int k = 0; k < b->h_table[r].ntiles; ++k) all_map[tile++] = (r << 8) | k;
+        all_map[tiles_per_scene] = tile;
     }
     b->total_tiles = all_tiles;
     b->n_live = row;
@@ -253,13 +274,13 @@ mppi_status upload_table(mppi_batch* b)
     if ((s = bhip(b, hipMemcpyAsync(wsp(b, b->o_table), b->h_table, sizeof(mppi::InstDesc) * std::max(row, 1),
                                     hipMemcpyHostToDevice, st), "upload table")))
         return s;
-    for (int sc = 0; sc < 4; ++sc) {
-        const int* map = b->h_tiles + sc * (tiles_per_scene + 1);
-        if (b->scene_tiles[sc] &&
-            (s = bhip(b, hipMemcpyAsync(wsp(b, b->o_tiles[sc]), map, sizeof(int) * b->scene_tiles[sc],
-                                        hipMemcpyHostToDevice, st), "upload tiles")))
+    for (int q = 0; q < kQueues; ++q) {
+        const int* map = b->h_tiles + q * (tiles_per_scene + 1);
+        const int n = q < 4 ? b->scene_tiles[q] : all_tiles;
+        if (n && (s = bhip(b, hipMemcpyAsync(wsp(b, b->o_tiles[q]), map, sizeof(int) * n, hipMemcpyHostToDevice, st),
+                           "upload tiles")))
             return s;
-        if ((s = bhip(b, hipMemcpyAsync(wsp(b, b->o_total[sc]), map + tiles_per_scene, sizeof(int),
+        if ((s = bhip(b, hipMemcpyAsync(wsp(b, b->o_total[q]), map + tiles_per_scene, sizeof(int),
                                         hipMemcpyHostToDevice, st), "upload tile count")))
             return s;
     }
@@ -288,9 +309,26 @@ mppi_status capture(mppi_batch* b)
         return s;
     hipStream_t st = b->cap_stream;
     if ((s = bhip(b, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture"))) return s;
-    // the scenes' kernels run one after another in the graph
+    // the scenes' kernels run one after another in the graph, or one kernel takes the
+    // combined queue of every scene's tiles
     hipError_t le = hipSuccess;
-    for (int sc = 0; sc < 4 && le == hipSuccess; ++sc) {
+    if (b->mode == 1) {
+        const int q = 4;
+        if (b->arith == 1) {
+            mppi::BatchArgs<float> a{(const mppi::InstDesc*)wsp(b, b->o_table),
+                                     (const mppi::ModelT<float>*)wsp(b, b->o_models),
+                                     (const int*)wsp(b, b->o_tiles[q]), (const int*)wsp(b, b->o_total[q]),
+                                     (int*)wsp(b, b->o_head[q]), (int*)wsp(b, b->o_exited[q])};
+            le = mppi::launch_batch_all(1, &a, b->grid, lds, st);
+        } else {
+            mppi::BatchArgs<double> a{(const mppi::InstDesc*)wsp(b, b->o_table),
+                                      (const mppi::ModelT<double>*)wsp(b, b->o_models),
+                                      (const int*)wsp(b, b->o_tiles[q]), (const int*)wsp(b, b->o_total[q]),
+                                      (int*)wsp(b, b->o_head[q]), (int*)wsp(b, b->o_exited[q])};
+            le = mppi::launch_batch_all(0, &a, b->grid, lds, st);
+        }
+    }
+    for (int sc = 0; sc < 4 && le == hipSuccess && b->mode == 0; ++sc) {
         if (!b->scene_used[sc]) continue;
         hipStream_t ss = st;
         if (b->arith == 1) {
@@ -362,7 +400,7 @@ mppi_status mppi_batch_create(int max_instances, int max_horizon, int max_hf_cel
     const int max_tiles = max_instances * (4096 / mppi::kTileSamples);
     if (hipHostMalloc((void**)&b->h_table, sizeof(mppi::InstDesc) * max_instances, hipHostMallocDefault) !=
             hipSuccess ||
-        hipHostMalloc((void**)&b->h_tiles, sizeof(int) * 4 * (max_tiles + 1), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_tiles, sizeof(int) * kQueues * (max_tiles + 1), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_prows, sizeof(prop::BatchPropRow) * max_instances, hipHostMallocDefault) !=
             hipSuccess ||
         hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming) != hipSuccess) {
@@ -389,7 +427,8 @@ void mppi_batch_destroy(mppi_batch* b)
 size_t mppi_batch_control_bytes(int max_instances, int arith)
 {
     const int max_tiles = max_instances * (4096 / mppi::kTileSamples);
-    return align_up(sizeof(mppi::InstDesc) * max_instances) + 4 * (align_up(sizeof(int) * max_tiles) + 3 * kAlign) +
+    return align_up(sizeof(mppi::InstDesc) * max_instances) +
+           kQueues * (align_up(sizeof(int) * max_tiles) + 3 * kAlign) +
            align_up(model_size(arith) * MPPI_BATCH_MAX_MODELS) + prop_bytes(max_instances);
 }
 
@@ -406,13 +445,13 @@ mppi_status mppi_batch_bind(mppi_batch* b, void* ws, size_t bytes, void* stream)
     size_t o = 0;
     b->o_table = o; o += align_up(sizeof(mppi::InstDesc) * b->max_inst);
     const size_t queues = o;
-    for (int sc = 0; sc < 4; ++sc) {
-        b->o_total[sc] = o; o += kAlign;
-        b->o_head[sc] = o; o += kAlign;
-        b->o_exited[sc] = o; o += kAlign;
+    for (int q = 0; q < kQueues; ++q) {
+        b->o_total[q] = o; o += kAlign;
+        b->o_head[q] = o; o += kAlign;
+        b->o_exited[q] = o; o += kAlign;
     }
-    for (int sc = 0; sc < 4; ++sc) {
-        b->o_tiles[sc] = o;
+    for (int q = 0; q < kQueues; ++q) {
+        b->o_tiles[q] = o;
         o += align_up(sizeof(int) * b->max_inst * (4096 / mppi::kTileSamples));
     }
     b->o_models = o; o += align_up(model_size(b->arith) * MPPI_BATCH_MAX_MODELS);
@@ -433,7 +472,7 @@ mppi_status mppi_batch_bind(mppi_batch* b, void* ws, size_t bytes, void* stream)
     hipStream_t st = b->stream;
     mppi_status s;
     // zero the queue heads, exit counters and tile counts (plain fill before any capture)
-    if ((s = bhip(b, hipMemsetAsync(wsp(b, queues), 0, 4 * 3 * kAlign, st), "clear queues"))) return s;
+    if ((s = bhip(b, hipMemsetAsync(wsp(b, queues), 0, kQueues * 3 * kAlign, st), "clear queues"))) return s;
     return bhip(b, hipStreamSynchronize(st), "bind synchronise");
 }
 
@@ -614,6 +653,24 @@ mppi_status mppi_batch_set_tuning(mppi_batch* b, int blocks_per_cu, int order)
     return MPPI_OK;
 }
 
+mppi_status mppi_batch_set_launch_mode(mppi_batch* b, int mode)
+{
+    if (!b || (mode != 0 && mode != 1))
+        return bfail(b, MPPI_EINVAL, "launch mode 0 (one kernel per scene) or 1 (one kernel for every scene)");
+    if (mode != b->mode) drop_graph(b);
+    b->mode = mode;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_get_tuning(mppi_batch* b, int* blocks_per_cu, int* order, int* mode)
+{
+    if (!b) return bfail(nullptr, MPPI_EINVAL, "null batch");
+    if (blocks_per_cu) *blocks_per_cu = b->blocks_per_cu;
+    if (order) *order = b->order;
+    if (mode) *mode = b->mode;
+    return MPPI_OK;
+}
+
 mppi_status mppi_batch_autotune(mppi_batch* b, int steps, int* best_blocks_per_cu, int* best_order,
                                 float* best_ms)
 {
@@ -621,7 +678,7 @@ mppi_status mppi_batch_autotune(mppi_batch* b, int steps, int* best_blocks_per_c
     if (!b->ws) return bfail(b, MPPI_ESTATE, "no workspace bound");
     const int cand_blocks[] = {2, 4, 8, 16};
     float best = 1e30f;
-    int bb = b->blocks_per_cu, bo = b->order;
+    int bb = b->blocks_per_cu, bo = b->order, bm = b->mode;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess) return bfail(b, MPPI_EHIP, "event create");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -629,28 +686,29 @@ mppi_status mppi_batch_autotune(mppi_batch* b, int steps, int* best_blocks_per_c
         return bfail(b, MPPI_EHIP, "event create");
     }
     mppi_status s = MPPI_OK;
-    for (int order = 0; order < 2 && !s; ++order)
-        for (int cb : cand_blocks) {
-            if ((s = mppi_batch_set_tuning(b, cb, order))) break;
-            if ((s = mppi_batch_step(b))) break;  // warm-up and capture
-            if ((s = bhip(b, hipEventRecord(e0, b->stream), "autotune event"))) break;
-            for (int i = 0; i < steps && !s; ++i) s = mppi_batch_step(b);
-            if (s || (s = bhip(b, hipEventRecord(e1, b->stream), "autotune event"))) break;
-            float ms = 0.f;
-            if ((s = bhip(b, hipEventSynchronize(e1), "autotune wait")) ||
-                (s = bhip(b, hipEventElapsedTime(&ms, e0, e1), "autotune timing")))
-                break;
-            ms /= steps;
-            if (ms < best) {
-                best = ms;
-                bb = cb;
-                bo = order;
-            }
+    for (int c = 0; c < 16 && !s; ++c) {
+        const int mode = c >> 3, order = (c >> 2) & 1, cb = cand_blocks[c & 3];
+        if ((s = mppi_batch_set_launch_mode(b, mode)) || (s = mppi_batch_set_tuning(b, cb, order))) break;
+        if ((s = mppi_batch_step(b))) break;  // warm-up and capture
+        if ((s = bhip(b, hipEventRecord(e0, b->stream), "autotune event"))) break;
+        for (int i = 0; i < steps && !s; ++i) s = mppi_batch_step(b);
+        if (s || (s = bhip(b, hipEventRecord(e1, b->stream), "autotune event"))) break;
+        float ms = 0.f;
+        if ((s = bhip(b, hipEventSynchronize(e1), "autotune wait")) ||
+            (s = bhip(b, hipEventElapsedTime(&ms, e0, e1), "autotune timing")))
+            break;
+        ms /= steps;
+        if (ms < best) {
+            best = ms;
+            bb = cb;
+            bo = order;
+            bm = mode;
         }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (s) return s;
-    if ((s = mppi_batch_set_tuning(b, bb, bo))) return s;
+    if ((s = mppi_batch_set_launch_mode(b, bm)) || (s = mppi_batch_set_tuning(b, bb, bo))) return s;
     if (best_blocks_per_cu) *best_blocks_per_cu = bb;
     if (best_order) *best_order = bo;
     if (best_ms) *best_ms = best;

@@ -389,6 +389,48 @@ __device__ __forceinline__ void instance_tail(const InstDesc& I, const DevParams
     }
 }
 
+// one tile of one instance: stage its basis (and heightfield) in LDS, roll out its 16
+// samples; the workgroup that completes the instance's last tile runs its tail
+template <int SCENE, typename R>
+__device__ __forceinline__ void batch_tile(const InstDesc& I, const ModelT<R>& M, int n_base, unsigned char* lds,
+                                           float* sMup, int* s_last)
+{
+    DevParams P = I.P;
+    P.step = I.step[0];
+    R* sB = reinterpret_cast<R*>(lds);
+    R* sTh = sB + P.H * P.nk;
+    float* sHF = reinterpret_cast<float*>(sTh + 64 * 3 * kMaxKnots);
+    stage_lds(P, SCENE, I.hf_cells, I.B, I.hf, sB, sHF);
+    __syncthreads();
+    // Philox noise drawn here and stored for the tail, or the given dimension-major noise
+    const float* ein = I.explicit_eps ? I.eps : nullptr;
+    rollout_samples<SCENE, R>(M, P, sB, sHF, sTh, I.mu, I.x, ein, 1, P.K, ein ? nullptr : I.eps, I.costs, nullptr,
+                              n_base);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) *s_last = (atomicAdd(I.done, 1) == I.ntiles - 1);
+    __syncthreads();
+    if (*s_last) {
+        __threadfence();
+        instance_tail<SCENE, R>(I, P, M, sHF, sMup);
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// the queue is drained: the last workgroup to find it empty resets it for the next launch
+template <typename R>
+__device__ __forceinline__ void batch_exit(const BatchArgs<R>& a)
+{
+    if (threadIdx.x == 0) {
+        if (atomicAdd(a.exited, 1) == (int)gridDim.x - 1) {
+            *a.head = 0;
+            *a.exited = 0;
+            __threadfence();
+        }
+    }
+}
+
 // one persistent kernel per scene: its own queue of that scene's tiles
 template <int SCENE, typename R>
 __global__ __launch_bounds__(64) void batch_kernel(BatchArgs<R> a)
@@ -437,6 +479,36 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchArgs<R> a)
             __threadfence();
         }
     }
+}
+
+// one persistent kernel for every scene: a single queue whose entries pack the instance
+// row and the tile's index inside its instance (row << 8 | tile); each tile branches to
+// its scene's code (uniform over the workgroup)
+template <typename R>
+__global__ __launch_bounds__(64) void batch_kernel_all(BatchArgs<R> a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int s_tile, s_last;
+    __shared__ float sMup[12 * kMaxKnots];
+    const int total = *a.total_tiles;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(a.head, 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (t >= total) break;
+        const int packed = __builtin_amdgcn_readfirstlane(a.tile_map[t]);
+        const InstDesc& I = a.inst[packed >> 8];
+        const ModelT<R>& M = a.models[__builtin_amdgcn_readfirstlane(I.model)];
+        const int n_base = (packed & 255) * kTileSamples;
+        switch (__builtin_amdgcn_readfirstlane(I.scene)) {
+        case 0: batch_tile<0, R>(I, M, n_base, lds_raw, sMup, &s_last); break;
+        case 1: batch_tile<1, R>(I, M, n_base, lds_raw, sMup, &s_last); break;
+        case 2: batch_tile<2, R>(I, M, n_base, lds_raw, sMup, &s_last); break;
+        default: batch_tile<3, R>(I, M, n_base, lds_raw, sMup, &s_last); break;
+        }
+    }
+    batch_exit(a);
 }
 
 // ---------------------------------------------------------------------------------
@@ -531,6 +603,17 @@ static hipError_t launch_batch_t(int scene, const BatchArgs<R>& a, int grid, siz
     case 3: hipLaunchKernelGGL((batch_kernel<3, R>), dim3(grid), dim3(64), lds, st, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_all(int arith, const void* args, int grid, size_t lds, hipStream_t st)
+{
+    if (arith == 1)
+        hipLaunchKernelGGL(batch_kernel_all<float>, dim3(grid), dim3(64), lds, st,
+                           *static_cast<const BatchArgs<float>*>(args));
+    else
+        hipLaunchKernelGGL(batch_kernel_all<double>, dim3(grid), dim3(64), lds, st,
+                           *static_cast<const BatchArgs<double>*>(args));
     return hipGetLastError();
 }
 

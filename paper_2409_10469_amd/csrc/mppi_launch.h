@@ -107,5 +107,7 @@ struct BatchArgs {
 
 hipError_t launch_batch(int arith, int scene, const void* args /* BatchArgs<R> */, int grid, size_t lds,
                         hipStream_t st);
+// one persistent kernel for all scenes; its tile map entries are (row << 8 | tile of the row)
+hipError_t launch_batch_all(int arith, const void* args /* BatchArgs<R> */, int grid, size_t lds, hipStream_t st);
 
 }  // namespace mppi

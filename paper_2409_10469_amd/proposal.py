@@ -329,10 +329,12 @@ def evaluate_batched(policy, n_inst=256, K_plain=(256, 1024), k_prop=256, steps=
     runs = [("plain_K%d" % K, K, False) for K in K_plain] + [("learned_K%d" % k_prop, k_prop, True)]
     for name, K, learned in runs:
         tb, _ = make(K, learned)
-        bpc, order, _ = tb.autotune(steps=3)
+        tb.autotune(steps=3)
+        bpc, order, mode = tb.tuning()
         del tb
         batch, ids = make(K, learned)
         batch.set_tuning(bpc, order)
+        batch.set_launch_mode(mode)
         ev = []
         t0 = time.perf_counter()
         for _ in range(steps):

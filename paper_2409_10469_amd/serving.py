@@ -112,7 +112,7 @@ class ServingSim:
             self.step_no += 1
         if autotune:
             self.stream.synchronize()
-            tune = self.batch.autotune(steps=1)
+            tune = self.batch.autotune(steps=1) + (self.batch.tuning()[2],)
         self.stream.synchronize()
         lat, host_ms, work, flops, live = [], [], 0, 0.0, []
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]

@@ -183,12 +183,27 @@ static void batch(mppi_model* flat, mppi_model* terrain, mppi_model* push, mppi_
         if (s.slot == sp) REFUSED(mppi_batch_set_proposal(b, id, pol, cmd, org));  // 50-float state
     }
     for (int k = 0; k < 3; ++k) OK(mppi_batch_step(b));
+    REFUSED(mppi_batch_set_launch_mode(b, 2));
+    OK(mppi_batch_set_launch_mode(b, 1));  // one kernel over the combined queue
+    for (int order = 0; order < 2; ++order) {
+        OK(mppi_batch_set_tuning(b, 4, order));
+        OK(mppi_batch_step(b));
+    }
+    int tb = 0, to = 0, tm = 0;
+    OK(mppi_batch_get_tuning(b, &tb, &to, &tm));
+    if (tb != 4 || to != 1 || tm != 1) {
+        std::printf("BAD tuning read back %d %d %d\n", tb, to, tm);
+        ++g_bad;
+    }
+    OK(mppi_batch_set_launch_mode(b, 0));
     OK(mppi_batch_set_proposal(b, ids[0], nullptr, nullptr, nullptr));
     OK(mppi_batch_remove(b, ids[1]));
     OK(mppi_batch_record(b, ids[2], devf(7 * (37 + 48)), 7));
     int bb = 0, bo = 0;
     float ms = 0;
     OK(mppi_batch_autotune(b, 1, &bb, &bo, &ms));
+    for (int k = 0; k < 2; ++k) OK(mppi_batch_step(b));
+    OK(mppi_batch_set_launch_mode(b, 1));  // after a removal and a proposal change
     for (int k = 0; k < 2; ++k) OK(mppi_batch_step(b));
     std::vector<float> x(50), u0(12), mu(96);
     float acc;

@@ -115,17 +115,27 @@ hipError_t launch_sim_step(const DevModelF& Mf, const DevModelD& Md, int arith, 
 }
 
 // what one persistent batch kernel touches for each tile of its scene's queue
+// (scene -1: the single-launch queue, whose entries are row << 8 | tile of the row)
 static void check_batch(int scene, const BatchArgs<double>& a)
 {
     const int total = *a.total_tiles;
+    std::vector<std::vector<int>> seen;
     for (int t = 0; t < total; ++t) {
         range_check(a.tile_map + t, 4, "tile map");
-        const int row = a.tile_map[t];
+        const int row = scene < 0 ? a.tile_map[t] >> 8 : a.tile_map[t];
+        if (row < 0) fail("negative table row");
         range_check(a.inst + row, sizeof(InstDesc), "instance row");
         const InstDesc& I = a.inst[row];
         const int K = I.P.K, D = 12 * I.P.nk, nx = I.P.nx;
-        if (I.scene != scene) fail("tile of another scene");
-        const int n0 = (t - I.tile0) * kTileSamples, n1 = std::min(K, n0 + kTileSamples);
+        if (scene >= 0 && I.scene != scene) fail("tile of another scene");
+        if (I.scene < 0 || I.scene > 3) fail("scene out of range");
+        const int k = scene < 0 ? (a.tile_map[t] & 255) : t - I.tile0;
+        if (k < 0 || k >= I.ntiles) fail("tile index outside its instance");
+        // every tile of a row exactly once, so the row's tile counter reaches ntiles once
+        if ((int)seen.size() <= row) seen.resize(row + 1);
+        if (seen[row].empty()) seen[row].assign(I.ntiles, 0);
+        if (seen[row][k]++) fail("tile queued twice");
+        const int n0 = k * kTileSamples, n1 = std::min(K, n0 + kTileSamples);
         if (n0 < 0 || n0 >= K) fail("tile outside its instance");
         range_check(I.B, 8ull * I.P.H * I.P.nk, "batch basis");
         range_check(I.S, 4ull * I.P.nk * I.P.nk, "batch shift");
@@ -143,6 +153,9 @@ static void check_batch(int scene, const BatchArgs<double>& a)
         if (I.explicit_eps && I.P.sigma != 1.f) fail("given-noise row without unit scale");
         ++g_batch_tiles;
     }
+    for (const auto& r : seen)
+        for (int c : r)
+            if (c != 1) fail("a tile of a queued row is missing");
 }
 
 struct Captured {
@@ -155,6 +168,13 @@ hipError_t launch_batch(int, int scene, const void* args, int grid, size_t lds, 
 {
     if (grid < 1 || lds > 65536) fail("batch launch shape");
     g_captured.push_back({scene, *static_cast<const BatchArgs<double>*>(args)});  // same layout for both types
+    return hipSuccess;
+}
+
+hipError_t launch_batch_all(int, const void* args, int grid, size_t lds, hipStream_t)
+{
+    if (grid < 1 || lds > 65536) fail("batch launch shape");
+    g_captured.push_back({-1, *static_cast<const BatchArgs<double>*>(args)});
     return hipSuccess;
 }
 }  // namespace mppi

@@ -147,8 +147,9 @@ def test_autotune_and_replay_determinism(B):
         if trial == 0:
             bb, bo, ms = batch.autotune(steps=1)
             assert bb in (2, 4, 8, 16) and bo in (0, 1) and ms > 0
+            assert batch.tuning()[:2] == (bb, bo) and batch.tuning()[2] in (0, 1)
         else:
-            for _ in range(16):  # autotune ran 8 candidates x (1 warm-up + 1 timed) steps
+            for _ in range(32):  # autotune ran 16 candidates x (1 warm-up + 1 timed) steps
                 batch.step()
         out = [batch.read(i, models[s[0]["name"]].nx, s[3]) for i, s in zip(ids, SPECS)]
         outs.append(out)
@@ -255,3 +256,68 @@ def test_full_size_serving_batch_sampled_instances(B):
             ou0, omu, _, _ = orc.mppi_step(p, 0, x0, mu)
             assert np.abs(bu0 - ou0).max() <= KNOT_TOL, (name, p["K"], p["H"])
             assert np.abs(bmu - omu).max() <= KNOT_TOL, (name, p["K"], p["H"])
+
+
+@pytest.mark.parametrize("arith", ["fp64", "fp32"])
+def test_single_launch_matches_per_scene_kernels(B, arith):
+    """One persistent kernel over the combined queue of every scene's tiles gives, bit for
+    bit, the per-scene kernels' states, controls, nominals, running costs and counters,
+    over several steps, for both tile orders and after a removal and a new admission."""
+    outs = []
+    for mode in (0, 1):
+        batch, slots, models, mds = _setup(B, arith=arith)
+        batch.set_launch_mode(mode)
+        ids = []
+        for wl, K, H, nk, seed, inst in SPECS:
+            p = _params(wl, K, H, nk, seed, inst, arith=arith)
+            mu = f32(W.stance_knots(nk) + np.random.default_rng(seed).uniform(-0.05, 0.05, 12 * nk))
+            ids.append(batch.admit(slots[wl["name"]], p, _init_state(wl, seed), mu))
+        for order in (1, 0):
+            batch.set_tuning(4, order)
+            for _ in range(3):
+                batch.step()
+        batch.remove(ids[1])
+        wl, K, H, nk, seed, inst = W.BOX_CLIMB, 4096, 50, 6, 9, 50  # 256 tiles: the largest tile index
+        extra = batch.admit(slots[wl["name"]], _params(wl, K, H, nk, seed, inst, arith=arith), _init_state(wl, seed),
+                            f32(W.stance_knots(nk)))
+        assert batch.tuning() == (4, 0, mode)
+        for _ in range(3):
+            batch.step()
+        keep = [(i, s) for j, (i, s) in enumerate(zip(ids, SPECS)) if j != 1]
+        keep.append((extra, (wl, K, H, nk, seed, inst)))
+        outs.append([batch.read(i, models[s[0]["name"]].nx, s[3]) for i, s in keep])
+        del batch
+    for a, b in zip(*outs):
+        assert a[4] == b[4]
+        for u, v in zip(a[:4], b[:4]):
+            np.testing.assert_array_equal(u, v)
+        assert np.isfinite(a[0]).all()
+
+
+def test_single_launch_matches_per_scene_kernels_at_serving_size(B):
+    """The serving mix (mixed tasks, K up to 4096, H up to 80, about 160 live instances
+    under the 64 MiB budget, Poisson arrivals and departures): the single launch and the
+    per-scene kernels agree bit for bit after four steps."""
+    from paper_2409_10469_amd.serving import ServingSim, TASKS
+    outs = []
+    for mode in (0, 1):
+        sim = ServingSim(seed=0)
+        sim.prefill(256)
+        sim.batch.set_launch_mode(mode)
+        sim.batch.set_tuning(8, 1)
+        for _ in range(4):
+            sim.host_tick()
+            with torch.cuda.stream(sim.stream):
+                sim.batch.step()
+            sim.step_no += 1
+        sim.stream.synchronize()
+        assert len(sim.live) > 100
+        outs.append({iid: sim.batch.read(iid, sim.models[req["task"]].nx, TASKS[req["task"]]["nk"])
+                     for iid, (req, _) in sim.live.items()})
+        del sim
+    assert outs[0].keys() == outs[1].keys()
+    for iid in outs[0]:
+        a, b = outs[0][iid], outs[1][iid]
+        assert a[4] == b[4] and a[4] >= 1
+        for u, v in zip(a[:4], b[:4]):
+            np.testing.assert_array_equal(u, v)
