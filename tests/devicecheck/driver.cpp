@@ -3,7 +3,8 @@
 // device model (hip/hip_runtime.h, emu.cpp), run under the sanitizers on the launch
 // sequences of the GPU tests: full control steps on flat ground, the heightfield and
 // the free-box scene, rollouts with caller noise and trajectories, the proposal step
-// (explicit centre and spread) and the tracking cost.  Every result is compared with the
+// (explicit centre and spread), the tracking cost and batched serving in both launch
+// modes (per-scene kernels, one kernel for every scene).  Every result is compared with the
 // FP64 oracle (knots and controls within 1e-3, 10-step costs within 1e-4 relative), so a
 // kernel that reads undefined memory or races on LDS also shows up as a wrong value.
 // Prints one line per case and "failures: N"; the exit status is 0 only when N is 0.
@@ -289,9 +290,83 @@ static void tracking_case(int scene)
     mppi_model_destroy(m);
 }
 
+// batched serving: three instances (flat ground, heightfield, free box; ragged tiles)
+// stepped twice by the per-scene persistent kernels and by the single kernel over every
+// scene's tiles.  The first step's controls match the oracle's control step; states,
+// controls, nominals, running costs and counters of the two launch modes agree bit for bit.
+static void batch_case()
+{
+    struct Spec { int scene, K, H, nk; float dt; };
+    const Spec sp[3] = {{MPPI_SCENE_FLAT, 20, 8, 4, 0.02f},
+                        {MPPI_SCENE_HEIGHTFIELD, 18, 6, 6, 0.01f},
+                        {MPPI_SCENE_FREE_BOX, 17, 6, 8, 0.01f}};
+    mppi_model_desc d[3]; orc_model o[3]; std::vector<float> hf[3]; std::vector<double> hfd[3];
+    mppi_model* m[3];
+    for (int i = 0; i < 3; ++i) {
+        fill(sp[i].scene, d[i], o[i], hf[i], hfd[i]);
+        must("model", mppi_model_create(&d[i], &m[i]));
+    }
+    std::vector<float> out[2];
+    for (int mode = 0; mode < 2; ++mode) {
+        mppi_batch* b = nullptr;
+        must("batch create", mppi_batch_create(4, 16, 256, 0, &b));
+        const size_t bytes = mppi_batch_control_bytes(4, 0) + (8u << 20);
+        must("batch bind", mppi_batch_bind(b, dev(bytes / 4 + 64), bytes, nullptr));
+        must("launch mode", mppi_batch_set_launch_mode(b, mode));
+        int ids[3];
+        mppi_params p[3]; orc_params op[3];
+        std::vector<float> xs[3], ms[3];
+        for (int i = 0; i < 3; ++i) {
+            int slot = -1;
+            must("add model", mppi_batch_add_model(b, m[i], &slot));
+            params(sp[i].K, sp[i].H, sp[i].nk, sp[i].dt, p[i], op[i]);
+            p[i].instance = op[i].instance = 5 + i;
+            xs[i] = start_state(mppi_model_nx(m[i]), i);
+            ms[i] = stance_knots(sp[i].nk, i);
+            must("admit", mppi_batch_admit(b, slot, &p[i], xs[i].data(), ms[i].data(), &ids[i]));
+        }
+        for (int s = 0; s < 2; ++s) {
+            must("batch step", mppi_batch_step(b));
+            for (int i = 0; i < 3 && s == 0; ++i) {
+                const int nx = mppi_model_nx(m[i]), D = 12 * sp[i].nk;
+                std::vector<float> u0(12);
+                must("batch read", mppi_batch_read(b, ids[i], nullptr, u0.data(), nullptr, nullptr, nullptr));
+                std::vector<double> ox = to_d(xs[i].data(), nx), omu = to_d(ms[i].data(), D), ou0(12);
+                orc_mppi_step(&o[i], &op[i], 0, ox.data(), omu.data(), ou0.data(), nullptr, 1);
+                char what[128];
+                std::snprintf(what, sizeof what, "batch (launch mode %d) scene %d first step: first control", mode,
+                              sp[i].scene);
+                check(what, max_abs_diff(u0.data(), ou0.data(), 12), 1e-3);
+            }
+        }
+        for (int i = 0; i < 3; ++i) {
+            const int nx = mppi_model_nx(m[i]), D = 12 * sp[i].nk;
+            std::vector<float> x(nx), u0(12), mu(D);
+            float acc = 0.f;
+            uint32_t step = 0;
+            must("batch read", mppi_batch_read(b, ids[i], x.data(), u0.data(), mu.data(), &acc, &step));
+            if (step != 2) ++g_fail;
+            out[mode].insert(out[mode].end(), x.begin(), x.end());
+            out[mode].insert(out[mode].end(), u0.begin(), u0.end());
+            out[mode].insert(out[mode].end(), mu.begin(), mu.end());
+            out[mode].push_back(acc);
+        }
+        mppi_batch_destroy(b);
+    }
+    double diff = out[0].size() == out[1].size() ? 0.0 : INFINITY;
+    for (size_t k = 0; k < out[0].size() && k < out[1].size(); ++k)
+        diff = std::fmax(diff, std::memcmp(&out[0][k], &out[1][k], 4) ? std::fabs(out[0][k] - out[1][k]) + 1e-30 : 0.0);
+    check("batch: single launch against per-scene kernels, 2 steps", diff, 0.0);
+    for (int i = 0; i < 3; ++i) mppi_model_destroy(m[i]);
+}
+
 int main(int argc, char** argv)
 {
     const bool quick = argc > 1 && std::strcmp(argv[1], "quick") == 0;
+    // "no-batch": the batch runtime's first-fit allocator keeps a std::map, whose tree
+    // rebalancing runs inside the (uninstrumented) C++ library, so MemorySanitizer would
+    // report the tree's own links as uninitialised
+    const bool no_batch = argc > 2 && std::strcmp(argv[2], "no-batch") == 0;
     steps_case("flat K=64 H=25", MPPI_SCENE_FLAT, 64, 25, 4, 0.02f, quick ? 1 : 3);
     rollout_case(MPPI_SCENE_FLAT, 20, 4);
     proposal_case();
@@ -302,6 +377,7 @@ int main(int argc, char** argv)
         tracking_case(MPPI_SCENE_FLAT);
         tracking_case(MPPI_SCENE_FREE_BOX);
     }
+    if (!no_batch) batch_case();
     for (void* p : g_mem) std::free(p);
     std::printf("failures: %d\n", g_fail);
     return g_fail ? 1 : 0;

@@ -22,6 +22,7 @@
 
 thread_local dim3 threadIdx, blockIdx;
 dim3 blockDim, gridDim;
+EmuGraph* g_emu_capture = nullptr;
 namespace mppi {
 alignas(16) unsigned char lds_raw[kEmuLdsBytes];
 }

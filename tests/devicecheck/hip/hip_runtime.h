@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <vector>
 
 #ifndef __clang__
 typedef unsigned short __bf16;  // the network headers name the type; no network kernel is built here
@@ -65,8 +66,55 @@ inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (void*
 inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
+inline hipError_t hipEventCreate(hipEvent_t* e) { *e = (void*)1; return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 1.f; return hipSuccess; }
 inline const char* hipGetErrorString(hipError_t) { return "emulation"; }
 hipError_t hipGetLastError();
+// one emulated device of two compute units (the persistent batch grid is blocks_per_cu x 2)
+enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount };
+inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 2; return hipSuccess; }
+// pinned host memory is plain host memory here
+enum { hipHostMallocDefault = 0 };
+inline hipError_t hipHostMalloc(void** p, size_t n, unsigned)
+{
+    *p = std::malloc(n ? n : 1);
+    return *p ? hipSuccess : hipErrorInvalidValue;
+}
+inline hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
+// stream capture records the launches issued while it is open; a graph launch replays them
+struct EmuGraph {
+    std::vector<std::function<void()>> ops;
+};
+typedef EmuGraph* hipGraph_t;
+typedef EmuGraph* hipGraphExec_t;
+enum hipStreamCaptureMode { hipStreamCaptureModeThreadLocal };
+extern EmuGraph* g_emu_capture;
+inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode)
+{
+    if (g_emu_capture) return hipErrorInvalidValue;
+    g_emu_capture = new EmuGraph;
+    return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g)
+{
+    *g = g_emu_capture;
+    g_emu_capture = nullptr;
+    return *g ? hipSuccess : hipErrorInvalidValue;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, void*, void*, size_t)
+{
+    *e = new EmuGraph(*g);
+    return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t)
+{
+    for (auto& op : e->ops) op();
+    return hipSuccess;
+}
+inline hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t e) { delete e; return hipSuccess; }
 
 // ---- device built-ins --------------------------------------------------------------
 void __syncthreads();
@@ -95,7 +143,7 @@ inline T __shfl_xor(T v, int mask, int width = 64)
     std::memcpy(&r, &b, sizeof(T));
     return r;
 }
-inline int __builtin_amdgcn_readfirstlane(int v) { return v; }  // only in the batch kernel (not run here)
+inline int __builtin_amdgcn_readfirstlane(int v) { return v; }  // the batch kernels: wave-uniform values
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
 inline float __int_as_float(int i) { float f; std::memcpy(&f, &i, 4); return f; }
@@ -119,6 +167,8 @@ void emu_run_grid(dim3 grid, dim3 block, size_t lds, const std::function<void()>
 template <typename K, typename... A>
 void emu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... args)
 {
-    emu_run_grid(grid, block, lds, [=]() { kernel(args...); });
+    std::function<void()> run = [=]() { emu_run_grid(grid, block, lds, [=]() { kernel(args...); }); };
+    if (g_emu_capture) g_emu_capture->ops.push_back(run);
+    else run();
 }
 #define hipLaunchKernelGGL(kernel, grid, block, lds, stream, ...) emu_launch(kernel, grid, block, lds, __VA_ARGS__)
