@@ -294,14 +294,15 @@ def test_single_launch_matches_per_scene_kernels(B, arith):
         assert np.isfinite(a[0]).all()
 
 
-def test_single_launch_matches_per_scene_kernels_at_serving_size(B):
+@pytest.mark.parametrize("arith", ["fp64", "fp32"])
+def test_single_launch_matches_per_scene_kernels_at_serving_size(B, arith):
     """The serving mix (mixed tasks, K up to 4096, H up to 80, about 160 live instances
     under the 64 MiB budget, Poisson arrivals and departures): the single launch and the
     per-scene kernels agree bit for bit after four steps."""
     from paper_2409_10469_amd.serving import ServingSim, TASKS
     outs = []
     for mode in (0, 1):
-        sim = ServingSim(seed=0)
+        sim = ServingSim(seed=0, arith=arith)
         sim.prefill(256)
         sim.batch.set_launch_mode(mode)
         sim.batch.set_tuning(8, 1)

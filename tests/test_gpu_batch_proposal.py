@@ -48,9 +48,11 @@ SPECS = [
 ]
 
 
-def test_batched_proposal_matches_controller_and_oracle(B):
+@pytest.mark.parametrize("mode", [0, 1])  # per-scene kernels, one kernel for every scene
+def test_batched_proposal_matches_controller_and_oracle(B, mode):
     pol, (im, isd, om, osd) = _policy(B)
     batch = B.Batch(max_instances=8, budget_bytes=64 << 20, max_horizon=80, max_hf_cells=4096)
+    batch.set_launch_mode(mode)
     models, mds, slots = {}, {}, {}
     for wl in (W.FLAT_WALK, W.TERRAIN_WALK):
         mds[wl["name"]] = round_model(W.model_dict(wl, 0))
