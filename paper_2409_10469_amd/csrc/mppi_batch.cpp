@@ -171,8 +171,9 @@ size_t prop_bytes(int max_inst)
 // teardown: errors here have no caller to report to and do not change what is released
 void drop_graph(mppi_batch* b)
 {
-    // an executable graph may still be running on the caller's stream: let it finish
-    if (b->exec && b->stream) (void)hipStreamSynchronize(b->stream);
+    // an executable graph may still be running on the caller's stream (the null stream
+    // included): let it finish
+    if (b->exec) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
