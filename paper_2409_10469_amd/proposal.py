@@ -354,7 +354,8 @@ def evaluate_batched(policy, n_inst=256, K_plain=(256, 1024), k_prop=256, steps=
             episode_cost_median=float(np.median(costs)), falls=falls,
             latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
                             mean=float(lat.mean())),
-            rollout_steps_per_s=n_inst * K * H * steps / wall, tuning=dict(blocks_per_cu=bpc, order=order))
+            rollout_steps_per_s=n_inst * K * H * steps / wall,
+            tuning=dict(blocks_per_cu=bpc, order=order, launch_mode=mode))
         log(f"  batched {name}: episode cost {np.mean(costs):.3f}, falls {falls}/{n_inst}, step latency p50 "
             f"{np.percentile(lat, 50):.3f} p99 {np.percentile(lat, 99):.3f} ms")
         del batch
