@@ -146,6 +146,9 @@ def main():
     ap.add_argument("--eval-steps", type=int, default=200, help="proposal_training: steps per evaluation episode")
     ap.add_argument("--eval-instances", type=int, default=256,
                     help="proposal_training: instances of the batched-serving evaluation")
+    ap.add_argument("--batch-tuning", default=None, metavar="BPC,ORDER,MODE",
+                    help="batched_serving: fixed tuning instead of the autotuner (blocks per CU, tile order "
+                         "0 admission / 1 longest first, launch mode 0 per scene / 1 one kernel for every scene)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -286,7 +289,14 @@ def bench_serving(args):
     from paper_2409_10469_amd.serving import ServingSim
     sim = ServingSim(seed=args.seed, arith=args.arith)
     sim.prefill(256)
-    r = sim.run(args.steps, warmup=args.warmup, autotune=True)
+    fixed = None
+    if args.batch_tuning:
+        fixed = [int(v) for v in args.batch_tuning.split(",")]
+        if len(fixed) != 3:
+            raise SystemExit("--batch-tuning takes BPC,ORDER,MODE")
+        sim.batch.set_tuning(fixed[0], fixed[1])
+        sim.batch.set_launch_mode(fixed[2])
+    r = sim.run(args.steps, warmup=args.warmup, autotune=fixed is None)
     lat = r["latency_ms"]
     value = r["rollout_steps"] / r["elapsed"]
     achieved = r["flops"] / (lat.sum() * 1e-3) / 1e12
@@ -311,6 +321,9 @@ def bench_serving(args):
         "autotune": {"blocks_per_cu": r["tune"][0], "order": "longest_first" if r["tune"][1] else "admission",
                      "launch": "one kernel for every scene" if r["tune"][3] else "one kernel per scene",
                      "ms": r["tune"][2]} if r["tune"] else None,
+        "fixed_tuning": {"blocks_per_cu": fixed[0], "order": "longest_first" if fixed[1] else "admission",
+                         "launch": "one kernel for every scene" if fixed[2] else "one kernel per scene"}
+        if fixed else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None},
         "budget": r["stats"],
