@@ -483,9 +483,11 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchArgs<R> a)
 
 // one persistent kernel for every scene: a single queue whose entries pack the instance
 // row and the tile's index inside its instance (row << 8 | tile); each tile branches to
-// its scene's code (uniform over the workgroup)
+// its scene's code (uniform over the workgroup).  In FP32 the four scenes' code together
+// needs a few registers more than half the file; it is held to two waves per SIMD (the
+// per-scene FP32 kernels' occupancy), in FP64 to one.
 template <typename R>
-__global__ __launch_bounds__(64) void batch_kernel_all(BatchArgs<R> a)
+__global__ __launch_bounds__(64, sizeof(R) == 4 ? 2 : 1) void batch_kernel_all(BatchArgs<R> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int s_tile, s_last;
