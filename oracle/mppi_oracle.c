@@ -861,6 +861,31 @@ void orc_contact_total(const orc_model *m, const double *x, double *F_robot, dou
     *n_active = s.n_active;
 }
 
+int orc_terrain(const orc_model *m, const double *c, double r, double *delta, double *n)
+{
+    return terrain(m, c, r, delta, n);
+}
+
+int orc_sphere_box(const double *c, double r, const double *p, const double *quat, const double *h, double *delta,
+                   double *n)
+{
+    double R[9];
+    quat_to_mat(quat, R);
+    return sphere_box(c, r, p, R, h, delta, n);
+}
+
+int orc_point_box(const double *x, const double *p, const double *quat, const double *h, double *delta, double *n)
+{
+    double R[9];
+    quat_to_mat(quat, R);
+    return point_box(x, p, R, h, delta, n);
+}
+
+int orc_contact_law(const orc_model *m, double delta, const double *n, const double *vrel, double *F, double *D)
+{
+    return contact_law(m, delta, n, vrel, F, D);
+}
+
 /* ------------------------------------------------------------------ */
 /* counter-based Gaussian sampler                                       */
 /* ------------------------------------------------------------------ */

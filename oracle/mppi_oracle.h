@@ -90,6 +90,15 @@ int  orc_step(const orc_model *m, const double *x, const double *u, double kp, d
 int  orc_step_system(const orc_model *m, const double *x, const double *u, double kp, double kd, double dt,
                      double *A_out, double *rhs_out);
 void orc_contact_total(const orc_model *m, const double *x, double *F_robot /*3*/, double *F_box /*3*/, int *n_active);
+/* contact geometry and law, exported for their pins (quat is the box orientation, w x y z):
+   terrain below a sphere (r > 0) or point (r = 0); sphere against an oriented box (normal
+   from the box toward the sphere); point strictly inside an oriented box (shallowest face);
+   the penalty law's force and 3x3 damping.  Each returns 1 when in contact. */
+int  orc_terrain(const orc_model *m, const double *c, double r, double *delta, double *n);
+int  orc_sphere_box(const double *c, double r, const double *p, const double *quat, const double *h, double *delta,
+                    double *n);
+int  orc_point_box(const double *x, const double *p, const double *quat, const double *h, double *delta, double *n);
+int  orc_contact_law(const orc_model *m, double delta, const double *n, const double *vrel, double *F, double *D);
 
 /* Cost, rollout and MPPI (Eqs. 1-2, Algorithm 1). */
 double orc_stage_cost(const orc_model *m, const orc_params *p, const double *x, const double *tau);

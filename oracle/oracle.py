@@ -117,6 +117,10 @@ def lib():
             "orc_step": (C.c_int, [mp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]),
             "orc_contact_total": (None, [mp, dp, dp, dp, C.POINTER(C.c_int)]),
             "orc_step_system": (C.c_int, [mp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]),
+            "orc_terrain": (C.c_int, [mp, dp, C.c_double, dp, dp]),
+            "orc_sphere_box": (C.c_int, [dp, C.c_double, dp, dp, dp, dp, dp]),
+            "orc_point_box": (C.c_int, [dp, dp, dp, dp, dp, dp]),
+            "orc_contact_law": (C.c_int, [mp, C.c_double, dp, dp, dp, dp]),
             "orc_stage_cost": (C.c_double, [mp, pp, dp, dp]),
             "orc_rollout": (C.c_double, [mp, pp, dp, dp, dp]),
             "orc_rollout_batch": (None, [mp, pp, dp, dp, dp, dp, dp, C.c_int]),
@@ -276,6 +280,17 @@ class Oracle:
         self.L.orc_contact_total(C.byref(self.m), _dp(_f64(x, self.nx)), _dp(Fr), _dp(Fb), C.byref(n))
         return Fr, Fb, n.value
 
+    def terrain(self, c, r):
+        d, n = C.c_double(0), np.zeros(3)
+        hit = self.L.orc_terrain(C.byref(self.m), _dp(_f64(c, 3)), float(r), C.byref(d), _dp(n))
+        return bool(hit), d.value, n
+
+    def contact_law(self, delta, n, vrel):
+        F, D = np.zeros(3), np.zeros((3, 3))
+        hit = self.L.orc_contact_law(C.byref(self.m), float(delta), _dp(_f64(n, 3)), _dp(_f64(vrel, 3)), _dp(F),
+                                     _dp(D))
+        return bool(hit), F, D
+
     def stage_cost(self, p: dict, x, tau):
         ps = self.params(p)
         return self.L.orc_stage_cost(C.byref(self.m), C.byref(ps), _dp(_f64(x, self.nx)), _dp(_f64(tau, 12)))
@@ -360,6 +375,22 @@ def gait_foot(c: dict, leg: int, t: float, v_h, cmd_h):
 
 
 # ---- model-free pieces ---------------------------------------------------
+def sphere_box(c, r, p, quat, h):
+    """Sphere (centre c, radius r) against an oriented box: (hit, depth, normal box -> sphere)."""
+    d, n = C.c_double(0), np.zeros(3)
+    hit = lib().orc_sphere_box(_dp(_f64(c, 3)), float(r), _dp(_f64(p, 3)), _dp(_f64(quat, 4)), _dp(_f64(h, 3)),
+                               C.byref(d), _dp(n))
+    return bool(hit), d.value, n
+
+
+def point_box(x, p, quat, h):
+    """Point strictly inside an oriented box: (hit, depth of the shallowest face, its outward normal)."""
+    d, n = C.c_double(0), np.zeros(3)
+    hit = lib().orc_point_box(_dp(_f64(x, 3)), _dp(_f64(p, 3)), _dp(_f64(quat, 4)), _dp(_f64(h, 3)), C.byref(d),
+                              _dp(n))
+    return bool(hit), d.value, n
+
+
 def philox(ctr, key):
     L = lib()
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
