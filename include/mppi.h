@@ -100,7 +100,16 @@ typedef struct mppi_params {
     int32_t arith;              /* MPPI_ARITH_FP64 (0, default) or MPPI_ARITH_FP32 */
     int32_t basis;              /* knot interpolation, MPPI_BASIS_* (0: cubic, the default) */
     int32_t cost;               /* MPPI_COST_RUNNING (0, default) or MPPI_COST_TRACKING */
+    int32_t lanes;              /* lanes per sample of the rollout kernel, MPPI_LANES_* (0: default) */
 } mppi_params;
+
+/* Rollout decomposition.  QUAD: one lane per leg, 16 samples per wave.  SPLIT: 16 lanes
+ * per sample (four per leg: knot interpolation, trigonometry and the trunk and box
+ * corner contacts spread over them), 4 samples per wave, so K = 4096 fills every SIMD of
+ * the chip.  Both compute the same step; only summation orders differ.  DEFAULT picks
+ * SPLIT when its LDS rows fit (a heightfield above about 11,000 cells in FP64 does not)
+ * and QUAD otherwise. */
+enum { MPPI_LANES_DEFAULT = 0, MPPI_LANES_QUAD = 4, MPPI_LANES_SPLIT = 16 };
 
 /* Interpolation of the knots into per-step joint targets (Sec. III-B uses the cubic
  * spline and names zeroth-order and linear interpolation as the alternatives):

@@ -50,7 +50,7 @@ class Params(C.Structure):
         ("v_ref", C.c_float), ("w_torque", C.c_float), ("w_reach", C.c_float), ("w_box", C.c_float),
         ("goal", C.c_float * 2),
         ("seed", C.c_uint64), ("instance", C.c_uint32), ("arith", C.c_int32), ("basis", C.c_int32),
-        ("cost", C.c_int32),
+        ("cost", C.c_int32), ("lanes", C.c_int32),
     ]
 
 
@@ -193,6 +193,7 @@ def params_struct(p: dict) -> Params:
     s.arith = ARITH[p.get("arith", "fp64")]
     s.basis = int(p.get("basis", 0))  # 0 cubic, 1 linear, 2 zeroth order
     s.cost = COST[p.get("cost", "running")]
+    s.lanes = int(p.get("lanes", 0))  # 0 default, 4 quad kernel, 16 lane-split kernel
     return s
 
 

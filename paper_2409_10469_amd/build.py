@@ -1,20 +1,23 @@
-"""Builds the HIP library libmppi.so in-tree for gfx950 with hipcc."""
+"""Builds the HIP library libmppi.so in-tree for gfx950 with hipcc (one object per source,
+compiled in parallel, then linked)."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmppi.so")
-SOURCES = ["mppi_kernels.hip", "mlp_kernels.hip", "proposal_kernels.hip", "tracking_kernels.hip", "mppi_api.cpp",
-           "mppi_batch.cpp", "mppi_policy.cpp"]
+OBJ = os.path.join(PKG, "_build")
+SOURCES = ["mppi_kernels.hip", "rollout16.hip", "mlp_kernels.hip", "proposal_kernels.hip", "tracking_kernels.hip",
+           "mppi_api.cpp", "mppi_batch.cpp", "mppi_policy.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off (they are not trusted on this hardware)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
@@ -22,12 +25,27 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    jobs = []
+    for s in SOURCES:
+        obj = os.path.join(OBJ, s + ".o")
+        jobs.append(([HIPCC, *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", obj], obj))
+
+    def run(job):
+        if verbose:
+            print(" ".join(job[0]), flush=True)
+        return subprocess.run(job[0], capture_output=True, text=True)
+
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        results = list(ex.map(run, jobs))
+    for r, (cmd, _) in zip(results, jobs):
+        sys.stderr.write("".join(l + "\n" for l in r.stderr.splitlines() if "packed-fp32-ops" not in l))
+        if r.returncode != 0:
+            raise subprocess.CalledProcessError(r.returncode, cmd)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for _, o in jobs], "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -18,6 +18,9 @@
 #include "proposal_launch.h"
 #include "tracking_launch.h"
 
+// MPPI_LANES_DEFAULT picks the lane-split rollout where its LDS fits
+constexpr bool kSplitByDefault = false;
+
 struct mppi_model {
     mppi_model_desc desc;
     std::vector<float> hf;
@@ -53,6 +56,7 @@ struct mppi_ctx {
     track::TrackDev track{};
     bool track_set = false;
     size_t off_traj = 0, off_uref = 0;
+    bool split = false;  // rollouts on the lane-split kernel (16 lanes per sample)
     std::string err;
 };
 
@@ -227,6 +231,13 @@ mppi_status need_bound(mppi_ctx* c)
     return MPPI_OK;
 }
 
+// the rollout launch of a controller: the lane-split or the quad kernel
+hipError_t launch_roll(const mppi_ctx* c, const mppi::DevParams& P, const mppi::RolloutArgs& a, hipStream_t st)
+{
+    return c->split ? mppi::launch_rollout16(c->model.dev_f, c->model.dev_d, c->p.arith, P, a, st)
+                    : mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, P, a, st);
+}
+
 }  // namespace
 
 namespace mppi_host {
@@ -343,8 +354,14 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
         return fail(nullptr, MPPI_EINVAL, "basis must be MPPI_BASIS_CUBIC, _LINEAR or _ZERO");
     if (p->cost != MPPI_COST_RUNNING && p->cost != MPPI_COST_TRACKING)
         return fail(nullptr, MPPI_EINVAL, "cost must be MPPI_COST_RUNNING or MPPI_COST_TRACKING");
+    if (p->lanes != MPPI_LANES_DEFAULT && p->lanes != MPPI_LANES_QUAD && p->lanes != MPPI_LANES_SPLIT)
+        return fail(nullptr, MPPI_EINVAL, "lanes must be MPPI_LANES_DEFAULT, _QUAD or _SPLIT");
+    const bool split_fits = mppi::rollout16_fits(p->arith, model->desc.scene, (int)model->hf.size());
+    if (p->lanes == MPPI_LANES_SPLIT && !split_fits)
+        return fail(nullptr, MPPI_EINVAL, "the lane-split rollout's LDS does not fit this heightfield");
     mppi_ctx* c = new (std::nothrow) mppi_ctx();
     if (!c) return fail(nullptr, MPPI_ENOMEM, "host allocation failed");
+    c->split = p->lanes == MPPI_LANES_SPLIT || (p->lanes == MPPI_LANES_DEFAULT && kSplitByDefault && split_fits);
     c->model = *model;
     c->p = *p;
     c->D = 12 * p->n_knots;
@@ -493,7 +510,7 @@ static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, f
     a.traj = d_traj;
     a.samples_per_block = 16;
     mppi_status s;
-    if ((s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, P, a, c->stream),
+    if ((s = hip_check(c, launch_roll(c, P, a, c->stream),
                        "rollout launch")) ||
         !tracking)
         return s;
@@ -593,7 +610,7 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
         if (!c->side) return fail(c, MPPI_ESTATE, "no side stream (bind the controller again)");
         if ((s = hip_check(c, hipEventRecord(c->ev_fork, c->stream), "fork record")) ||
             (s = hip_check(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "fork wait")) ||
-            (s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, Pp, a, c->side),
+            (s = hip_check(c, launch_roll(c, Pp, a, c->side),
                            "proposal rollout launch")) ||
             (s = hip_check(c, hipEventRecord(c->ev_join, c->side), "join record")))
             return s;
@@ -601,7 +618,7 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
         // join before returning, also after a failed launch, so that no work is left on the side stream
         if ((s = hip_check(c, hipStreamWaitEvent(c->stream, c->ev_join, 0), "join wait"))) return s;
         if (rs) return rs;
-    } else if ((s = hip_check(c, mppi::launch_rollout(c->model.dev_f, c->model.dev_d, c->p.arith, Pp, a, c->stream),
+    } else if ((s = hip_check(c, launch_roll(c, Pp, a, c->stream),
                               "proposal rollout launch"))) {
         return s;
     }

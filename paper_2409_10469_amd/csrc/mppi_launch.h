@@ -60,6 +60,11 @@ hipError_t launch_sample(const DevParams& P, int D, float* eps, uint32_t* raw, h
 // arith: 0 = FP64 step arithmetic, 1 = FP32
 hipError_t launch_rollout(const DevModelF& Mf, const DevModelD& Md, int arith, const DevParams& P,
                           const RolloutArgs& a, hipStream_t st);
+// the lane-split rollout (16 lanes per sample); same arguments as launch_rollout, whose
+// samples_per_block it ignores.  rollout16_fits: whether its LDS fits for the model.
+hipError_t launch_rollout16(const DevModelF& Mf, const DevModelD& Md, int arith, const DevParams& P,
+                            const RolloutArgs& a, hipStream_t st);
+bool rollout16_fits(int arith, int scene, int hf_cells);
 hipError_t launch_update(const DevParams& P, const UpdateArgs& a, hipStream_t st);
 hipError_t launch_sim_step(const DevModelF& Mf, const DevModelD& Md, int arith, int n, int nx, const float* x,
                            const float* u, float kp, float kd, float dt, float* xo, float* tau, const float* hf,

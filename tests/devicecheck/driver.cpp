@@ -78,9 +78,12 @@ static void fill(int scene, mppi_model_desc& d, orc_model& o, std::vector<float>
     o.box_mass = d.box_mass;
 }
 
+static int g_lanes = 0;  // rollout decomposition of the controllers made here
+
 static void params(int K, int H, int nk, float dt, mppi_params& p, orc_params& o)
 {
     p = mppi_params{};
+    p.lanes = g_lanes;
     p.K = K; p.H = H; p.n_knots = nk; p.dt = dt; p.sigma = 0.3f; p.lambda = 0.1f; p.kp = 40.f; p.kd = 1.f;
     p.w_height = 100.f; p.h_ref = 0.27f; p.w_upright = 10.f; p.w_vel = 1.f; p.v_ref = 0.5f; p.w_torque = 1e-3f;
     p.w_reach = 1.f; p.w_box = 2.f; p.goal[0] = 2.0f; p.goal[1] = -0.5f; p.seed = 0x1234abcdull; p.instance = 3;
@@ -377,6 +380,16 @@ int main(int argc, char** argv)
         tracking_case(MPPI_SCENE_FLAT);
         tracking_case(MPPI_SCENE_FREE_BOX);
     }
+    // the same controller checks on the lane-split rollout (16 lanes per sample)
+    g_lanes = MPPI_LANES_SPLIT;
+    steps_case("split flat K=64 H=25", MPPI_SCENE_FLAT, 64, 25, 4, 0.02f, 1);
+    rollout_case(MPPI_SCENE_FLAT, 21, 4);
+    if (!quick) {
+        steps_case("split heightfield K=16 H=12", MPPI_SCENE_HEIGHTFIELD, 16, 12, 6, 0.01f, 1);
+        steps_case("split free box K=18 H=10", MPPI_SCENE_FREE_BOX, 18, 10, 8, 0.01f, 1);
+        rollout_case(MPPI_SCENE_FREE_BOX, 9, 8);
+    }
+    g_lanes = 0;
     if (!no_batch) batch_case();
     for (void* p : g_mem) std::free(p);
     std::printf("failures: %d\n", g_fail);

@@ -79,6 +79,20 @@ hipError_t launch_rollout(const DevModelF& Mf, const DevModelD& Md, int arith, c
     return hipSuccess;
 }
 
+hipError_t launch_rollout16(const DevModelF& Mf, const DevModelD& Md, int arith, const DevParams& P,
+                            const RolloutArgs& a, hipStream_t st)
+{
+    if (!rollout16_fits(arith, arith == 1 ? Mf.scene : Md.scene, arith == 1 ? Mf.hf_nx * Mf.hf_ny : Md.hf_nx * Md.hf_ny))
+        fail("rollout16 LDS");
+    return launch_rollout(Mf, Md, arith, P, a, st);  // same ranges as the quad kernel
+}
+
+bool rollout16_fits(int arith, int scene, int hf_cells)
+{
+    const size_t rows = (4 * 55 * 20 + 4 * 64) * (arith == 1 ? 4 : 8);
+    return rows + (scene == 1 ? 4ull * hf_cells : 0) <= 65536;
+}
+
 hipError_t launch_update(const DevParams& P, const UpdateArgs& a, hipStream_t)
 {
     const int D = 12 * P.nk;

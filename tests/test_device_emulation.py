@@ -31,7 +31,7 @@ ORC = os.path.join(ROOT, "oracle")
 CLANG = "/opt/rocm/llvm/bin/clang++"
 CLANG_C = "/opt/rocm/llvm/bin/clang"
 
-KERNELS = ["mppi_kernels.hip", "proposal_kernels.hip", "tracking_kernels.hip"]
+KERNELS = ["mppi_kernels.hip", "rollout16.hip", "proposal_kernels.hip", "tracking_kernels.hip"]
 HOST = [os.path.join(DC, "emu.cpp"), os.path.join(DC, "driver.cpp"), os.path.join(CS, "mppi_api.cpp"),
         os.path.join(CS, "mppi_policy.cpp"), os.path.join(CS, "mppi_batch.cpp")]
 ORACLE = [os.path.join(ORC, "mppi_oracle.c"), os.path.join(ORC, "tracking_oracle.c")]
