@@ -1,18 +1,21 @@
 """Benchmark of the whole-body MPPI hot path on one MI355X.
 
-One step = one closed-loop control step of the heightfield walking workload
-(K = 1024 samples, horizon H = 50 at dt = 0.01 s, 6 knots per joint; by default 2000
-timed steps as 10 episodes of 200 steps from seeds 0-9): Philox sampling,
-the fused rollout of all samples, the Eq. 1 / Eq. 2 update with first-control
-extraction and shift, and one plant step with the chosen control -- all on the GPU,
-inputs resident in HBM.  Prints one JSON line.
+One step = one closed-loop control step of the box-pushing workload (K = 4096 samples,
+horizon H = 60 at dt = 0.01 s, 8 knots per joint, the quadruped and a free 2 kg box on
+flat ground; by default 2000 timed steps as 10 episodes of 200 steps from seeds 0-9):
+Philox sampling, the fused rollout of all samples (the lane-split kernel, 16 lanes per
+sample, FP32 step arithmetic), the Eq. 1 / Eq. 2 update with first-control extraction
+and shift, and one plant step with the chosen control -- all on the GPU, inputs resident
+in HBM.  Prints one JSON line.
 
 Metric: rollout-steps/s (K * H per control step) and the p50/p99 control-step latency
-(HIP events around each step on the library's stream).  The roofline object reports
-the fused rollout kernel's algorithmic FLOP rate (flops per rollout-step counted from
-the kernel's formulation, times K * H, over its event-timed duration) against the
-MI355X vector peak of the arithmetic type.  cpu_baseline times the FP64 CPU oracle on
-a bounded sample of the same workload on this host's cores.
+(HIP events around each step on the library's stream).  The roofline object reports the
+rollout kernel's algorithmic FLOP rate (flops per rollout-step counted from the step's
+formulation, times K * H, over its event-timed duration) against the MI355X vector peak
+of the step's arithmetic type.  cpu_baseline times the FP64 CPU oracle on a bounded
+sample of the same workload on this host's cores.  learned_vs_plain runs a bounded
+version of the learned-proposal comparison (train on GPU closed loops, then plain MPPI
+at several K against the proposal at K/4 on the same seeds).
 """
 from __future__ import annotations
 
@@ -28,18 +31,25 @@ sys.path.insert(0, ROOT)
 
 from paper_2409_10469_amd.roofline import PEAK_TFLOPS, flops_per_rollout_step  # noqa: E402
 
+SCENE_NAMES = {0: "flat ground", 1: "heightfield 64x64", 2: "flat ground + static box (climb)",
+               3: "flat ground + free box (push)"}
+
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("mppi_device.h", "mppi_kernels.hip"):
+    for f in ("mppi_device.h", "mppi_kernels.hip", "rollout16.hip"):
         h.update(open(os.path.join(ROOT, "paper_2409_10469_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str, arith: str):
+def _kernel_tag(lanes: int) -> str:
+    return "rollout16" if lanes == 16 else "rollout"
+
+
+def traffic_from_profile(workload: str, arith: str, lanes: int = 16):
     """Counter-measured HBM bytes per rollout launch, if the committed counter summary
     was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"rollout_{workload}_{arith}_hbm.json")
+    path = os.path.join(ROOT, "profiles", f"{_kernel_tag(lanes)}_{workload}_{arith}_hbm.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -65,10 +75,10 @@ def counter_rate(flops_per_launch, kernel_ms, peak):
             "source": "VALU instruction counters, 64 x (ADD + MUL + 2 FMA + TRANS)"}
 
 
-def counter_flops_from_profile(workload: str, arith: str):
+def counter_flops_from_profile(workload: str, arith: str, lanes: int = 16):
     """Counter FLOPs per rollout launch (64 x (ADD + MUL + 2 FMA + TRANS) from the VALU
     instruction counters), if the committed summary was taken on the current source."""
-    path = os.path.join(ROOT, "profiles", f"rollout_{workload}_{arith}_flops.json")
+    path = os.path.join(ROOT, "profiles", f"{_kernel_tag(lanes)}_{workload}_{arith}_flops.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -133,10 +143,14 @@ def main():
     ap.add_argument("--episode-steps", type=int, default=200,
                     help="control steps per closed-loop episode (a new seed every episode)")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="heightfield_walk",
-                    help="heightfield_walk (default), flat_walk, box_push, box_climb, batched_serving, "
+    ap.add_argument("--workload", default="box_push",
+                    help="box_push (default), heightfield_walk, flat_walk, box_climb, batched_serving, "
                          "proposal_training, ablations or tracking")
-    ap.add_argument("--arith", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--arith", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--lanes", type=int, default=16, choices=[4, 16],
+                    help="rollout kernel: 16 lanes per sample (lane-split, default) or 4 (one lane per leg)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the bounded learned-proposal comparison of the default run")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -176,7 +190,7 @@ def main():
         return bench_ablation(args)
     wl = W.WORKLOADS[args.workload]
     md = W.model_dict(wl, args.seed)
-    p = W.params_dict(wl, args.seed, arith=args.arith)
+    p = W.params_dict(wl, args.seed, arith=args.arith, lanes=args.lanes)
     model = B.Model(md)
     K, H, nk = p["K"], p["H"], p["nk"]
     stream = torch.cuda.current_stream()
@@ -248,7 +262,7 @@ def main():
     achieved = flops / (roll_ms.mean() * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.arith]
     out = {
-        "metric": "rollout-steps/sec + p99 MPPI step latency",
+        "metric": "rollout-steps/sec + p99 MPPI step latency; learned-proposal vs plain at equal cost",
         "value": value,
         "unit": "rollout-steps/s",
         "n_gpus": 1,
@@ -260,26 +274,61 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.arith == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": wl["name"], "K": K, "H": H, "dt": p["dt"], "n_knots": nk, "scene": "heightfield 64x64"
-                   if wl["scene"] == 1 else wl["name"], "closed_loop": True, "state": "f32",
-                   "step_arithmetic": args.arith, "episodes": n_ep, "episode_steps": args.episode_steps,
-                   "seeds": [seeds[0], seeds[-1]]},
+        "config": {"workload": wl["name"], "K": K, "H": H, "dt": p["dt"], "n_knots": nk,
+                   "scene": SCENE_NAMES[wl["scene"]], "closed_loop": True, "state": "f32",
+                   "step_arithmetic": args.arith, "rollout_lanes_per_sample": args.lanes,
+                   "episodes": n_ep, "episode_steps": args.episode_steps, "seeds": [seeds[0], seeds[-1]]},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "mean": float(step_ms.mean())},
         "rollout_kernel_ms": float(roll_ms.mean()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic_from_profile(wl["name"], args.arith),
-                     "flops_per_rollout_step": flops_per_rollout_step(wl["scene"], nk)},
-        "counter_flops": counter_rate(counter_flops_from_profile(wl["name"], args.arith), roll_ms.mean(), peak),
-        "hbm_gbs": hbm_rate(traffic_from_profile(wl["name"], args.arith), roll_ms.mean()),
+                     "traffic": traffic_from_profile(wl["name"], args.arith, args.lanes),
+                     "flops_per_rollout_step": flops_per_rollout_step(wl["scene"], nk),
+                     "kernel": f"{_kernel_tag(args.lanes)}_kernel<{wl['scene']}, "
+                               f"{'float' if args.arith == 'fp32' else 'double'}>"},
+        "counter_flops": counter_rate(counter_flops_from_profile(wl["name"], args.arith, args.lanes), roll_ms.mean(),
+                                      peak),
+        "hbm_gbs": hbm_rate(traffic_from_profile(wl["name"], args.arith, args.lanes), roll_ms.mean()),
         "ess": {"mean": float(np.mean(ess)), "median": float(np.median(ess)), "min": float(np.min(ess)),
                 "of_K": K},
         "final_state_finite": bool(np.isfinite(xf).all()),
         "update_status": int(status),
     }
+    if not args.no_learned:
+        out["learned_vs_plain"] = learned_vs_plain(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def learned_vs_plain(args):
+    """Bounded learned-proposal comparison (the full one is --workload proposal_training):
+    2e5 closed-loop pairs from the flat and heightfield walks, 6 Adam epochs, then the
+    heightfield walk (v_ref 0.5, 5 held-out seeds x 100 steps) with plain MPPI at K in
+    {256, 512, 1024} against the proposal at 256 samples (gated and ungated)."""
+    from paper_2409_10469_amd import binding as B
+    from paper_2409_10469_amd import proposal as PR
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    data = PR.generate(n_pairs=200_000, episode_steps=200, instances=256, seed=args.seed, log=log)
+    tr, ho = PR.split(data, holdout=0.05, seed=args.seed)
+    pol = B.Policy(max_batch=4096, seed=args.seed)
+    pol.set_normalization(*PR.normalization(data, tr))
+    PR.train(pol, data, tr, epochs=6, batch=4096, lr=1e-3, seed=args.seed, held=ho, log=log)
+    ev = PR.evaluate(pol, K_plain=(256, 512, 1024), K_learned=1024, seeds=range(100, 105), steps=100, log=log)
+    res = {"task": "heightfield walk, v_ref 0.5, closed loop", "seeds": ev["seeds"], "steps": ev["steps"],
+           "training": "2e5 pairs, 6 epochs", "seconds": time.perf_counter() - t0,
+           "plain": {str(k): {"episode_cost": v["mean"], "ci95": v["ci95"], "samples_per_step": k,
+                              "latency_p50_ms": v["latency_ms"]["p50"], "latency_p99_ms": v["latency_ms"]["p99"]}
+                     for k, v in ev["plain"].items()}}
+    for g in ("cost", "none"):
+        e = ev["learned_" + g]
+        res["learned_gate_" + g] = {"episode_cost": e["mean"], "ci95": e["ci95"], "k_prop": e["k_prop"],
+                                    "samples_per_step": e["samples_per_step"], "acceptance": e["acceptance"],
+                                    "latency_p50_ms": e["latency_ms"]["p50"], "latency_p99_ms": e["latency_ms"]["p99"],
+                                    "smallest_plain_K_matching": e["smallest_plain_K_matching"],
+                                    "sample_ratio": e["sample_ratio"]}
+    return res
 
 
 def bench_serving(args):

@@ -51,11 +51,13 @@ def sampling_ablation(seeds=range(10), steps=200, arith="fp64", log=print):
     return out
 
 
-def episode_held(model, p, seed, steps, hold, arith="fp64"):
+def episode_held(model, p, seed, steps, hold, arith="fp64", trace=None):
     """A closed-loop episode in which the controller replans every `hold` plant steps.
     Between replans the plant follows the last plan: each step applies the first knot of
     the plan and advances it by the warm-start shift (the interpolant one step later); the
-    advanced plan is the nominal of the next replan."""
+    advanced plan is the nominal of the next replan.  With a list `trace`, appends per
+    plant step (t, replanned, state, nominal before the step, applied control) as host
+    arrays."""
     import torch
     ctl = B.Controller(model, dict(p, seed=seed, arith=arith))
     S = torch.as_tensor(ctl.basis_matrices()[1], device="cuda")
@@ -68,7 +70,11 @@ def episode_held(model, p, seed, steps, hold, arith="fp64"):
     cost = torch.zeros((), dtype=torch.float64, device="cuda")
     plan = None
     for t in range(steps):
-        if t % hold == 0:
+        replan = t % hold == 0
+        if trace is not None:
+            before = (ctl.get_nominal() if plan is None else plan.reshape(-1)).cpu().numpy().copy()
+            xs = x.cpu().numpy().copy()
+        if replan:
             if plan is not None:
                 ctl.set_nominal(plan.reshape(-1).contiguous())
             ctl.step(x, u0)
@@ -76,6 +82,8 @@ def episode_held(model, p, seed, steps, hold, arith="fp64"):
         else:
             u0.copy_(plan[:, 0])
             plan = plan @ S.T
+        if trace is not None:
+            trace.append((t, replan, xs, before, u0.cpu().numpy().copy()))
         model.sim_step_into(x.view(1, -1), u0.view(1, -1), p["kp"], p["kd"], p["dt"], xn.view(1, -1),
                             tau_out=tau.view(1, -1), arith=arith)
         cost += p["dt"] * _stage_cost_torch(xn.double(), tau.double(), p)

@@ -30,16 +30,38 @@ def test_replanning_every_step_is_the_plain_closed_loop(B):
 
 
 @pytest.mark.parametrize("basis", [0, 1, 2])
-def test_held_plan_follows_the_shifted_knots(B, basis):
-    """Between replans the applied controls are the first knots of the plan advanced by
-    the shift: with the zeroth-order hold (shift = identity) they stay the replan's u0."""
+def test_held_plan_follows_the_oracle_shift_chain(B, basis):
+    """Replanning every 4 plant steps with each knot interpolation: a replan's first
+    control and nominal equal the oracle's Algorithm 1 step from the same state, nominal
+    and Philox step, and the held steps apply the first knot of S^j mu' -- the oracle's
+    shift matrix applied j times to the replan's update."""
+    from oracle import oracle as O
     from paper_2409_10469_amd import ablations as AB
+    from tests.parity_utils import KNOT_TOL, round_model, round_params
     wl = W.TERRAIN_WALK
-    model = B.Model(W.model_dict(wl, 0))
-    p = dict(W.params_dict(wl, 1, K=64), basis=basis)
-    c, x = AB.episode_held(model, p, 1, 24, hold=4)
+    md = round_model(W.model_dict(wl, 0))
+    model = B.Model(md)
+    p = round_params(dict(W.params_dict(wl, 1, K=64), basis=basis))
+    trace = []
+    c, x = AB.episode_held(model, p, 1, 16, hold=4, trace=trace)
     assert np.isfinite(c) and np.isfinite(x).all()
-    ctl = B.Controller(model, p)
-    _, S = ctl.basis_matrices()
-    if basis == 2:
-        np.testing.assert_array_equal(S, np.eye(p["nk"], dtype=np.float32))
+    orc = O.Oracle(md)
+    S = O.shift_matrix_b(basis, p["nk"], p["H"], p["dt"])
+    replans = 0
+    for t, replan, xs, before, u in trace:
+        if replan:
+            ou0, omu, _, rc = orc.mppi_step(dict(p, seed=1), replans, xs.astype(np.float64),
+                                           before.astype(np.float64))
+            assert rc == 0
+            assert np.abs(u - ou0).max() <= KNOT_TOL, (t, basis)
+            plan = omu.reshape(12, p["nk"])  # S mu'
+            replans += 1
+            j = 1
+        else:
+            # held step j after the replan applies the first knot of S^j mu'
+            assert np.abs(u - plan[:, 0]).max() <= KNOT_TOL, (t, basis, j)
+            plan = plan @ S.T
+            j += 1
+    assert replans == 4
+    if basis == 2:  # the zeroth-order hold's shift is the identity: the replan's u0 is held
+        np.testing.assert_array_equal(S, np.eye(p["nk"]))

@@ -136,7 +136,8 @@ def test_rollout_trajectory_is_a_chain_of_oracle_steps(B):
 
 
 # ---------------------------------------------------------------------------- a10
-@pytest.mark.parametrize("K,nk,lam", [(64, 4, 0.1), (1024, 6, 0.05), (300, 8, 0.05), (1, 4, 0.1)])
+@pytest.mark.parametrize("K,nk,lam", [(64, 4, 0.1), (1024, 6, 0.05), (300, 8, 0.05), (1, 4, 0.1), (1025, 6, 0.05),
+                                      (2048, 8, 0.05), (4096, 8, 0.05)])
 def test_update_with_identical_costs(B, K, nk, lam):
     md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=K, nk=nk, lam=lam)
     rng = np.random.default_rng(K)
@@ -171,6 +172,17 @@ def test_update_nonfinite_costs(B):
 
 
 # ---------------------------------------------------------------------------- a1-a11
+def r16_knot_sensitivity(p, step, mu, costs):
+    """First-order change of the updated knots when every cost moves by the cost
+    tolerance: sum_n (w_n / lambda) |L_n| COST_TOL |theta_n - mu'|, max over knots."""
+    w, _ = O.weights(costs, p["lam"])
+    theta = mu + p["sigma"] * O.sample_eps(p, step)
+    theta[0] = mu
+    mup = w @ theta
+    ok = np.isfinite(costs)
+    return float((w[ok, None] * np.abs(costs[ok, None]) * np.abs(theta[ok] - mup)).sum(0).max() / p["lam"] * COST_TOL)
+
+
 def test_mppi_step_flat_walk_matches_oracle(B):
     """One full control step of the flat walking workload (K=64, H=25, dt=0.02, nk=4)."""
     md, p, orc, model, ctl = _setup(B, W.FLAT_WALK)
@@ -183,9 +195,12 @@ def test_mppi_step_flat_walk_matches_oracle(B):
         nominal = ctl.get_nominal().cpu().numpy()
         assert ctl.sync_status() == 0 and ctl.step_counter == seed + 1
         ou0, omu, ocosts, rc = orc.mppi_step(p, seed, x0, mu)
-        w, _ = O.weights(ocosts, p["lam"])
-        ess = 1.0 / np.sum(w ** 2)
-        assert ess >= 1.0
+        # R16: the weights are sharp here (effective sample size 1-2 of 64), so the knot
+        # comparison is meaningful only if cost errors at the cost tolerance move the
+        # update by less than the knot tolerance; to first order d mu' / d L_n =
+        # -(w_n / lambda) (theta_n - mu')
+        sens = r16_knot_sensitivity(p, seed, mu, ocosts)
+        assert sens <= KNOT_TOL, sens
         assert np.abs(u0.cpu().numpy() - ou0).max() <= KNOT_TOL, seed
         assert np.abs(nominal - omu).max() <= KNOT_TOL, seed
 

@@ -7,8 +7,10 @@ that faulted the GPU, stay skipped with the reason.
 Tolerances (relative L2 over the compared array unless stated):
   forward vs the BF16-operand oracle       <= 1e-3  (same operand roundings; FP32 vs FP64
                                                       sums can flip a rare bf16 rounding)
-  gradient vs the BF16-operand oracle      <= 1e-2  per layer (the backward rounds dz to
-                                                      bf16 too, so flips compound)
+  gradient vs the BF16-operand oracle      <= 1e-2  per weight matrix and per bias vector,
+                                                      both max |diff| / max |ref| and relative
+                                                      L2 (the backward rounds dz to bf16 too,
+                                                      so flips compound)
   gradient vs the exact FP64 oracle        <= 2e-2, cosine >= 0.999
   Adam vs FP64 Adam on the same gradient   per element: FP32 rounding of the master weight
                                            each step plus 1e-6 of the step size
@@ -49,12 +51,24 @@ def _params(pol):
     return pol.get_params().cpu().numpy().astype(np.float64)
 
 
-def _layer_slices():
+def _tensor_slices():
+    """(name, slice) of every weight matrix and every bias vector in the flat vector."""
     out, off = [], 0
-    for fi, fo in zip(O.MLP_DIMS[:-1], O.MLP_DIMS[1:]):
-        out.append(slice(off, off + fi * fo + fo))
+    for l, (fi, fo) in enumerate(zip(O.MLP_DIMS[:-1], O.MLP_DIMS[1:])):
+        out.append((f"W{l}", slice(off, off + fi * fo)))
+        out.append((f"b{l}", slice(off + fi * fo, off + fi * fo + fo)))
         off += fi * fo + fo
     return out
+
+
+def _per_tensor(G, R, tol):
+    """Each weight matrix and each bias vector on its own: max |G - R| <= tol max |R| and
+    relative L2 <= tol (a bias gradient is too small a share of its layer's norm to be
+    checked through the layer)."""
+    for name, sl in _tensor_slices():
+        worst = np.abs(G[sl] - R[sl]).max() / max(np.abs(R[sl]).max(), 1e-30)
+        assert worst <= tol, (name, worst)
+        assert _rel(G[sl], R[sl]) <= tol, (name, _rel(G[sl], R[sl]))
 
 
 # ---------------------------------------------------------------------------- forward
@@ -99,8 +113,7 @@ def test_gradient_matches_oracle(B, Bsz, gather):
     Lb, Gb = O.mlp_grad(P, X, Y, bf16=True)
     Le, Ge = O.mlp_grad(P, X, Y)
     assert abs(float(loss.item()) - Lb) <= 1e-3 * abs(Lb)
-    for sl in _layer_slices():
-        assert _rel(G[sl], Gb[sl]) <= 1e-2, (sl, _rel(G[sl], Gb[sl]))
+    _per_tensor(G, Gb, 1e-2)
     assert _rel(G, Ge) <= 2e-2
     assert G @ Ge / (np.linalg.norm(G) * np.linalg.norm(Ge)) >= 0.999
 
@@ -119,8 +132,7 @@ def test_gradient_with_batch_splits_matches_oracle(B):
     G = G.cpu().numpy().astype(np.float64)
     Lb, Gb = O.mlp_grad(P, f32(Xall[idx]), f32(Yall[idx]), bf16=True)
     assert abs(float(loss.item()) - Lb) <= 1e-3 * abs(Lb)
-    for sl in _layer_slices():
-        assert _rel(G[sl], Gb[sl]) <= 1e-2, (sl, _rel(G[sl], Gb[sl]))
+    _per_tensor(G, Gb, 1e-2)
 
 
 def test_gradient_is_deterministic(B):
@@ -219,8 +231,14 @@ def _ctl(B, K=64, H=10):
     return md, p, O.Oracle(md), B.Controller(B.Model(md), p)
 
 
-@pytest.mark.skip(reason="the proposal control step faulted the GPU (memory aperture violation) on its first "
-                         "run and no cause has been identified; the step is switched off in the library")
+FAULTED = ("records the first implementation of the proposal step, which passed the per-knot std, the "
+           "sample-1 override and the gate as new arguments of the quad rollout kernel; that build faulted the GPU "
+           "(memory aperture violation in rollout_kernel<0, double>) on its first run and no cause was shown, so "
+           "the change was taken out; the step now runs on the unchanged kernels "
+           "(test_proposal_step_on_plain_kernels_matches_oracle)")
+
+
+@pytest.mark.skip(reason=FAULTED)
 @pytest.mark.parametrize("accept", [True, False])
 def test_step_proposal_matches_oracle(B, accept):
     md, p, orc, ctl = _ctl(B)
@@ -238,20 +256,17 @@ def test_step_proposal_matches_oracle(B, accept):
     Kp = 16
     ctl.set_nominal(_dev(nominal))
     ctl.set_step(5)
-    u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), Kp, gate=gate).cpu().numpy()
+    u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), Kp).cpu().numpy()
     nom = ctl.get_nominal().cpu().numpy()
     acc, steps = ctl.proposal_stats()
-    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp,
-                                                         gate=0 if gate == "cost" else 1)
-    taken = accept or gate == "none"
-    assert oacc == taken and acc == int(taken) and steps == 1
+    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp)
+    assert oacc == accept and acc == int(accept) and steps == 1
     assert ctl.sync_status() == 0 and ctl.step_counter == 6
     assert np.abs(u0 - ou0).max() <= KNOT_TOL
     assert np.abs(nom - onom).max() <= KNOT_TOL
 
 
-@pytest.mark.skip(reason="the proposal control step faulted the GPU (memory aperture violation) on its first "
-                         "run and no cause has been identified; the step is switched off in the library")
+@pytest.mark.skip(reason=FAULTED)
 def test_learned_step_matches_oracle_chain(B):
     """mppi_step through the policy: features, BF16 forward, head and proposal step against
     the oracle's features, BF16-operand forward, head and proposal step."""
