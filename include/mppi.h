@@ -55,8 +55,12 @@ enum {
 
 /* Arithmetic of one dynamics step.  The state is FP32 between steps in both modes. */
 enum {
-    MPPI_ARITH_FP64 = 0, /* default: step computed in FP64 (FP32-state-limited accuracy) */
-    MPPI_ARITH_FP32 = 1  /* step computed in FP32: faster, per-step error set by the contact conditioning */
+    MPPI_ARITH_FP64 = 0,  /* default: step computed in FP64 (FP32-state-limited accuracy) */
+    MPPI_ARITH_FP32 = 1,  /* step computed in FP32: faster, per-step error set by the contact conditioning */
+    MPPI_ARITH_MIXED = 2  /* kinematics, contact detection and law in FP32; the implicit system (mass matrix,
+                             bias, contact damping and forces, leg elimination, 6x6 solves) in FP64.  Lane-split
+                             rollout only (MPPI_LANES_SPLIT or DEFAULT); other kernels of the controller (the
+                             tracking cost) run in FP32 */
 };
 
 #define MPPI_MAX_KNOTS 8
@@ -97,7 +101,7 @@ typedef struct mppi_params {
     float goal[2];
     uint64_t seed;
     uint32_t instance;
-    int32_t arith;              /* MPPI_ARITH_FP64 (0, default) or MPPI_ARITH_FP32 */
+    int32_t arith;              /* MPPI_ARITH_FP64 (0, default), MPPI_ARITH_FP32 or MPPI_ARITH_MIXED */
     int32_t basis;              /* knot interpolation, MPPI_BASIS_* (0: cubic, the default) */
     int32_t cost;               /* MPPI_COST_RUNNING (0, default) or MPPI_COST_TRACKING */
     int32_t lanes;              /* lanes per sample of the rollout kernel, MPPI_LANES_* (0: default) */
@@ -238,7 +242,7 @@ mppi_status mppi_sync_status(mppi_ctx *ctx);
 /* One dynamics step for n independent states (the plant of a closed loop):
  * x_out = step(x, u) with joint targets d_u (n x 12), PD gains kp, kd, time step dt.
  * d_tau_out (optional) receives the PD torques (n x 12).  d_hf: device heightfield for
- * scene 1 (may be NULL otherwise). */
+ * scene 1 (may be NULL otherwise).  arith: MPPI_ARITH_*; MPPI_ARITH_MIXED steps in FP64. */
 mppi_status mppi_sim_step(const mppi_model *model, int arith, int n, const float *d_x, const float *d_u, float kp,
                           float kd, float dt, float *d_x_out, float *d_tau_out, const float *d_hf, void *hip_stream);
 

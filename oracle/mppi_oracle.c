@@ -848,6 +848,30 @@ int orc_step_system(const orc_model *m, const double *x, const double *u, double
     return s.n_active;
 }
 
+int orc_step_system_box(const orc_model *m, const double *x, const double *u, double kp, double kd, double dt,
+                        double *A_out, double *rhs_out)
+{
+    (void)u; (void)kp; (void)kd;
+    if (m->scene != ORC_SCENE_FREE_BOX) return -1;
+    tree_t t; fk_t k;
+    build_tree(m, &t);
+    fk_compute(m, &t, x, &k);
+    double f[ORC_NV] = {0}, D[ORC_NV * ORC_NV] = {0}, fbox[6] = {0}, Dbox[36] = {0};
+    cstate_t s;
+    contact_setup(m, &t, &k, x, &s, f, D, fbox, Dbox);
+    all_contacts(&s);
+    const double *xb = x + ORC_NX, *wb = xb + 10;
+    double mb = m->box_mass, sx = 2 * m->box_half[0], sy = 2 * m->box_half[1], sz = 2 * m->box_half[2];
+    double Ib[3] = {mb * (sy * sy + sz * sz) / 12, mb * (sx * sx + sz * sz) / 12, mb * (sx * sx + sy * sy) / 12};
+    double Iw[3] = {Ib[0] * wb[0], Ib[1] * wb[1], Ib[2] * wb[2]}, gyro[3];
+    cross3(wb, Iw, gyro);
+    double bb[6] = {0, 0, mb * m->gravity, gyro[0], gyro[1], gyro[2]};
+    for (int i = 0; i < 36; ++i) A_out[i] = dt * Dbox[i];
+    for (int i = 0; i < 3; ++i) { A_out[i * 6 + i] += mb; A_out[(3 + i) * 6 + 3 + i] += Ib[i]; }
+    for (int i = 0; i < 6; ++i) rhs_out[i] = dt * (fbox[i] - bb[i]);
+    return s.n_active;
+}
+
 void orc_contact_total(const orc_model *m, const double *x, double *F_robot, double *F_box, int *n_active)
 {
     tree_t t; fk_t k;

@@ -89,6 +89,9 @@ int  orc_step(const orc_model *m, const double *x, const double *u, double kp, d
               double *xo, double *tau_out);
 int  orc_step_system(const orc_model *m, const double *x, const double *u, double kp, double kd, double dt,
                      double *A_out, double *rhs_out);
+/* the free box's 6x6 system of the same step, A_b dv_b = rhs_b (scene 3), for diagnostics */
+int  orc_step_system_box(const orc_model *m, const double *x, const double *u, double kp, double kd, double dt,
+                         double *A_out /*36*/, double *rhs_out /*6*/);
 void orc_contact_total(const orc_model *m, const double *x, double *F_robot /*3*/, double *F_box /*3*/, int *n_active);
 /* contact geometry and law, exported for their pins (quat is the box orientation, w x y z):
    terrain below a sphere (r > 0) or point (r = 0); sphere against an oriented box (normal

@@ -117,6 +117,7 @@ def lib():
             "orc_step": (C.c_int, [mp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]),
             "orc_contact_total": (None, [mp, dp, dp, dp, C.POINTER(C.c_int)]),
             "orc_step_system": (C.c_int, [mp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]),
+            "orc_step_system_box": (C.c_int, [mp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]),
             "orc_terrain": (C.c_int, [mp, dp, C.c_double, dp, dp]),
             "orc_sphere_box": (C.c_int, [dp, C.c_double, dp, dp, dp, dp, dp]),
             "orc_point_box": (C.c_int, [dp, dp, dp, dp, dp, dp]),
@@ -279,6 +280,13 @@ class Oracle:
         Fr, Fb, n = np.zeros(3), np.zeros(3), C.c_int(0)
         self.L.orc_contact_total(C.byref(self.m), _dp(_f64(x, self.nx)), _dp(Fr), _dp(Fb), C.byref(n))
         return Fr, Fb, n.value
+
+    def step_system_box(self, x, u, kp, kd, dt):
+        """The free box's 6x6 system of the step (scene 3): A_b, rhs_b, active contacts."""
+        A, r = np.zeros((6, 6)), np.zeros(6)
+        n = self.L.orc_step_system_box(C.byref(self.m), _dp(_f64(x, self.nx)), _dp(_f64(u, 12)), float(kp),
+                                       float(kd), float(dt), _dp(A), _dp(r))
+        return A, r, n
 
     def terrain(self, c, r):
         d, n = C.c_double(0), np.zeros(3)

@@ -343,8 +343,8 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     if (p->H < 1 || p->H > MPPI_MAX_HORIZON) return fail(nullptr, MPPI_EINVAL, "H must be in [1, 256]");
     if (p->n_knots < 2 || p->n_knots > MPPI_MAX_KNOTS) return fail(nullptr, MPPI_EINVAL, "n_knots must be in [2, 8]");
     if (!finite_pos(p->dt)) return fail(nullptr, MPPI_EINVAL, "dt must be > 0");
-    if (p->arith != MPPI_ARITH_FP64 && p->arith != MPPI_ARITH_FP32)
-        return fail(nullptr, MPPI_EINVAL, "arith must be MPPI_ARITH_FP64 or MPPI_ARITH_FP32");
+    if (p->arith != MPPI_ARITH_FP64 && p->arith != MPPI_ARITH_FP32 && p->arith != MPPI_ARITH_MIXED)
+        return fail(nullptr, MPPI_EINVAL, "arith must be MPPI_ARITH_FP64, _FP32 or _MIXED");
     if (!finite_pos(p->lambda)) return fail(nullptr, MPPI_EINVAL, "lambda must be > 0");
     if (!(p->sigma >= 0.f) || !std::isfinite(p->sigma)) return fail(nullptr, MPPI_EINVAL, "sigma must be >= 0");
     if (!std::isfinite(p->kp) || !std::isfinite(p->kd) || p->kd < 0.f)
@@ -361,7 +361,12 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
         return fail(nullptr, MPPI_EINVAL, "the lane-split rollout's LDS does not fit this heightfield");
     mppi_ctx* c = new (std::nothrow) mppi_ctx();
     if (!c) return fail(nullptr, MPPI_ENOMEM, "host allocation failed");
-    c->split = p->lanes == MPPI_LANES_SPLIT || (p->lanes == MPPI_LANES_DEFAULT && kSplitByDefault && split_fits);
+    if (p->arith == MPPI_ARITH_MIXED && (p->lanes == MPPI_LANES_QUAD || !split_fits)) {
+        delete c;
+        return fail(nullptr, MPPI_EINVAL, "MPPI_ARITH_MIXED needs the lane-split rollout");
+    }
+    c->split = p->lanes == MPPI_LANES_SPLIT ||
+               (p->lanes == MPPI_LANES_DEFAULT && split_fits && (kSplitByDefault || p->arith == MPPI_ARITH_MIXED));
     c->model = *model;
     c->p = *p;
     c->D = 12 * p->n_knots;
@@ -530,7 +535,8 @@ static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, f
     t.dt = c->p.dt;
     t.step = c->step;
     t.costs = d_costs;
-    return hip_check(c, track::launch_tracking_cost(c->p.arith, t, d_x0, wsf(c, c->off_uref), c->stream),
+    const int track_arith = c->p.arith == MPPI_ARITH_FP64 ? MPPI_ARITH_FP64 : MPPI_ARITH_FP32;
+    return hip_check(c, track::launch_tracking_cost(track_arith, t, d_x0, wsf(c, c->off_uref), c->stream),
                      "tracking cost launch");
 }
 
@@ -787,7 +793,9 @@ mppi_status mppi_proposal_stats(mppi_ctx* c, int* accepted, int* steps)
 mppi_status mppi_sim_step(const mppi_model* m, int arith, int n, const float* d_x, const float* d_u, float kp,
                           float kd, float dt, float* d_x_out, float* d_tau_out, const float* d_hf, void* stream)
 {
-    if (arith != MPPI_ARITH_FP64 && arith != MPPI_ARITH_FP32) return fail(nullptr, MPPI_EINVAL, "bad arith");
+    if (arith != MPPI_ARITH_FP64 && arith != MPPI_ARITH_FP32 && arith != MPPI_ARITH_MIXED)
+        return fail(nullptr, MPPI_EINVAL, "bad arith");
+    if (arith == MPPI_ARITH_MIXED) arith = MPPI_ARITH_FP64;  // the plant step has no mixed variant
     if (!m || n < 0 || !d_x || !d_u || !d_x_out) return fail(nullptr, MPPI_EINVAL, "null argument or n < 0");
     if (!finite_pos(dt) || !std::isfinite(kp) || !(kd >= 0.f)) return fail(nullptr, MPPI_EINVAL, "bad dt/kp/kd");
     if (m->desc.scene == MPPI_SCENE_HEIGHTFIELD && !d_hf) return fail(nullptr, MPPI_EINVAL, "heightfield scene needs d_hf");

@@ -57,26 +57,113 @@ __device__ __forceinline__ R sel(bool c, R a, R b)
     return c ? a : b;
 }
 
+template <typename R>
+__device__ __forceinline__ V3<R> selv(bool c, V3<R> a, V3<R> b)
+{
+    return v3(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z);
+}
+
+// pose and velocity of a rigid body (the trunk or the free box): rotation to world,
+// position, world linear velocity, body-frame angular velocity
+template <typename R>
+struct Pose {
+    M33<R> Rt;
+    V3<R> p, vw, w;
+};
+template <typename R>
+__device__ __forceinline__ V3<R> pose_point_vel(const Pose<R>& B, V3<R> x)
+{
+    return B.vw + mul(B.Rt, cross(B.w, mulT(B.Rt, x - B.p)));
+}
+template <typename R>
+__device__ __forceinline__ Pose<R> sel_pose(bool c, const Pose<R>& a, const Pose<R>& b)
+{
+    Pose<R> o;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o.Rt.m[i] = c ? a.Rt.m[i] : b.Rt.m[i];
+    o.p = selv(c, a.p, b.p);
+    o.vw = selv(c, a.vw, b.vw);
+    o.w = selv(c, a.w, b.w);
+    return o;
+}
+
+template <typename T, typename U>
+__device__ __forceinline__ V3<T> cv(V3<U> a)
+{
+    return V3<T>{T(a.x), T(a.y), T(a.z)};
+}
+
+// a contact on the leg's calf with weight wgt (1: applied, 0: nothing added).  The contact
+// velocity and the law are evaluated in the geometry type R; the force and damping terms
+// on the trunk's base rows and on the leg's joint rows accumulate in the system type S.
+template <typename R, typename S>
+__device__ __forceinline__ void leg_contact_w(const ModelT<R>& M, const LegGeo<R>& G, V3<R> vb, V3<R> w,
+                                              const R qd[3], R delta, V3<R> n, V3<R> r, V3<R> vo, S dt, R wgt, S* Q,
+                                              S* rb, LegSys<S>& L, V3<R>& F, R& eta)
+{
+    const V3<R> ex = v3(R(1), R(0), R(0));
+    const V3<R> ja = cross(ex, r - G.h), jf = cross(G.ey, r - G.h), jk = cross(G.ey, r - G.pk);
+    const V3<R> vc = vb + cross(w, r) + qd[0] * ja + qd[1] * jf + qd[2] * jk - vo;
+    contact_law(M, delta, n, vc, F, eta);
+    F = wgt * F;
+    eta = wgt * eta;
+    const S e = S(eta), cw = S(wgt) * S(M.cc);
+    const S ce = cw - e;
+    const V3<S> rs = cv<S>(r), ns = cv<S>(n), Fs = cv<S>(F);
+    base_contact(e, cw, rs, ns, Fs, dt, Q, rb);
+    const V3<S> jv[3] = {cv<S>(ja), cv<S>(jf), cv<S>(jk)};
+    const S gj[3] = {dot(jv[0], ns), dot(jv[1], ns), dot(jv[2], ns)};
+    const V3<S> gA = cross(rs, ns);
+    const S g0[6] = {gA.x, gA.y, gA.z, ns.x, ns.y, ns.z};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const V3<S> rxj = cross(rs, jv[j]);
+        const S jb[6] = {rxj.x, rxj.y, rxj.z, jv[j].x, jv[j].y, jv[j].z};
+#pragma unroll
+        for (int i = 0; i < 6; ++i) L.C[j][i] += dt * (e * jb[i] + ce * g0[i] * gj[j]);
+        L.rl[j] += dt * dot(jv[j], Fs);
+    }
+    L.A00 += dt * (e * dot(jv[0], jv[0]) + ce * gj[0] * gj[0]);
+    L.A01 += dt * (e * dot(jv[0], jv[1]) + ce * gj[0] * gj[1]);
+    L.A02 += dt * (e * dot(jv[0], jv[2]) + ce * gj[0] * gj[2]);
+    L.A11 += dt * (e * dot(jv[1], jv[1]) + ce * gj[1] * gj[1]);
+    L.A12 += dt * (e * dot(jv[1], jv[2]) + ce * gj[1] * gj[2]);
+    L.A22 += dt * (e * dot(jv[2], jv[2]) + ce * gj[2] * gj[2]);
+}
+
+// contact terms of a force F at body-frame point r with normal n and secant eta (all in
+// the geometry type R) on a 6x6 body system accumulated in S
+template <typename R, typename S>
+__device__ __forceinline__ void body_contact(R eta, R c, V3<R> r, V3<R> n, V3<R> F, S dt, S* Q, S* rb)
+{
+    base_contact(S(eta), S(c), cv<S>(r), cv<S>(n), cv<S>(F), dt, Q, rb);
+}
+
 // ------------------------------------------------------------------------------
 // one dynamics step of one sample; lane g (0..15) of the sample, leg g >> 2, sub-lane
-// g & 3.  uj: the joint target this lane interpolated (joint g & 3 of its leg, lanes 3
+// g & 3.  R: the geometry type (kinematics, contact detection and law, state); S: the
+// system type (mass matrix, bias, contact damping and forces as terms of the implicit
+// system, the leg elimination, the sums and the 6x6 solves).  MR / MS: the model in
+// both.  uj: the joint target this lane interpolated (joint g & 3 of its leg, lanes 3
 // repeat joint 2).  red / sred: this sample's LDS rows.  tau2 receives sum tau^2.
 // ------------------------------------------------------------------------------
-template <int SCENE, typename R>
-__device__ __forceinline__ void step16(const ModelT<R>& M, const float* __restrict__ hf, R dt, R kp, R kd, int g,
-                                       Base<R>& b, Leg<R>& lg, BoxS<R>& bx, R uj, R* red, R* sred, R& tau2)
+template <int SCENE, typename R, typename S>
+__device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS, const float* __restrict__ hf, S dt,
+                                       S kp, S kd, int g, Base<R>& b, Leg<R>& lg, BoxS<R>& bx, R uj, S* red,
+                                       S* sred, R& tau2)
 {
     const int leg = g >> 2, sub = g & 3;
+    const R dtr = R(dt);
     const R u[3] = {dpp<0x00>(uj), dpp<0x55>(uj), dpp<0xAA>(uj)};
-    R tau[3];
+    S tau[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) tau[j] = kp * (u[j] - lg.q[j]) - kd * lg.qd[j];
-    const R t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+    for (int j = 0; j < 3; ++j) tau[j] = kp * (S(u[j]) - S(lg.q[j])) - kd * S(lg.qd[j]);
+    const S t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
 
     const M33<R> Rm = quat_R(b.qw, b.qx, b.qy, b.qz);
     const V3<R> w = b.w;
     const V3<R> vb = mulT(Rm, b.vw);
-    const V3<R> gb = (-M.g) * v3(Rm.m[6], Rm.m[7], Rm.m[8]);
+    const V3<R> gb = (-MR.g) * v3(Rm.m[6], Rm.m[7], Rm.m[8]);
 
     // ---- leg kinematics: lane `sub` evaluates angle sub of the leg, the quad shares them
     R sn, cs;
@@ -88,217 +175,263 @@ __device__ __forceinline__ void step16(const ModelT<R>& M, const float* __restri
     const R sf = dpp<0x55>(sn), cf = dpp<0x55>(cs);
     const R s12 = dpp<0xAA>(sn), c12 = dpp<0xAA>(cs);
     LegGeo<R> G;
-    const V3<R> ex = v3(R(1), R(0), R(0));
     G.ey = v3(R(0), ca, sa);
     G.d1 = v3(-sf, sa * cf, -ca * cf);
     G.d2 = v3(-s12, sa * c12, -ca * c12);
-    G.h = v3((leg < 2) ? M.hip_x : -M.hip_x, (leg & 1) ? -M.hip_y : M.hip_y, R(0));
-    G.pk = G.h + M.l1 * G.d1;
-    G.pf = G.pk + M.l2 * G.d2;
-    G.c1 = G.h + (R(0.5) * M.l1) * G.d1;
-    G.c2 = G.pk + (R(0.5) * M.l2) * G.d2;
-    const V3<R> ey = G.ey, d1 = G.d1, d2 = G.d2, h = G.h, pk = G.pk, c1 = G.c1, c2 = G.c2;
-    const R dqa = lg.qd[0], dqf = lg.qd[1], dqk = lg.qd[2];
+    G.h = v3((leg < 2) ? MR.hip_x : -MR.hip_x, (leg & 1) ? -MR.hip_y : MR.hip_y, R(0));
+    G.pk = G.h + MR.l1 * G.d1;
+    G.pf = G.pk + MR.l2 * G.d2;
+    G.c1 = G.h + (R(0.5) * MR.l1) * G.d1;
+    G.c2 = G.pk + (R(0.5) * MR.l2) * G.d2;
+
+    // the leg's geometry and velocities in the system type
+    const V3<S> ex = v3(S(1), S(0), S(0));
+    const V3<S> ey = cv<S>(G.ey), d1 = cv<S>(G.d1), d2 = cv<S>(G.d2), h = cv<S>(G.h), pk = cv<S>(G.pk),
+                c1 = cv<S>(G.c1), c2 = cv<S>(G.c2);
+    const V3<S> ws = cv<S>(w), gbs = cv<S>(gb);
+    const S dqa = S(lg.qd[0]), dqf = S(lg.qd[1]), dqk = S(lg.qd[2]);
 
     // ---- the leg's mass-matrix terms: base block, coupling columns, leg block
-    R Q[21];
+    S Q[21];
 #pragma unroll
-    for (int i = 0; i < 21; ++i) Q[i] = R(0);
+    for (int i = 0; i < 21; ++i) Q[i] = S(0);
     {
-        const R r1 = dot(c1, c1), r2 = dot(c2, c2);
-        const R cv1[3] = {c1.x, c1.y, c1.z}, cv2[3] = {c2.x, c2.y, c2.z};
-        const R d1v[3] = {d1.x, d1.y, d1.z}, d2v[3] = {d2.x, d2.y, d2.z};
+        const S r1 = dot(c1, c1), r2 = dot(c2, c2);
+        const S cv1[3] = {c1.x, c1.y, c1.z}, cv2[3] = {c2.x, c2.y, c2.z};
+        const S d1v[3] = {d1.x, d1.y, d1.z}, d2v[3] = {d2.x, d2.y, d2.z};
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = i; j < 3; ++j) {
-                const R I = (i == j) ? R(1) : R(0);
-                Q[s6(i, j)] = M.k1 * (I - d1v[i] * d1v[j]) + M.k2 * (I - d2v[i] * d2v[j]) +
-                              M.m1 * (r1 * I - cv1[i] * cv1[j]) + M.m2 * (r2 * I - cv2[i] * cv2[j]);
+                const S I = (i == j) ? S(1) : S(0);
+                Q[s6(i, j)] = MS.k1 * (I - d1v[i] * d1v[j]) + MS.k2 * (I - d2v[i] * d2v[j]) +
+                              MS.m1 * (r1 * I - cv1[i] * cv1[j]) + MS.m2 * (r2 * I - cv2[i] * cv2[j]);
             }
-        const V3<R> hl = M.m1 * c1 + M.m2 * c2;
+        const V3<S> hl = MS.m1 * c1 + MS.m2 * c2;
         Q[s6(0, 4)] = -hl.z; Q[s6(0, 5)] = hl.y;
         Q[s6(1, 3)] = hl.z;  Q[s6(1, 5)] = -hl.x;
         Q[s6(2, 3)] = -hl.y; Q[s6(2, 4)] = hl.x;
     }
-    LegSys<R> S;
+    LegSys<S> L;
     {
-        const V3<R> ua1 = cross(ex, c1 - h), ua2 = cross(ex, c2 - h);
-        const V3<R> uf1 = cross(ey, c1 - h), uf2 = cross(ey, c2 - h);
-        const V3<R> uk2 = cross(ey, c2 - pk);
-        const V3<R> Pa = M.m1 * ua1 + M.m2 * ua2;
-        const V3<R> La = M.m1 * cross(c1, ua1) + M.m2 * cross(c2, ua2) + rod_I(M.k1, d1, ex) + rod_I(M.k2, d2, ex);
-        const V3<R> Pf = M.m1 * uf1 + M.m2 * uf2;
-        const V3<R> Lf = M.m1 * cross(c1, uf1) + M.m2 * cross(c2, uf2) + rod_I(M.k1, d1, ey) + rod_I(M.k2, d2, ey);
-        const V3<R> Pk = M.m2 * uk2;
-        const V3<R> Lk = M.m2 * cross(c2, uk2) + rod_I(M.k2, d2, ey);
-        const V3<R> Ls[3] = {La, Lf, Lk}, Ps[3] = {Pa, Pf, Pk};
+        const V3<S> ua1 = cross(ex, c1 - h), ua2 = cross(ex, c2 - h);
+        const V3<S> uf1 = cross(ey, c1 - h), uf2 = cross(ey, c2 - h);
+        const V3<S> uk2 = cross(ey, c2 - pk);
+        const V3<S> Pa = MS.m1 * ua1 + MS.m2 * ua2;
+        const V3<S> La =
+            MS.m1 * cross(c1, ua1) + MS.m2 * cross(c2, ua2) + rod_I(MS.k1, d1, ex) + rod_I(MS.k2, d2, ex);
+        const V3<S> Pf = MS.m1 * uf1 + MS.m2 * uf2;
+        const V3<S> Lf =
+            MS.m1 * cross(c1, uf1) + MS.m2 * cross(c2, uf2) + rod_I(MS.k1, d1, ey) + rod_I(MS.k2, d2, ey);
+        const V3<S> Pk = MS.m2 * uk2;
+        const V3<S> Lk = MS.m2 * cross(c2, uk2) + rod_I(MS.k2, d2, ey);
+        const V3<S> Ls[3] = {La, Lf, Lk}, Ps[3] = {Pa, Pf, Pk};
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            S.C[j][0] = Ls[j].x; S.C[j][1] = Ls[j].y; S.C[j][2] = Ls[j].z;
-            S.C[j][3] = Ps[j].x; S.C[j][4] = Ps[j].y; S.C[j][5] = Ps[j].z;
+            L.C[j][0] = Ls[j].x; L.C[j][1] = Ls[j].y; L.C[j][2] = Ls[j].z;
+            L.C[j][3] = Ps[j].x; L.C[j][4] = Ps[j].y; L.C[j][5] = Ps[j].z;
         }
-        const V3<R> oxa_a = cross(h, ex), oxa_f = cross(h, ey), oxa_k = cross(pk, ey);
-        S.A00 = dot(ex, La) + dot(oxa_a, Pa);
-        S.A01 = dot(ex, Lf) + dot(oxa_a, Pf);
-        S.A02 = dot(ex, Lk) + dot(oxa_a, Pk);
-        S.A11 = dot(ey, Lf) + dot(oxa_f, Pf);
-        S.A12 = dot(ey, Lk) + dot(oxa_f, Pk);
-        S.A22 = dot(ey, Lk) + dot(oxa_k, Pk);
+        const V3<S> oxa_a = cross(h, ex), oxa_f = cross(h, ey), oxa_k = cross(pk, ey);
+        L.A00 = dot(ex, La) + dot(oxa_a, Pa);
+        L.A01 = dot(ex, Lf) + dot(oxa_a, Pf);
+        L.A02 = dot(ex, Lk) + dot(oxa_a, Pk);
+        L.A11 = dot(ey, Lf) + dot(oxa_f, Pf);
+        L.A12 = dot(ey, Lk) + dot(oxa_f, Pk);
+        L.A22 = dot(ey, Lk) + dot(oxa_k, Pk);
     }
 
     // ---- bias forces of the leg (zero generalized acceleration, gravity)
-    R rb[6];
+    S rb[6];
     {
-        const V3<R> w1 = w + dqa * ex + dqf * ey;
-        const V3<R> al1 = dqa * cross(w, ex) + dqf * cross(w + dqa * ex, ey);
-        const V3<R> ah = cross(w, cross(w, h));
-        const V3<R> r1 = c1 - h, rk = pk - h;
-        const V3<R> ac1 = ah + cross(al1, r1) + cross(w1, cross(w1, r1));
-        const V3<R> apk = ah + cross(al1, rk) + cross(w1, cross(w1, rk));
-        const V3<R> w2 = w1 + dqk * ey;
-        const V3<R> al2 = al1 + dqk * cross(w1, ey);
-        const V3<R> r2 = c2 - pk;
-        const V3<R> ac2 = apk + cross(al2, r2) + cross(w2, cross(w2, r2));
-        const V3<R> F1 = M.m1 * (ac1 - gb), F2 = M.m2 * (ac2 - gb);
-        const V3<R> N1 = rod_I(M.k1, d1, al1) + cross(w1, rod_I(M.k1, d1, w1));
-        const V3<R> N2 = rod_I(M.k2, d2, al2) + cross(w2, rod_I(M.k2, d2, w2));
-        const V3<R> Tk = N2 + cross(r2, F2);
-        const V3<R> Th = N1 + cross(r1, F1) + N2 + cross(c2 - h, F2);
-        const V3<R> Tb = N1 + N2 + cross(c1, F1) + cross(c2, F2);
-        const V3<R> Fb = F1 + F2;
+        const V3<S> w1 = ws + dqa * ex + dqf * ey;
+        const V3<S> al1 = dqa * cross(ws, ex) + dqf * cross(ws + dqa * ex, ey);
+        const V3<S> ah = cross(ws, cross(ws, h));
+        const V3<S> r1 = c1 - h, rk = pk - h;
+        const V3<S> ac1 = ah + cross(al1, r1) + cross(w1, cross(w1, r1));
+        const V3<S> apk = ah + cross(al1, rk) + cross(w1, cross(w1, rk));
+        const V3<S> w2 = w1 + dqk * ey;
+        const V3<S> al2 = al1 + dqk * cross(w1, ey);
+        const V3<S> r2 = c2 - pk;
+        const V3<S> ac2 = apk + cross(al2, r2) + cross(w2, cross(w2, r2));
+        const V3<S> F1 = MS.m1 * (ac1 - gbs), F2 = MS.m2 * (ac2 - gbs);
+        const V3<S> N1 = rod_I(MS.k1, d1, al1) + cross(w1, rod_I(MS.k1, d1, w1));
+        const V3<S> N2 = rod_I(MS.k2, d2, al2) + cross(w2, rod_I(MS.k2, d2, w2));
+        const V3<S> Tk = N2 + cross(r2, F2);
+        const V3<S> Th = N1 + cross(r1, F1) + N2 + cross(c2 - h, F2);
+        const V3<S> Tb = N1 + N2 + cross(c1, F1) + cross(c2, F2);
+        const V3<S> Fb = F1 + F2;
         rb[0] = -dt * Tb.x; rb[1] = -dt * Tb.y; rb[2] = -dt * Tb.z;
         rb[3] = -dt * Fb.x; rb[4] = -dt * Fb.y; rb[5] = -dt * Fb.z;
-        S.rl[0] = dt * (tau[0] - dot(ex, Th));
-        S.rl[1] = dt * (tau[1] - dot(ey, Th));
-        S.rl[2] = dt * (tau[2] - dot(ey, Tk));
+        L.rl[0] = dt * (tau[0] - dot(ex, Th));
+        L.rl[1] = dt * (tau[1] - dot(ey, Th));
+        L.rl[2] = dt * (tau[2] - dot(ey, Tk));
     }
-    S.A00 += dt * kd; S.A11 += dt * kd; S.A22 += dt * kd;
+    L.A00 += dt * kd; L.A11 += dt * kd; L.A22 += dt * kd;
 
     [[maybe_unused]] BoxFrame<R> bf;
-    [[maybe_unused]] R Qb[21], rbx[6];
+    [[maybe_unused]] S Qb[21], rbx[6];
     const V3<R> zero = v3(R(0), R(0), R(0));
     V3<R> F;
     R eta;
     if constexpr (SCENE == 3) {
         bf.Rb = quat_R(bx.qw, bx.qx, bx.qy, bx.qz);
 #pragma unroll
-        for (int i = 0; i < 21; ++i) Qb[i] = R(0);
+        for (int i = 0; i < 21; ++i) Qb[i] = S(0);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) rbx[i] = R(0);
+        for (int i = 0; i < 6; ++i) rbx[i] = S(0);
     }
 
-    // ---- the leg's foot against terrain and the static or free box
+    // ---- the leg's foot against terrain and the static or free box.  Each lane lists its
+    // foot's contacts (terrain, box) and the wave runs one contact body per listed entry:
+    // usually one pass, a second only where a foot touches both.
     {
         const V3<R> pfw = b.p + mul(Rm, G.pf);
-        R delta;
-        V3<R> nw;
-        if (terrain<SCENE>(M, hf, pfw, M.foot_r, delta, nw)) {
-            const V3<R> n = mulT(Rm, nw);
-            leg_contact(M, G, vb, w, lg.qd, delta, n, G.pf - M.foot_r * n, zero, dt, Q, rb, S, F, eta);
-        }
+        R dT, dB = R(0);
+        V3<R> nT, nB = zero;
+        const bool hitT = terrain<SCENE>(MR, hf, pfw, MR.foot_r, dT, nT);
+        bool hitB = false;
         if constexpr (SCENE == 2) {
-            const V3<R> l = pfw - v3(M.sb_cx, M.sb_cy, M.sb_cz);
-            if (sphere_aabox(l, M.foot_r, v3(M.sb_hx, M.sb_hy, M.sb_hz), delta, nw)) {
-                const V3<R> n = mulT(Rm, nw);
-                leg_contact(M, G, vb, w, lg.qd, delta, n, G.pf - M.foot_r * n, zero, dt, Q, rb, S, F, eta);
-            }
+            hitB = sphere_aabox(pfw - v3(MR.sb_cx, MR.sb_cy, MR.sb_cz), MR.foot_r, v3(MR.sb_hx, MR.sb_hy, MR.sb_hz),
+                                dB, nB);
         }
         if constexpr (SCENE == 3) {
             V3<R> nl;
-            if (sphere_aabox(mulT(bf.Rb, pfw - bx.p), M.foot_r, v3(M.bx_hx, M.bx_hy, M.bx_hz), delta, nl)) {
-                const V3<R> nb = mul(bf.Rb, nl);
-                const V3<R> pcw = pfw - M.foot_r * nb;
-                const V3<R> n = mulT(Rm, nb);
-                const V3<R> vo = mulT(Rm, box_point_vel(bx, bf, pcw));
-                leg_contact(M, G, vb, w, lg.qd, delta, n, G.pf - M.foot_r * n, vo, dt, Q, rb, S, F, eta);
-                box_share(M, bx, bf, pcw, nb, R(-1) * mul(Rm, F), eta, dt, Qb, rbx);
+            hitB = sphere_aabox(mulT(bf.Rb, pfw - bx.p), MR.foot_r, v3(MR.bx_hx, MR.bx_hy, MR.bx_hz), dB, nl);
+            nB = mul(bf.Rb, nl);  // box -> foot (world)
+        }
+        const int cnt = int(hitT) + int(hitB);
+#pragma unroll
+        for (int it = 0; it < ((SCENE == 2 || SCENE == 3) ? 2 : 1); ++it) {
+            if (!__builtin_amdgcn_ballot_w64(it < cnt)) break;
+            const bool isB = (it == 0) ? !hitT : true;  // pass 0: terrain if touched, else the box
+            const R wgt = (it < cnt) ? R(1) : R(0);
+            const R delta = isB ? dB : dT;
+            const V3<R> nw = selv(isB, nB, nT);
+            const V3<R> n = mulT(Rm, nw);
+            V3<R> vo = zero;
+            [[maybe_unused]] V3<R> pcw;
+            if constexpr (SCENE == 3) {
+                pcw = pfw - MR.foot_r * nw;
+                vo = selv(isB, mulT(Rm, box_point_vel(bx, bf, pcw)), zero);
+            }
+            leg_contact_w(MR, G, vb, w, lg.qd, delta, n, G.pf - MR.foot_r * n, vo, dt, wgt, Q, rb, L, F, eta);
+            if constexpr (SCENE == 3) {
+                // the box's share in its frame (zero weight for the terrain contact)
+                const R wb = isB ? wgt : R(0);
+                body_contact(wb * eta, wb * MR.cc, mulT(bf.Rb, pcw - bx.p), mulT(bf.Rb, nw),
+                             mulT(bf.Rb, (-wb) * mul(Rm, F)), dt, Qb, rbx);
             }
         }
     }
 
     // ---- eliminate the leg: W = A_ll^-1 A_l0, y = A_ll^-1 r_l
-    const Chol3<R> L3 = chol3(S.A00, S.A01, S.A11, S.A02, S.A12, S.A22);
-    R W[3][6];
+    const Chol3<S> L3 = chol3(L.A00, L.A01, L.A11, L.A02, L.A12, L.A22);
+    S W[3][6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        R x0 = S.C[0][i], x1 = S.C[1][i], x2 = S.C[2][i];
+        S x0 = L.C[0][i], x1 = L.C[1][i], x2 = L.C[2][i];
         solve3(L3, x0, x1, x2);
         W[0][i] = x0; W[1][i] = x1; W[2][i] = x2;
     }
-    R y0 = S.rl[0], y1 = S.rl[1], y2 = S.rl[2];
+    S y0 = L.rl[0], y1 = L.rl[1], y2 = L.rl[2];
     solve3(L3, y0, y1, y2);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
 #pragma unroll
-        for (int j = i; j < 6; ++j) Q[s6(i, j)] -= S.C[0][i] * W[0][j] + S.C[1][i] * W[1][j] + S.C[2][i] * W[2][j];
-        rb[i] -= S.C[0][i] * y0 + S.C[1][i] * y1 + S.C[2][i] * y2;
+        for (int j = i; j < 6; ++j) Q[s6(i, j)] -= L.C[0][i] * W[0][j] + L.C[1][i] * W[1][j] + L.C[2][i] * W[2][j];
+        rb[i] -= L.C[0][i] * y0 + L.C[1][i] * y1 + L.C[2][i] * y2;
     }
 
     // the leg's terms are the same in its four lanes: only sub-lane 0's copy is summed
     const bool keep = sub == 0;
 #pragma unroll
-    for (int i = 0; i < 21; ++i) Q[i] = sel(keep, Q[i], R(0));
+    for (int i = 0; i < 21; ++i) Q[i] = sel(keep, Q[i], S(0));
 #pragma unroll
-    for (int i = 0; i < 6; ++i) rb[i] = sel(keep, rb[i], R(0));
+    for (int i = 0; i < 6; ++i) rb[i] = sel(keep, rb[i], S(0));
     if constexpr (SCENE == 3) {
 #pragma unroll
-        for (int i = 0; i < 21; ++i) Qb[i] = sel(keep, Qb[i], R(0));
+        for (int i = 0; i < 21; ++i) Qb[i] = sel(keep, Qb[i], S(0));
 #pragma unroll
-        for (int i = 0; i < 6; ++i) rbx[i] = sel(keep, rbx[i], R(0));
+        for (int i = 0; i < 6; ++i) rbx[i] = sel(keep, rbx[i], S(0));
     }
 
     // ---- one corner per lane: trunk corner g (g < 8), free-box corner g - 8 (g >= 8)
-    if (g < 8) {
-        const V3<R> rloc = v3((g & 1 ? R(0.5) : R(-0.5)) * M.tsx, (g & 2 ? R(0.5) : R(-0.5)) * M.tsy,
-                              (g & 4 ? R(0.5) : R(-0.5)) * M.tsz);
-        const V3<R> pw = b.p + mul(Rm, rloc);
-        R delta;
-        V3<R> nw;
-        if (terrain<SCENE>(M, hf, pw, R(0), delta, nw))
-            trunk_contact(M, vb, w, delta, mulT(Rm, nw), rloc, zero, dt, Q, rb, F, eta);
-        if constexpr (SCENE == 2) {
-            if (point_aabox(pw - v3(M.sb_cx, M.sb_cy, M.sb_cz), v3(M.sb_hx, M.sb_hy, M.sb_hz), delta, nw))
-                trunk_contact(M, vb, w, delta, mulT(Rm, nw), rloc, zero, dt, Q, rb, F, eta);
-        }
-        if constexpr (SCENE == 3) {
-            V3<R> nl;
-            if (point_aabox(mulT(bf.Rb, pw - bx.p), v3(M.bx_hx, M.bx_hy, M.bx_hz), delta, nl)) {
-                const V3<R> nb = mul(bf.Rb, nl);
-                const V3<R> vo = mulT(Rm, box_point_vel(bx, bf, pw));
-                trunk_contact(M, vb, w, delta, mulT(Rm, nb), rloc, vo, dt, Q, rb, F, eta);
-                box_share(M, bx, bf, pw, nb, R(-1) * mul(Rm, F), eta, dt, Qb, rbx);
+    if constexpr (SCENE != 3) {
+        if (g < 8) {
+            const V3<R> rloc = v3((g & 1 ? R(0.5) : R(-0.5)) * MR.tsx, (g & 2 ? R(0.5) : R(-0.5)) * MR.tsy,
+                                  (g & 4 ? R(0.5) : R(-0.5)) * MR.tsz);
+            const V3<R> pw = b.p + mul(Rm, rloc);
+            R delta;
+            V3<R> nw;
+            if (terrain<SCENE>(MR, hf, pw, R(0), delta, nw)) {
+                const V3<R> n = mulT(Rm, nw);
+                contact_law(MR, delta, n, vb + cross(w, rloc), F, eta);
+                body_contact(eta, MR.cc, rloc, n, F, dt, Q, rb);
+            }
+            if constexpr (SCENE == 2) {
+                if (point_aabox(pw - v3(MR.sb_cx, MR.sb_cy, MR.sb_cz), v3(MR.sb_hx, MR.sb_hy, MR.sb_hz), delta, nw)) {
+                    const V3<R> n = mulT(Rm, nw);
+                    contact_law(MR, delta, n, vb + cross(w, rloc), F, eta);
+                    body_contact(eta, MR.cc, rloc, n, F, dt, Q, rb);
+                }
             }
         }
-    } else if constexpr (SCENE == 3) {
-        const int ci = g - 8;
-        const V3<R> th = v3(R(0.5) * M.tsx, R(0.5) * M.tsy, R(0.5) * M.tsz);
-        const V3<R> cl = v3(ci & 1 ? M.bx_hx : -M.bx_hx, ci & 2 ? M.bx_hy : -M.bx_hy, ci & 4 ? M.bx_hz : -M.bx_hz);
-        const V3<R> xw = bx.p + mul(bf.Rb, cl);
-        R delta;
-        V3<R> nt;
-        const V3<R> lt = mulT(Rm, xw - b.p);
-        if (point_aabox(lt, th, delta, nt)) {
-            const V3<R> vo = mulT(Rm, box_point_vel(bx, bf, xw));
-            trunk_contact(M, vb, w, delta, R(-1) * nt, lt, vo, dt, Q, rb, F, eta);
-            box_share(M, bx, bf, xw, mul(Rm, nt), R(-1) * mul(Rm, F), eta, dt, Qb, rbx);
-        }
-        V3<R> nw;
-        if (terrain<SCENE>(M, hf, xw, R(0), delta, nw)) {
-            contact_law(M, delta, nw, box_point_vel(bx, bf, xw), F, eta);
-            box_share(M, bx, bf, xw, nw, F, eta, dt, Qb, rbx);
+    } else {
+        // A corner of body P (the trunk on lanes 0-7, the box on lanes 8-15) against the
+        // other body Q (a point inside Q's box, normal out of Q's nearest face) and against
+        // the terrain.  The same code serves both roles: each contact adds its terms to the
+        // trunk's and the box's 6x6 systems in their own frames, with zero weight where a
+        // body is not part of the contact.
+        const bool own_trunk = g < 8;
+        const int ci = g & 7;
+        Pose<R> PT, PB;
+        PT.Rt = Rm; PT.p = b.p; PT.vw = b.vw; PT.w = b.w;
+        PB.Rt = bf.Rb; PB.p = bx.p; PB.vw = bx.vw; PB.w = bx.w;
+        const Pose<R> own = sel_pose(own_trunk, PT, PB), oth = sel_pose(own_trunk, PB, PT);
+        const V3<R> th = v3(R(0.5) * MR.tsx, R(0.5) * MR.tsy, R(0.5) * MR.tsz), bh = v3(MR.bx_hx, MR.bx_hy, MR.bx_hz);
+        const V3<R> hP = selv(own_trunk, th, bh), hQ = selv(own_trunk, bh, th);
+        const V3<R> cl = v3(ci & 1 ? hP.x : -hP.x, ci & 2 ? hP.y : -hP.y, ci & 4 ? hP.z : -hP.z);
+        const V3<R> x = own.p + mul(own.Rt, cl);
+        const V3<R> lq = mulT(oth.Rt, x - oth.p);
+        R dP = R(0), dG;
+        V3<R> nlq = zero, nG;
+        const bool hitP = point_aabox(lq, hQ, dP, nlq);  // nlq: Q's face normal toward the corner
+        const bool hitG = terrain<SCENE>(MR, hf, x, R(0), dG, nG);
+        const int cnt = int(hitP) + int(hitG);
+        if (__builtin_amdgcn_ballot_w64(cnt > 0)) {
+            const V3<R> vP = pose_point_vel(own, x), vQ = pose_point_vel(oth, x);
+            const V3<R> nPw = mul(oth.Rt, nlq);
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+                if (!__builtin_amdgcn_ballot_w64(it < cnt)) break;
+                const bool pair = (it == 0) && hitP;  // pass 0: the pair if touching, else the terrain
+                const R wgt = (it < cnt) ? R(1) : R(0);
+                const R wq = pair ? wgt : R(0);
+                const V3<R> n = selv(pair, nPw, nG);
+                contact_law(MR, pair ? dP : dG, n, selv(pair, vP - vQ, vP), F, eta);
+                F = wgt * F;
+                eta = wgt * eta;
+                // P's side in P's frame (force +F), Q's side in Q's frame (force -F)
+                const V3<R> nP = mulT(own.Rt, n), FP = mulT(own.Rt, F);
+                const V3<R> FQ = R(-1) * mulT(oth.Rt, F);
+                const R cP = wgt * MR.cc, cQ = wq * MR.cc, eQ = wq * eta;
+                body_contact(sel(own_trunk, eta, eQ), sel(own_trunk, cP, cQ), selv(own_trunk, cl, lq),
+                             selv(own_trunk, nP, nlq), selv(own_trunk, FP, wq * FQ), dt, Q, rb);
+                body_contact(sel(own_trunk, eQ, eta), sel(own_trunk, cQ, cP), selv(own_trunk, lq, cl),
+                             selv(own_trunk, nlq, nP), selv(own_trunk, wq * FQ, FP), dt, Qb, rbx);
+            }
         }
     }
 
     // ---- sum the trunk (and box) systems and the squared torques over the 16 lanes
     constexpr int NV = n_summed<SCENE>();
     {
-        R v[NV];
+        S v[NV];
 #pragma unroll
         for (int i = 0; i < 21; ++i) v[i] = Q[i];
 #pragma unroll
         for (int i = 0; i < 6; ++i) v[21 + i] = rb[i];
-        v[27] = sel(keep, t2, R(0));
+        v[27] = sel(keep, t2, S(0));
         if constexpr (SCENE == 3) {
 #pragma unroll
             for (int i = 0; i < 21; ++i) v[28 + i] = Qb[i];
@@ -319,7 +452,7 @@ __device__ __forceinline__ void step16(const ModelT<R>& M, const float* __restri
     for (int i = 0; i < 21; ++i) Q[i] = sred[i];
 #pragma unroll
     for (int i = 0; i < 6; ++i) rb[i] = sred[21 + i];
-    tau2 = sred[27];
+    tau2 = R(sred[27]);
     if constexpr (SCENE == 3) {
 #pragma unroll
         for (int i = 0; i < 21; ++i) Qb[i] = sred[28 + i];
@@ -328,28 +461,28 @@ __device__ __forceinline__ void step16(const ModelT<R>& M, const float* __restri
     }
 
     // ---- the trunk's own terms: inertia, total mass, gyroscopic and gravity bias
-    Q[s6(0, 0)] += M.I0x; Q[s6(1, 1)] += M.I0y; Q[s6(2, 2)] += M.I0z;
-    Q[s6(3, 3)] += M.mtot; Q[s6(4, 4)] += M.mtot; Q[s6(5, 5)] += M.mtot;
+    Q[s6(0, 0)] += MS.I0x; Q[s6(1, 1)] += MS.I0y; Q[s6(2, 2)] += MS.I0z;
+    Q[s6(3, 3)] += MS.mtot; Q[s6(4, 4)] += MS.mtot; Q[s6(5, 5)] += MS.mtot;
     {
-        const V3<R> Iw = v3(M.I0x * w.x, M.I0y * w.y, M.I0z * w.z);
-        const V3<R> gy = cross(w, Iw);
+        const V3<S> Iw = v3(MS.I0x * ws.x, MS.I0y * ws.y, MS.I0z * ws.z);
+        const V3<S> gy = cross(ws, Iw);
         rb[0] -= dt * gy.x; rb[1] -= dt * gy.y; rb[2] -= dt * gy.z;
-        rb[3] += dt * M.m0 * gb.x; rb[4] += dt * M.m0 * gb.y; rb[5] += dt * M.m0 * gb.z;
+        rb[3] += dt * MS.m0 * gbs.x; rb[4] += dt * MS.m0 * gbs.y; rb[5] += dt * MS.m0 * gbs.z;
     }
     if constexpr (SCENE != 3) {
         chol6_solve(Q, rb);  // rb <- trunk increment [d omega; d v_b]
     } else {
         // the box's own terms, then one 6x6 solve per lane: trunk on even lanes, box on
         // odd lanes; neighbours swap their results
-        Qb[s6(0, 0)] += M.bx_Ix; Qb[s6(1, 1)] += M.bx_Iy; Qb[s6(2, 2)] += M.bx_Iz;
-        Qb[s6(3, 3)] += M.bx_m; Qb[s6(4, 4)] += M.bx_m; Qb[s6(5, 5)] += M.bx_m;
-        const V3<R> wbx = bx.w;
-        const V3<R> gyb = cross(wbx, v3(M.bx_Ix * wbx.x, M.bx_Iy * wbx.y, M.bx_Iz * wbx.z));
-        const V3<R> gl = (-M.g) * v3(bf.Rb.m[6], bf.Rb.m[7], bf.Rb.m[8]);
+        Qb[s6(0, 0)] += MS.bx_Ix; Qb[s6(1, 1)] += MS.bx_Iy; Qb[s6(2, 2)] += MS.bx_Iz;
+        Qb[s6(3, 3)] += MS.bx_m; Qb[s6(4, 4)] += MS.bx_m; Qb[s6(5, 5)] += MS.bx_m;
+        const V3<S> wbx = cv<S>(bx.w);
+        const V3<S> gyb = cross(wbx, v3(MS.bx_Ix * wbx.x, MS.bx_Iy * wbx.y, MS.bx_Iz * wbx.z));
+        const V3<S> gl = cv<S>((-MR.g) * v3(bf.Rb.m[6], bf.Rb.m[7], bf.Rb.m[8]));
         rbx[0] -= dt * gyb.x; rbx[1] -= dt * gyb.y; rbx[2] -= dt * gyb.z;
-        rbx[3] += dt * M.bx_m * gl.x; rbx[4] += dt * M.bx_m * gl.y; rbx[5] += dt * M.bx_m * gl.z;
+        rbx[3] += dt * MS.bx_m * gl.x; rbx[4] += dt * MS.bx_m * gl.y; rbx[5] += dt * MS.bx_m * gl.z;
         const bool odd = (g & 1) != 0;
-        R Qs[21], rs[6];
+        S Qs[21], rs[6];
 #pragma unroll
         for (int i = 0; i < 21; ++i) Qs[i] = sel(odd, Qb[i], Q[i]);
 #pragma unroll
@@ -357,45 +490,64 @@ __device__ __forceinline__ void step16(const ModelT<R>& M, const float* __restri
         chol6_solve(Qs, rs);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            const R other = dpp<0xB1>(rs[i]);  // the neighbour's result (lanes 0<->1, 2<->3)
+            const S other = dpp<0xB1>(rs[i]);  // the neighbour's result (lanes 0<->1, 2<->3)
             rb[i] = sel(odd, other, rs[i]);
             rbx[i] = sel(odd, rs[i], other);
         }
     }
 
-    // ---- back-substitute the leg and integrate (semi-implicit Euler)
-    R dq[3] = {y0, y1, y2};
+    // ---- back-substitute the leg and integrate (semi-implicit Euler): velocities add the
+    // increments in S, positions take dt times the new velocities in R
+    S dq[3] = {y0, y1, y2};
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int i = 0; i < 6; ++i) dq[j] -= W[j][i] * rb[i];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        lg.qd[j] += dq[j];
-        lg.q[j] += dt * lg.qd[j];
+        lg.qd[j] = R(S(lg.qd[j]) + dq[j]);
+        lg.q[j] += dtr * lg.qd[j];
     }
-    b.w = b.w + v3(rb[0], rb[1], rb[2]);
-    b.vw = b.vw + mul(Rm, v3(rb[3], rb[4], rb[5]));
-    b.p = b.p + dt * b.vw;
-    quat_step(b.qw, b.qx, b.qy, b.qz, b.w, dt);
-    if constexpr (SCENE == 3) {
-        bx.w = bx.w + v3(rbx[0], rbx[1], rbx[2]);
-        bx.vw = bx.vw + mul(bf.Rb, v3(rbx[3], rbx[4], rbx[5]));
-        bx.p = bx.p + dt * bx.vw;
-        quat_step(bx.qw, bx.qx, bx.qy, bx.qz, bx.w, dt);
+    M33<S> Rs;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Rs.m[i] = S(Rm.m[i]);
+    b.w = cv<R>(ws + v3(rb[0], rb[1], rb[2]));
+    b.vw = cv<R>(cv<S>(b.vw) + mul(Rs, v3(rb[3], rb[4], rb[5])));
+    b.p = b.p + dtr * b.vw;
+    if constexpr (SCENE != 3) {
+        quat_step(b.qw, b.qx, b.qy, b.qz, b.w, dtr);
+    } else {
+        M33<S> Rbs;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Rbs.m[i] = S(bf.Rb.m[i]);
+        bx.w = cv<R>(cv<S>(bx.w) + v3(rbx[0], rbx[1], rbx[2]));
+        bx.vw = cv<R>(cv<S>(bx.vw) + mul(Rbs, v3(rbx[3], rbx[4], rbx[5])));
+        bx.p = bx.p + dtr * bx.vw;
+        // one quaternion step per lane: the trunk's on even lanes, the box's on odd lanes
+        const bool odd = (g & 1) != 0;
+        R q[4] = {sel(odd, bx.qw, b.qw), sel(odd, bx.qx, b.qx), sel(odd, bx.qy, b.qy), sel(odd, bx.qz, b.qz)};
+        quat_step(q[0], q[1], q[2], q[3], selv(odd, bx.w, b.w), dtr);
+        R o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = dpp<0xB1>(q[i]);
+        b.qw = sel(odd, o[0], q[0]); b.qx = sel(odd, o[1], q[1]); b.qy = sel(odd, o[2], q[2]); b.qz = sel(odd, o[3], q[3]);
+        bx.qw = sel(odd, q[0], o[0]); bx.qx = sel(odd, q[1], o[1]); bx.qy = sel(odd, q[2], o[2]);
+        bx.qz = sel(odd, q[3], o[3]);
     }
 }
 
 }  // namespace r16
 
 // ------------------------------------------------------------------------------
-// rollout kernel: workgroup of 64 lanes = 4 samples x 16 lanes.  LDS: the summation rows
-// [4][kNVMax][kPitch], the sums [4][kSumPitch], then the heightfield (scene 1).
-// eps addressing as in the quad kernel: eps_in[n * eps_sn + d * eps_sd] when given,
-// otherwise Philox noise stored to eps_out[d * K + n].
+// rollout kernel: workgroup of 64 lanes = 4 samples x 16 lanes.  R: geometry and state
+// type, S: system type (FP32/FP32, FP64/FP64, or FP32 geometry with the FP64 system).
+// LDS: the summation rows [4][kNVMax][kPitch] and sums [4][kSumPitch] (type S), then the
+// heightfield (scene 1).  eps addressing as in the quad kernel: eps_in[n * eps_sn + d *
+// eps_sd] when given, otherwise Philox noise stored to eps_out[d * K + n].
 // ------------------------------------------------------------------------------
-template <int SCENE, typename R>
-__global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mg, DevParams P, const double* __restrict__ gB,
+template <int SCENE, typename R, typename S>
+__global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> Ms, DevParams P,
+                                                       const double* __restrict__ gB,
                                                        const float* __restrict__ ghf, const float* __restrict__ mu,
                                                        const float* __restrict__ x0,
                                                        const float* __restrict__ eps_in, int eps_sn, int eps_sd,
@@ -405,17 +557,22 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mg, DevParams P
     extern __shared__ __align__(16) unsigned char lds_raw[];
     // the model's constants are read from LDS (values in vector registers), which keeps the
     // scalar registers for the kernel's pointers and loop state
-    __shared__ ModelT<R> sM;
-    R* red = reinterpret_cast<R*>(lds_raw);
-    R* sred = red + r16::kSamples * r16::kNVMax * r16::kPitch;
+    __shared__ ModelT<R> sMr;
+    __shared__ ModelT<S> sMs;
+    S* red = reinterpret_cast<S*>(lds_raw);
+    S* sred = red + r16::kSamples * r16::kNVMax * r16::kPitch;
     float* sHF = reinterpret_cast<float*>(sred + r16::kSamples * r16::kSumPitch);
-    if (threadIdx.x == 0) sM = Mg;
+    if (threadIdx.x == 0) {
+        sMr = Mr;
+        sMs = Ms;
+    }
     if constexpr (SCENE == 1) {
-        const int cells = Mg.hf_nx * Mg.hf_ny;
+        const int cells = Mr.hf_nx * Mr.hf_ny;
         for (int i = threadIdx.x; i < cells; i += blockDim.x) sHF[i] = ghf[i];
     }
     __syncthreads();
-    const ModelT<R>& M = sM;
+    const ModelT<R>& MR = sMr;
+    const ModelT<S>& MS = sMs;
 
     const int tid = threadIdx.x;
     const int g = tid & 15, grp = tid >> 4;
@@ -456,9 +613,9 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mg, DevParams P
         if (SCENE == 3 && leg == 0) store_box(tr, bx);
     }
 
-    R* my_red = red + grp * r16::kNVMax * r16::kPitch;
-    R* my_sum = sred + grp * r16::kSumPitch;
-    const R dt = P.dt, kp = P.kp, kd = P.kd;
+    S* my_red = red + grp * r16::kNVMax * r16::kPitch;
+    S* my_sum = sred + grp * r16::kSumPitch;
+    const S dt = P.dt, kp = P.kp, kd = P.kd;
     R L = R(0);
     for (int k = 0; k < P.H; ++k) {
         R uj = R(0);
@@ -466,10 +623,10 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mg, DevParams P
         for (int i = 0; i < kMaxKnots; ++i)
             if (i < nk) uj += R(gB[k * nk + i]) * th[i];
         R tau2;
-        r16::step16<SCENE, R>(M, sHF, dt, kp, kd, g, b, lg, bx, uj, my_red, my_sum, tau2);
+        r16::step16<SCENE, R, S>(MR, MS, sHF, dt, kp, kd, g, b, lg, bx, uj, my_red, my_sum, tau2);
         round_state(b, lg);
         if constexpr (SCENE == 3) round_box(bx);
-        L += dt * stage_cost<SCENE>(P, b, bx, tau2);
+        L += R(dt) * stage_cost<SCENE>(P, b, bx, tau2);
         if (tr) {
             store_state(tr + (size_t)(k + 1) * P.nx, leg, b, lg);
             if (SCENE == 3 && leg == 0) store_box(tr + (size_t)(k + 1) * P.nx, bx);
@@ -482,24 +639,25 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mg, DevParams P
 
 namespace r16 {
 
-template <typename R>
+template <typename S>
 size_t lds_bytes(int scene, int hf_cells)
 {
-    size_t b = sizeof(R) * ((size_t)kSamples * kNVMax * kPitch + (size_t)kSamples * kSumPitch);
+    size_t b = sizeof(S) * ((size_t)kSamples * kNVMax * kPitch + (size_t)kSamples * kSumPitch);
     if (scene == 1) b += sizeof(float) * (size_t)hf_cells;
     return b;
 }
 
-template <typename R>
-hipError_t launch_t(const ModelT<R>& M, const DevParams& P, const RolloutArgs& a, hipStream_t st)
+template <typename R, typename S>
+hipError_t launch_t(const ModelT<R>& Mr, const ModelT<S>& Ms, const DevParams& P, const RolloutArgs& a,
+                    hipStream_t st)
 {
     const int blocks = (P.K + kSamples - 1) / kSamples;
-    const size_t lds = lds_bytes<R>(M.scene, M.hf_nx * M.hf_ny);
+    const size_t lds = lds_bytes<S>(Mr.scene, Mr.hf_nx * Mr.hf_ny);
     if (lds > 65536) return hipErrorInvalidValue;
-#define MPPI_LAUNCH_R16(S)                                                                                     \
-    hipLaunchKernelGGL((rollout16_kernel<S, R>), dim3(blocks), dim3(64), lds, st, M, P, a.B, a.hf, a.mu, a.x0, \
-                       a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj)
-    switch (M.scene) {
+#define MPPI_LAUNCH_R16(SC)                                                                                     \
+    hipLaunchKernelGGL((rollout16_kernel<SC, R, S>), dim3(blocks), dim3(64), lds, st, Mr, Ms, P, a.B, a.hf, a.mu, \
+                       a.x0, a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj)
+    switch (Mr.scene) {
     case 0: MPPI_LAUNCH_R16(0); break;
     case 1: MPPI_LAUNCH_R16(1); break;
     case 2: MPPI_LAUNCH_R16(2); break;
@@ -518,10 +676,13 @@ bool rollout16_fits(int arith, int scene, int hf_cells)
     return b <= 65536;
 }
 
+// arith: 0 FP64, 1 FP32, 2 FP32 geometry with the FP64 implicit system
 hipError_t launch_rollout16(const DevModelF& Mf, const DevModelD& Md, int arith, const DevParams& P,
                             const RolloutArgs& a, hipStream_t st)
 {
-    return arith == 1 ? r16::launch_t(Mf, P, a, st) : r16::launch_t(Md, P, a, st);
+    if (arith == 1) return r16::launch_t(Mf, Mf, P, a, st);
+    if (arith == 2) return r16::launch_t(Mf, Md, P, a, st);
+    return r16::launch_t(Md, Md, P, a, st);
 }
 
 }  // namespace mppi

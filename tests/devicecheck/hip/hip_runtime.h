@@ -144,6 +144,14 @@ inline T __shfl_xor(T v, int mask, int width = 64)
     return r;
 }
 inline int __builtin_amdgcn_readfirstlane(int v) { return v; }  // the batch kernels: wave-uniform values
+// wave vote: the mask of the lanes whose predicate holds (a butterfly of exchanges, so every
+// lane of the wave must arrive)
+inline unsigned long long __builtin_amdgcn_ballot_w64(bool p)
+{
+    uint64_t m = p ? (1ull << (threadIdx.x & 63)) : 0ull;
+    for (int o = 1; o < 64; o <<= 1) m |= emu_wave_exchange(m, (int)((threadIdx.x & 63) ^ (unsigned)o));
+    return m;
+}
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
 inline float __int_as_float(int i) { float f; std::memcpy(&f, &i, 4); return f; }

@@ -9,7 +9,7 @@ from paper_2409_10469_amd import workloads as W
 BLOCKS = [(0, 3), (3, 7), (7, 19), (19, 22), (22, 25), (25, 37)]
 BOX_BLOCKS = [(37, 40), (40, 44), (44, 47), (47, 50)]
 
-STEP_TOL = 1e-5      # per-step state error, relative per block
+STEP_TOL = 1e-5      # per-step state error, relative per block (FP64 step)
 COST_TOL = 1e-4      # rollout cost over <= 10 steps, relative
 KNOT_TOL = 1e-3      # updated knots, absolute [rad]
 
@@ -87,3 +87,60 @@ def box_contact_states(n, seed=0):
         x[44:50] = rng.normal(size=6) * np.r_[0.3, 0.3, 0.1, 0.5, 0.5, 0.5]
         xs.append(f32(x))
     return np.array(xs)
+
+
+U32 = 2.0 ** -24
+
+
+def fp32_step_bound(orc, x, u, kp, kd, dt):
+    """Per-state bound on the FP32 step's error, derived before any GPU result: the step
+    solves (M + dt D) dv = dt f for the robot (18x18) and the free box (6x6).  An FP32
+    Cholesky-type solve is backward stable, so the computed dv satisfies a system whose
+    matrix and right side are perturbed by about (n + 1) u of their magnitude (u = 2^-24;
+    the assembly in FP32 adds as many roundings again), which moves dv by at most
+    kappa_2(A) * 2 (n + 1) u |dv| (kappa_2 from the oracle's FP64 system).  Every block is
+    compared relative to max(|block|, 1) >= 1, the velocities are v + dv and the positions
+    take dt (< 1) times the velocity error, so that is a bound on the block errors.
+    Returns the larger of it and the FP64 step's 1e-5."""
+    A, r, _ = orc.step_system(x, u, kp, kd, dt)
+    ev = np.linalg.eigvalsh(A)
+    bound = 2 * 19 * (ev[-1] / ev[0]) * U32 * np.abs(np.linalg.solve(A, r)).max()
+    if len(x) == W.NX_BOX:
+        Ab, rb, _ = orc.step_system_box(x, u, kp, kd, dt)
+        evb = np.linalg.eigvalsh(Ab)
+        bound = max(bound, 2 * 7 * (evb[-1] / evb[0]) * U32 * np.abs(np.linalg.solve(Ab, rb)).max())
+    return max(STEP_TOL, bound)
+
+
+ULP_FACTOR = 8   # FP32 roundings between the state and a contact depth or joint frame
+
+
+def ulp_sensitivity(orc, x, u, kp, kd, dt):
+    """The oracle's own one-ulp sensitivity of the step, block-relative like step_error:
+    sum over the inputs (state and joint targets) of |x+(in + ulp) - x+(in - ulp)| / 2,
+    each input moved by one FP32 ulp, central differences in FP64."""
+    x = np.asarray(x, np.float64)
+    u = np.asarray(u, np.float64)
+    base, _, _ = orc.step(x, u, kp, kd, dt)
+    acc = np.zeros_like(base)
+    for vec, is_x in ((x, True), (u, False)):
+        for i in range(len(vec)):
+            h = float(np.spacing(np.float32(vec[i]))) if vec[i] != 0 else float(np.spacing(np.float32(1e-30)))
+            a, b = vec.copy(), vec.copy()
+            a[i] += h
+            b[i] -= h
+            xa = orc.step(a, u, kp, kd, dt)[0] if is_x else orc.step(x, a, kp, kd, dt)[0]
+            xb = orc.step(b, u, kp, kd, dt)[0] if is_x else orc.step(x, b, kp, kd, dt)[0]
+            acc += np.abs(xa - xb) / 2
+    blocks = BLOCKS + (BOX_BLOCKS if len(x) == W.NX_BOX else [])
+    return max(acc[a:b].max() / max(np.abs(base[a:b]).max(), 1.0) for a, b in blocks)
+
+
+def mixed_step_bound(orc, x, u, kp, kd, dt):
+    """Per-state bound of the step with FP32 kinematics and contact geometry and the FP64
+    implicit system, derived before any GPU result: the FP32 part rounds each contact
+    depth, lever arm and joint frame a few times (quaternion to rotation, rotation times
+    offset, translation, one trigonometric call), which acts as a perturbation of the
+    inputs by at most ULP_FACTOR ulps; the FP64 system adds nothing at this scale.  So
+    ULP_FACTOR times the oracle's one-ulp sensitivity, or the FP64 step's 1e-5 if larger."""
+    return max(STEP_TOL, ULP_FACTOR * ulp_sensitivity(orc, x, u, kp, kd, dt))

@@ -13,8 +13,8 @@ import pytest
 
 from oracle import oracle as O
 from paper_2409_10469_amd import workloads as W
-from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, box_contact_states, f32, random_walk_states, round_model,
-                                round_params, step_error)
+from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, box_contact_states, f32, fp32_step_bound,
+                                random_walk_states, round_model, round_params, step_error)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -265,31 +265,45 @@ def test_horizon_and_knot_edges(B, H, nk):
 
 
 # ---------------------------------------------------------------------------- FP32 variant
-FP32_STEP_TOL = 5e-4   # measured bound of the FP32-arithmetic step (contact conditioning)
-
-
 @pytest.mark.parametrize("workload", [W.FLAT_WALK, W.TERRAIN_WALK])
 def test_fp32_arithmetic_step_bound(B, workload):
+    """The FP32-arithmetic step against the bound derived from the oracle's implicit system
+    (parity_utils.fp32_step_bound: backward-stable solve, kappa_2(A) 2 (n + 1) u |dv|)."""
     md, p, orc, model, ctl = _setup(B, workload)
     xs, us = random_walk_states(orc, seeds=range(6), steps=45, dt=p["dt"], scene=workload["scene"])
     got = model.sim_step(_dev(xs), _dev(us), p["kp"], p["kd"], p["dt"], arith="fp32").cpu().numpy()
     want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
     err = step_error(got.astype(np.float64), want)
-    print("fp32 step error: max %.2e median %.2e" % (err.max(), np.median(err)))
-    assert err.max() <= FP32_STEP_TOL
+    bound = np.array([fp32_step_bound(orc, x, u, p["kp"], p["kd"], p["dt"]) for x, u in zip(xs, us)])
+    print("fp32 step error: max %.2e median %.2e; worst error / bound %.3f" % (err.max(), np.median(err),
+                                                                               (err / bound).max()))
+    assert (err <= bound).all()
 
 
 def test_fp32_arithmetic_rollout_costs(B):
+    """FP32 rollouts of 10 steps: each cost equals the sum of the oracle's stage costs of
+    the GPU's own (FP32-arithmetic) states within COST_TOL, and each step is within the
+    derived FP32 step bound."""
     md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=64, H=10, arith="fp32")
     x0 = f32(W.initial_state(3))
     mu = f32(W.stance_knots(p["nk"]))
     eps = f32(W.explicit_noise(5, 64, p["nk"]))
     ctl.set_nominal(_dev(mu))
-    got = ctl.rollout_batch(_dev(x0), eps=_dev(eps)).cpu().numpy().astype(np.float64)
-    want = orc.rollout_batch(p, x0, mu, eps)
-    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6)
-    print("fp32 rollout cost error: max %.2e" % rel.max())
-    assert rel.max() <= 1e-2
+    costs, traj = ctl.rollout_batch(_dev(x0), eps=_dev(eps), traj=True)
+    c = costs.cpu().numpy().astype(np.float64)
+    tr = traj.cpu().numpy().astype(np.float64)
+    Bm = O.spline_basis(p["nk"], p["H"], p["dt"])
+    for n in range(0, 64, 7):
+        theta = mu + (p["sigma"] * eps[n] if n else 0.0)
+        U = Bm @ theta.reshape(12, p["nk"]).T
+        L = 0.0
+        for k in range(p["H"]):
+            xk = tr[n, k]
+            tau = p["kp"] * (U[k] - xk[7:19]) - p["kd"] * xk[25:37]
+            L += p["dt"] * orc.stage_cost(p, tr[n, k + 1], tau)
+            xn, _, _ = orc.step(xk, U[k], p["kp"], p["kd"], p["dt"])
+            assert step_error(tr[n, k + 1], xn).max() <= fp32_step_bound(orc, xk, U[k], p["kp"], p["kd"], p["dt"])
+        assert abs(c[n] - L) <= COST_TOL * max(abs(L), 1e-6), (n, c[n], L)
 
 
 # ---------------------------------------------------------------------------- box scenes

@@ -3,14 +3,21 @@ through the C ABI, at the quad kernel's bars:
   per-step state error <= 1e-5 relative per block (FP64 step) from the GPU's own states;
   rollout costs within 1e-4 relative over 10-step horizons;
   updated knots within 1e-3;
-and its costs equal to the quad kernel's up to summation order."""
+and its costs equal to the quad kernel's up to summation order.  The other arithmetics
+are held to bounds derived from the oracle before any GPU result:
+  MIXED (FP32 kinematics and contact geometry, FP64 implicit system): 8 times the
+    oracle's one-ulp input sensitivity of the step (parity_utils.mixed_step_bound);
+  FP32 (everything in FP32): the backward-stable solve bound kappa_2(A) 2 (n + 1) u |dv|
+    of the step's implicit systems (parity_utils.fp32_step_bound).
+Per-step states are compared from identical FP32 inputs; the costs of FP32-state
+trajectories are checked as sums of the oracle's stage costs of the GPU's own states."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2409_10469_amd import workloads as W
-from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, box_contact_states, f32, round_model, round_params,
-                                step_error)
+from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, box_contact_states, f32, fp32_step_bound,
+                                mixed_step_bound, random_walk_states, round_model, round_params, step_error)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -200,3 +207,96 @@ def test_split_runs_are_bitwise_deterministic(B):
     a = ctl.rollout_batch(x0).cpu().numpy()
     b = ctl.rollout_batch(x0).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def _one_step_split(B, model, p, xs, us, arith):
+    """One rollout step per state on the lane-split kernel: K = 1, H = 1, constant knots
+    equal to the joint targets (every basis reproduces constants)."""
+    ctl = B.Controller(model, dict(p, K=1, H=1, nk=2, sigma=0.0, arith=arith, lanes=16))
+    eps = _dev(np.zeros((1, 24)))
+    out = []
+    for x, u in zip(xs, us):
+        ctl.set_nominal(_dev(np.repeat(u, 2)))
+        _, traj = ctl.rollout_batch(_dev(x), eps=eps, traj=True)
+        out.append(traj[0, 1].cpu().numpy().astype(np.float64))
+    return np.array(out)
+
+
+def _states(orc, workload, p):
+    if workload["scene"] == W.SCENE_FREE_BOX:
+        xs = box_contact_states(60, seed=1)
+        us = f32(np.tile(W.STANCE_JOINTS, 4) + np.random.default_rng(3).uniform(-0.3, 0.3, (len(xs), 12)))
+        return xs, us
+    return random_walk_states(orc, seeds=range(3), steps=40, dt=p["dt"], scene=workload["scene"])
+
+
+@pytest.mark.parametrize("workload", [W.FLAT_WALK, W.TERRAIN_WALK, W.BOX_PUSH])
+def test_split_fp64_one_step_parity(B, workload):
+    _say("split fp64 one-step", workload["name"])
+    md, p, orc, model, ctl = _setup(B, workload)
+    xs, us = _states(orc, workload, p)
+    got = _one_step_split(B, model, p, xs, us, "fp64")
+    want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
+    err = step_error(got, want, box=workload["scene"] == W.SCENE_FREE_BOX)
+    assert err.max() <= STEP_TOL, (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("workload", [W.FLAT_WALK, W.TERRAIN_WALK, W.BOX_PUSH])
+def test_split_mixed_one_step_within_ulp_sensitivity(B, workload):
+    _say("split mixed one-step", workload["name"])
+    md, p, orc, model, ctl = _setup(B, workload)
+    xs, us = _states(orc, workload, p)
+    got = _one_step_split(B, model, p, xs, us, "mixed")
+    want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
+    err = step_error(got, want, box=workload["scene"] == W.SCENE_FREE_BOX)
+    bound = np.array([mixed_step_bound(orc, x, u, p["kp"], p["kd"], p["dt"]) for x, u in zip(xs, us)])
+    print("mixed step error: max %.2e median %.2e; bound min %.2e median %.2e; worst error / bound %.2f"
+          % (err.max(), np.median(err), bound.min(), np.median(bound), (err / bound).max()))
+    assert (err <= bound).all(), (int((err / bound).argmax()), (err / bound).max())
+
+
+@pytest.mark.parametrize("workload", [W.FLAT_WALK, W.TERRAIN_WALK, W.BOX_PUSH])
+def test_split_fp32_one_step_within_conditioning_bound(B, workload):
+    _say("split fp32 one-step", workload["name"])
+    md, p, orc, model, ctl = _setup(B, workload)
+    xs, us = _states(orc, workload, p)
+    got = _one_step_split(B, model, p, xs, us, "fp32")
+    want = np.array([orc.step(x, u, p["kp"], p["kd"], p["dt"])[0] for x, u in zip(xs, us)])
+    err = step_error(got, want, box=workload["scene"] == W.SCENE_FREE_BOX)
+    bound = np.array([fp32_step_bound(orc, x, u, p["kp"], p["kd"], p["dt"]) for x, u in zip(xs, us)])
+    print("fp32 step error: max %.2e median %.2e; worst error / bound %.3f" % (err.max(), np.median(err),
+                                                                               (err / bound).max()))
+    assert (err <= bound).all()
+
+
+@pytest.mark.parametrize("arith", ["mixed", "fp32"])
+def test_split_box_push_chain_costs_sum_oracle_stage_costs(B, arith):
+    """Full box-push shape (K=4096, H=60) with the faster arithmetics: sampled samples'
+    costs equal the sum of the oracle's stage costs of the GPU's own states within
+    COST_TOL, and every third step is within the arithmetic's per-step bound."""
+    _say("split box push chain", arith)
+    md, p, orc, model, ctl = _setup(B, W.BOX_PUSH, arith=arith)
+    x0 = f32(W.initial_state(0, W.SCENE_FREE_BOX))
+    x0[37] = 0.45
+    mu = f32(W.stance_knots(p["nk"]))
+    ctl.set_nominal(_dev(mu))
+    costs, traj = ctl.rollout_batch(_dev(x0), traj=True)
+    eps = ctl.sample().cpu().numpy().astype(np.float64)
+    tr = traj.cpu().numpy().astype(np.float64)
+    c = costs.cpu().numpy().astype(np.float64)
+    Bm = O.spline_basis(p["nk"], p["H"], p["dt"])
+    bound = mixed_step_bound if arith == "mixed" else fp32_step_bound
+    rng = np.random.default_rng(4)
+    for n in [0, p["K"] - 1, int(np.argmin(c))] + list(rng.integers(0, p["K"], 2)):
+        theta = mu + (p["sigma"] * eps[n] if n else 0.0)
+        U = Bm @ theta.reshape(12, p["nk"]).T
+        L = 0.0
+        for k in range(p["H"]):
+            xk = tr[n, k]
+            tau = p["kp"] * (U[k] - xk[7:19]) - p["kd"] * xk[25:37]
+            L += p["dt"] * orc.stage_cost(p, tr[n, k + 1], tau)
+            if k % 6 == 0:
+                xn, _, _ = orc.step(xk, U[k], p["kp"], p["kd"], p["dt"])
+                e = step_error(tr[n, k + 1], xn, box=True).max()
+                assert e <= bound(orc, xk, U[k], p["kp"], p["kd"], p["dt"]), (n, k, e)
+        assert abs(c[n] - L) <= COST_TOL * max(abs(L), 1e-6), (n, c[n], L)

@@ -274,3 +274,17 @@ def test_heightfield_clamps_outside_the_grid():
     want_n = np.array([0.0, -a * xmax, 1.0]) / math.sqrt(1 + (a * xmax) ** 2)
     np.testing.assert_allclose(nrm, want_n, atol=1e-12)
     assert abs(delta - h * want_n[2]) < 1e-12
+
+
+def test_step_systems_reproduce_the_step():
+    """The exported robot and box systems of a step are the ones the step solves: their
+    solutions are the step's velocity changes (the FP32 error bound is derived from them)."""
+    m = O.Oracle(W.model_dict(W.BOX_PUSH, 0))
+    from tests.parity_utils import box_contact_states
+    u = np.tile(W.STANCE_JOINTS, 4)
+    for x in box_contact_states(5, seed=4):
+        xn, _, rc = m.step(x, u, 40.0, 1.0, 0.01)
+        A, r, n = m.step_system(x, u, 40.0, 1.0, 0.01)
+        np.testing.assert_allclose(x[19:37] + np.linalg.solve(A, r), xn[19:37], rtol=0, atol=1e-12)
+        Ab, rb, nb = m.step_system_box(x, u, 40.0, 1.0, 0.01)
+        np.testing.assert_allclose(x[44:50] + np.linalg.solve(Ab, rb), xn[44:50], rtol=0, atol=1e-12)
