@@ -1054,6 +1054,14 @@ void orc_interp_eval(int basis, int nk, double T, const double *knots, double t,
         orc_spline_eval(nk, T, knots, t, out);
         return;
     }
+    if (basis == 3) {           /* direct: one value per control step, knot i applies on
+                                   [i dt, (i + 1) dt) with dt = T / nk, the last one held */
+        int s = (int)floor(t / (T / nk) + 1e-9);
+        if (s < 0) s = 0;
+        if (s > nk - 1) s = nk - 1;
+        *out = knots[s];
+        return;
+    }
     double hk = T / (nk - 1);
     if (basis == 2) {           /* zeroth order: the knot at the start of the interval; a time
                                    within 1e-9 of an interval of a knot time counts as on it */
@@ -1084,7 +1092,8 @@ void orc_basis_matrix(int basis, int nk, int H, double dt, double *B)
 
 void orc_spline_basis(int nk, int H, double dt, double *B) { orc_basis_matrix(0, nk, H, dt, B); }
 
-/* warm-start shift: new knot j = old interpolant at t_j + dt, held at the horizon end */
+/* warm-start shift: new knot j = old interpolant at t_j + dt, held at the horizon end
+   (knot times t_j = j T / (nk - 1); direct values sit at t_j = j dt) */
 void orc_shift_matrix_b(int basis, int nk, int H, double dt, double *S)
 {
     double T = H * dt;
@@ -1093,7 +1102,7 @@ void orc_shift_matrix_b(int basis, int nk, int H, double dt, double *S)
         memset(e, 0, sizeof(double) * nk);
         e[j] = 1;
         for (int i = 0; i < nk; ++i) {
-            double t = i * T / (nk - 1) + dt;
+            double t = (basis == 3 ? i * dt : i * T / (nk - 1)) + dt;
             if (t > T) t = T;
             orc_interp_eval(basis, nk, T, e, t, &S[i * nk + j]);
         }

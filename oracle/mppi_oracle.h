@@ -44,7 +44,7 @@ typedef struct orc_model {
 
 typedef struct orc_params {
     int32_t K, H, nk;
-    int32_t basis;                /* knot interpolation: 0 cubic (not-a-knot), 1 linear, 2 zeroth order */
+    int32_t basis;                /* knot interpolation: 0 cubic (not-a-knot), 1 linear, 2 zeroth order, 3 direct */
     double dt, sigma, lambda, kp, kd;
     double w_h, h_ref, w_o, w_v, v_ref, w_tau, w_reach, w_box;
     double goal[2];
@@ -65,7 +65,9 @@ void orc_spline_eval(int nk, double T, const double *knots, double t, double *ou
 void orc_shift_matrix(int nk, int H, double dt, double *S);
 /* The same for a chosen interpolation of the knots (Sec. III-B names the alternatives):
    basis 0 the cubic spline above, 1 straight lines between neighbouring knots, 2 the
-   value of the knot at the start of each knot interval held until the next knot. */
+   value of the knot at the start of each knot interval held until the next knot, 3
+   direct: nk = H values, one per control step (the basis is the identity and the shift
+   advances by one step). */
 void orc_interp_eval(int basis, int nk, double T, const double *knots, double t, double *out);
 void orc_basis_matrix(int basis, int nk, int H, double dt, double *B);
 void orc_shift_matrix_b(int basis, int nk, int H, double dt, double *S);

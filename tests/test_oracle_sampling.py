@@ -175,3 +175,39 @@ def test_linear_basis_reproduces_lines_and_is_not_cubic():
     np.testing.assert_allclose(BL @ (0.4 - 2.0 * tk), 0.4 - 2.0 * t, atol=1e-12)
     q = tk ** 2
     assert np.abs(BL @ q - t ** 2).max() > 1e-4  # a parabola is only matched at the knots
+
+
+DIRECT = 3
+
+
+@pytest.mark.parametrize("H,dt", [(1, 0.02), (7, 0.02), (50, 0.01), (60, 0.01)])
+def test_direct_basis_is_the_identity_and_the_shift_advances_one_step(H, dt):
+    """Direct sampling (Sec. III-B's per-timestep alternative): one value per control step,
+    so the step targets are the values themselves, and warm starting moves every value
+    one step earlier with the last one held."""
+    B = O.basis_matrix(DIRECT, H, H, dt)
+    np.testing.assert_array_equal(B, np.eye(H))
+    y = np.random.default_rng(H).normal(size=H)
+    S = O.shift_matrix_b(DIRECT, H, H, dt)
+    np.testing.assert_array_equal(S @ y, np.r_[y[1:], y[-1:]])
+    # the value applied at time t is the one of the step containing t; u0 is the first
+    for k in range(H):
+        assert O.interp_eval(DIRECT, y, H * dt, k * dt) == y[k]
+    assert O.interp_eval(DIRECT, y, H * dt, H * dt) == y[-1]
+
+
+def test_direct_rollout_applies_each_step_value():
+    """A direct-sampling rollout of the oracle applies value k at step k: the same
+    trajectory as stepping the dynamics with those targets by hand."""
+    from paper_2409_10469_amd import workloads as W
+    md = W.model_dict(W.FLAT_WALK, 0)
+    orc = O.Oracle(md)
+    H, dt = 6, 0.01
+    p = dict(W.params_dict(W.FLAT_WALK, 0, H=H, nk=H, dt=dt), basis=DIRECT)
+    theta = np.tile(W.STANCE_JOINTS, 4)[:, None] + np.random.default_rng(1).uniform(-0.2, 0.2, (12, H))
+    x0 = W.initial_state(2)
+    L, tr = orc.rollout(p, x0, theta.reshape(-1), traj=True)
+    x = x0.copy()
+    for k in range(H):
+        x, _, _ = orc.step(x, theta[:, k], p["kp"], p["kd"], dt)
+        np.testing.assert_allclose(tr[k + 1], x, atol=0)
