@@ -321,7 +321,7 @@ def learned_vs_plain(args):
            "plain": {str(k): {"episode_cost": v["mean"], "ci95": v["ci95"], "samples_per_step": k,
                               "latency_p50_ms": v["latency_ms"]["p50"], "latency_p99_ms": v["latency_ms"]["p99"]}
                      for k, v in ev["plain"].items()}}
-    for g in ("cost", "none"):
+    for g in ("cost", "best", "none"):
         e = ev["learned_" + g]
         res["learned_gate_" + g] = {"episode_cost": e["mean"], "ci95": e["ci95"], "k_prop": e["k_prop"],
                                     "samples_per_step": e["samples_per_step"], "acceptance": e["acceptance"],
@@ -453,10 +453,11 @@ def bench_proposal(args):
                             "episode_cost_ci95": ev["learned_" + g]["ci95"],
                             "smallest_plain_K_matching": ev["learned_" + g]["smallest_plain_K_matching"],
                             "sample_ratio": ev["learned_" + g]["sample_ratio"]}
-                        for g in ("cost", "none")},
-            "gates": "cost: the proposal's K/4 samples and the plain step's K samples are rolled out side by side "
-                     "(two streams) and the update uses the proposal only when its centre costs no more than the "
-                     "nominal; none: always the K/4 proposal samples alone, nominal kept as sample 1"},
+                        for g in ("cost", "best", "none")},
+            "gates": "cost: the proposal's K/4 samples are rolled out, then the plain step's K samples only when "
+                     "the proposal's centre costs more than the nominal (fallback); best: the same with the least "
+                     "cost over the proposal's samples other than the nominal; none: always the K/4 proposal "
+                     "samples alone, nominal kept as sample 1"},
         "batched_equal_cost": evb,
         "epoch_seconds": train_s / max(len(hist), 1), "train_steps": train_steps,
         "generation": {"seconds": gen_s, "batch_seconds": st["seconds"], "episodes": st["episodes"],

@@ -112,7 +112,7 @@ typedef struct mppi_params {
  * corner contacts spread over them), 4 samples per wave, so K = 4096 fills every SIMD of
  * the chip.  Both compute the same step; only summation orders differ.  DEFAULT picks
  * SPLIT when its LDS rows fit (a heightfield above about 11,000 cells in FP64 does not)
- * and QUAD otherwise. */
+ * and QUAD otherwise.  The plant step (mppi_sim_step) and batched serving use QUAD. */
 enum { MPPI_LANES_DEFAULT = 0, MPPI_LANES_QUAD = 4, MPPI_LANES_SPLIT = 16 };
 
 /* Interpolation of the knots into per-step joint targets (Sec. III-B uses the cubic
@@ -120,9 +120,13 @@ enum { MPPI_LANES_DEFAULT = 0, MPPI_LANES_QUAD = 4, MPPI_LANES_SPLIT = 16 };
  *   CUBIC  not-a-knot cubic spline through the knots;
  *   LINEAR straight lines between neighbouring knots;
  *   ZERO   each knot's value held from its time until the next knot's.
- * All three pass through the knots, so u0 is the first knot; the warm-start shift
- * evaluates the same interpolant one step later. */
-enum { MPPI_BASIS_CUBIC = 0, MPPI_BASIS_LINEAR = 1, MPPI_BASIS_ZERO = 2 };
+ * All pass through the knots, so u0 is the first knot; the warm-start shift evaluates
+ * the same interpolant one step later. */
+enum { MPPI_BASIS_CUBIC = 0, MPPI_BASIS_LINEAR = 1, MPPI_BASIS_ZERO = 2, MPPI_BASIS_DIRECT = 3 };
+/* DIRECT samples every control step's targets (the per-timestep representation Sec. III-B
+ * compares the spline with): n_knots must equal H (at most MPPI_MAX_HORIZON), knot i is the
+ * target of step i, the shift moves every value one step earlier and holds the last.  The
+ * noise is drawn inside the rollout's step loop.  Lane-split rollout and running cost only. */
 
 /* The sample cost.  RUNNING: the weights in mppi_params above, summed inside the rollout.
  * TRACKING: Eq. 3 (Sec. IV-B) with the gait reference below, plus Eq. 4's l1 box term

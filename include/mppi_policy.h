@@ -108,19 +108,23 @@ const char *mppi_policy_last_error(const mppi_policy *pol);
  * floats each, device): k_prop samples theta_0 = center, theta_1 = the current (shifted)
  * nominal, theta_n = center + sd * eps_n for 2 <= n < k_prop, with eps_n drawn from the
  * same Philox counters as a plain step (Box-Muller evaluated as mppi_sample does).
- * If the rollout cost of the centre is finite and not above the nominal's, Eq. 1 and
- * Eq. 2 run over these k_prop samples; otherwise the step is a plain step with K
- * samples.  Then, as in mppi_step, the first control goes to d_u0_out, the nominal is
- * shifted and the step counter advances.  With MPPI_PROPOSAL_GATE_COST the plain step's
- * rollout runs beside the proposal rollout (the proposal on an internal stream that
- * mppi_bind creates, the plain one on the bound stream) and the update chooses the branch
- * on the device from the two leading proposal costs, so the call does not synchronise;
+ * A gated step takes the proposal when its cost under the gate (GATE_COST: the centre's
+ * rollout cost; GATE_BEST: the least cost of its samples other than the nominal) is finite
+ * and not above the nominal's, and Eq. 1 and Eq. 2 then run over these k_prop samples;
+ * otherwise the step is a plain step with K samples around the nominal (the fallback).
+ * Then, as in mppi_step, the first control goes to d_u0_out, the nominal is shifted and
+ * the step counter advances.  The decision is made on the device, so the call does not
+ * synchronise.  With the lane-split rollout the plain K samples are rolled out only on a
+ * fallback (after the proposal and the gate, on the bound stream); with the quad rollout
+ * they are rolled out beside the proposal on an internal stream that mppi_bind creates.
  * MPPI_PROPOSAL_GATE_NONE always takes the proposal branch (the nominal still competes as
- * sample 1) and rolls out only the proposal.  2 <= k_prop <= K.  The proposal steps use the running cost
- * (EINVAL for a controller created with MPPI_COST_TRACKING). */
+ * sample 1) and rolls out only the proposal.  2 <= k_prop <= K.  The proposal steps use
+ * the running cost (EINVAL for a controller created with MPPI_COST_TRACKING). */
 enum {
     MPPI_PROPOSAL_GATE_COST = 0, /* proposal only if its centre's cost is finite and not above the nominal's */
-    MPPI_PROPOSAL_GATE_NONE = 1  /* always the proposal's k_prop samples */
+    MPPI_PROPOSAL_GATE_NONE = 1, /* always the proposal's k_prop samples */
+    MPPI_PROPOSAL_GATE_BEST = 2  /* proposal only if its best sample other than the nominal is finite and not
+                                    above the nominal's cost */
 };
 mppi_status mppi_step_proposal(mppi_ctx *ctx, const float *d_x0, const float *d_center, const float *d_sd,
                                int k_prop, int gate, float *d_u0_out);

@@ -1192,9 +1192,10 @@ void orc_rollout_batch(const orc_model *m, const orc_params *p, const double *x0
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
 #endif
     for (int n = 0; n < p->K; ++n) {
-        double theta[96];
+        double *theta = malloc(sizeof(double) * D);
         for (int d = 0; d < D; ++d) theta[d] = mu[d] + (n ? p->sigma * eps[(size_t)n * D + d] : 0.0);
         costs[n] = rollout_with_basis(m, p, B, x0, theta, traj ? traj + (size_t)n * (p->H + 1) * nx : NULL);
+        free(theta);
     }
     (void)nthreads;
     free(B);
@@ -1268,12 +1269,13 @@ int orc_mppi_step(const orc_model *m, const orc_params *p, uint32_t step, const 
     int K = p->K, D = 12 * p->nk;
     double *eps = malloc(sizeof(double) * (size_t)K * D);
     double *L = costs ? costs : malloc(sizeof(double) * K);
-    double mup[96];
+    double *mup = malloc(sizeof(double) * D);
     orc_sample_eps(p, step, eps);
     orc_rollout_batch(m, p, x0, mu, eps, L, NULL, nthreads);
     int rc = orc_update(p, L, mu, eps, mup, NULL);
     orc_shift(p, mup, mu, u0);
     free(eps);
+    free(mup);
     if (!costs) free(L);
     return rc;
 }
@@ -1284,7 +1286,8 @@ int orc_mppi_step(const orc_model *m, const orc_params *p, uint32_t step, const 
    theta_n = c + sd * eps_n for 2 <= n < Kp, eps from the same counters as a plain step.
    With gate 0, when L(c) is finite and L(c) <= L(mu) the Eq. 1-2 update runs over these
    Kp samples, otherwise the step falls back to a plain step with K samples around mu;
-   gate 1 always takes the Kp samples.  *accepted reports which branch ran; costs_p (Kp)
+   gate 2 does the same with the least cost over the samples other than mu in place of
+   L(c); gate 1 always takes the Kp samples.  *accepted reports which branch ran; costs_p (Kp)
    and costs (K, fallback only) are optional outputs. */
 int orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t step, const double *x0, double *mu,
                            const double *center, const double *sd, int Kp, int gate, double *u0, double *costs_p,
@@ -1310,11 +1313,19 @@ int orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t ste
     (void)nthreads;
     (void)nx;
     if (costs_p) memcpy(costs_p, L, sizeof(double) * Kp);
-    int acc = gate == 1 || (Kp >= 2 && isfinite(L[0]) && L[0] <= L[1]);
+    /* gate 0: the centre's cost against the nominal's; gate 2: the least cost over the
+       proposal's samples other than the nominal; gate 1: always the proposal */
+    double Lg = L[0];
+    if (gate == 2) {
+        Lg = INFINITY;
+        for (int n = 0; n < Kp; ++n)
+            if (n != 1 && isfinite(L[n]) && L[n] < Lg) Lg = L[n];
+    }
+    int acc = gate == 1 || (Kp >= 2 && isfinite(Lg) && Lg <= L[1]);
     if (accepted) *accepted = acc;
     int rc;
     if (acc) {
-        double *w = malloc(sizeof(double) * Kp), mup[96];
+        double *w = malloc(sizeof(double) * Kp), *mup = malloc(sizeof(double) * D);
         rc = orc_weights(Kp, p->lambda, L, w);
         for (int d = 0; d < D; ++d) {
             double s = 0;
@@ -1323,6 +1334,7 @@ int orc_mppi_step_proposal(const orc_model *m, const orc_params *p, uint32_t ste
         }
         orc_shift(p, mup, mu, u0);
         free(w);
+        free(mup);
     } else {
         rc = orc_mppi_step(m, p, step, x0, mu, u0, costs, nthreads);
     }

@@ -14,7 +14,7 @@ from . import binding as B
 from . import workloads as W
 from .proposal import FALL_Z, _stage_cost_torch, episode
 
-BASES = {"cubic": 0, "linear": 1, "zeroth_order": 2}
+BASES = {"cubic": 0, "linear": 1, "zeroth_order": 2, "direct": 3}
 
 
 def _summary(costs, falls):
@@ -25,9 +25,11 @@ def _summary(costs, falls):
 
 
 def sampling_ablation(seeds=range(10), steps=200, arith="fp64", log=print):
-    """Episode cost with each knot interpolation on three tasks: the heightfield walk with
-    6 and with 4 knots per joint, and the climb onto the 0.3 m box with the base height
-    target raised by the box height.  Same seeds, samples and horizon for every basis."""
+    """Episode cost with each sampling representation on three tasks: the heightfield walk
+    with 6 and with 4 knots per joint, and the climb onto the 0.3 m box with the base
+    height target raised by the box height.  Same seeds, samples and horizon for every
+    representation; direct sampling draws one value per control step (H per joint) with
+    the same sigma."""
     tasks = [
         ("heightfield_walk_6_knots", W.TERRAIN_WALK, {}),
         ("heightfield_walk_4_knots", W.TERRAIN_WALK, {"nk": 4}),
@@ -41,6 +43,8 @@ def sampling_ablation(seeds=range(10), steps=200, arith="fp64", log=print):
             costs, falls = [], 0
             for sd in seeds:
                 p = dict(W.params_dict(wl, sd, **over), basis=basis)
+                if basis == 3:  # direct: one value per control step (lane-split rollout)
+                    p.update(nk=p["H"], lanes=16)
                 c, xf, _, _ = episode(model, p, sd, steps, arith=arith)
                 costs.append(c)
                 falls += int(not (xf[2] > FALL_Z))

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -19,7 +20,7 @@
 #include "tracking_launch.h"
 
 // MPPI_LANES_DEFAULT picks the lane-split rollout where its LDS fits
-constexpr bool kSplitByDefault = false;
+constexpr bool kSplitByDefault = true;
 
 struct mppi_model {
     mppi_model_desc desc;
@@ -51,6 +52,7 @@ struct mppi_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t off_pstats = 0;
+    size_t off_gate = 0;  // gate costs (2 floats) and the skip flag of the fallback rollout
     // Eq. 3 / Eq. 4 tracking cost (p.cost == MPPI_COST_TRACKING): parameters and the
     // trajectory region the cost kernel reads
     track::TrackDev track{};
@@ -159,6 +161,11 @@ void build_spline(int nk, int H, double dt, int basis, std::vector<double>& B, s
     const double T = H * dt, h = T / (nk - 1);
     B.assign((size_t)H * nk, 0.0);
     S.assign((size_t)nk * nk, 0.f);
+    if (basis == MPPI_BASIS_DIRECT) {  // nk == H: identity, one-step advance with the last value held
+        for (int k = 0; k < H; ++k) B[(size_t)k * nk + k] = 1.0;
+        for (int i = 0; i < nk; ++i) S[(size_t)i * nk + std::min(i + 1, nk - 1)] = 1.f;
+        return;
+    }
     std::vector<double> y(nk), m(nk);
     for (int j = 0; j < nk; ++j) {
         std::fill(y.begin(), y.end(), 0.0);
@@ -341,7 +348,13 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     *out = nullptr;
     if (p->K < 1) return fail(nullptr, MPPI_EINVAL, "K must be >= 1");
     if (p->H < 1 || p->H > MPPI_MAX_HORIZON) return fail(nullptr, MPPI_EINVAL, "H must be in [1, 256]");
-    if (p->n_knots < 2 || p->n_knots > MPPI_MAX_KNOTS) return fail(nullptr, MPPI_EINVAL, "n_knots must be in [2, 8]");
+    if (p->basis == MPPI_BASIS_DIRECT) {
+        if (p->n_knots != p->H) return fail(nullptr, MPPI_EINVAL, "MPPI_BASIS_DIRECT needs n_knots == H");
+        if (p->lanes == MPPI_LANES_QUAD || p->cost != MPPI_COST_RUNNING)
+            return fail(nullptr, MPPI_EINVAL, "MPPI_BASIS_DIRECT needs the lane-split rollout and the running cost");
+    } else if (p->n_knots < 2 || p->n_knots > MPPI_MAX_KNOTS) {
+        return fail(nullptr, MPPI_EINVAL, "n_knots must be in [2, 8]");
+    }
     if (!finite_pos(p->dt)) return fail(nullptr, MPPI_EINVAL, "dt must be > 0");
     if (p->arith != MPPI_ARITH_FP64 && p->arith != MPPI_ARITH_FP32 && p->arith != MPPI_ARITH_MIXED)
         return fail(nullptr, MPPI_EINVAL, "arith must be MPPI_ARITH_FP64, _FP32 or _MIXED");
@@ -350,8 +363,8 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     if (!std::isfinite(p->kp) || !std::isfinite(p->kd) || p->kd < 0.f)
         return fail(nullptr, MPPI_EINVAL, "kp must be finite, kd >= 0");
     if ((long)p->K * p->H > (1L << 31)) return fail(nullptr, MPPI_EINVAL, "K * H too large");
-    if (p->basis < MPPI_BASIS_CUBIC || p->basis > MPPI_BASIS_ZERO)
-        return fail(nullptr, MPPI_EINVAL, "basis must be MPPI_BASIS_CUBIC, _LINEAR or _ZERO");
+    if (p->basis < MPPI_BASIS_CUBIC || p->basis > MPPI_BASIS_DIRECT)
+        return fail(nullptr, MPPI_EINVAL, "basis must be MPPI_BASIS_CUBIC, _LINEAR, _ZERO or _DIRECT");
     if (p->cost != MPPI_COST_RUNNING && p->cost != MPPI_COST_TRACKING)
         return fail(nullptr, MPPI_EINVAL, "cost must be MPPI_COST_RUNNING or MPPI_COST_TRACKING");
     if (p->lanes != MPPI_LANES_DEFAULT && p->lanes != MPPI_LANES_QUAD && p->lanes != MPPI_LANES_SPLIT)
@@ -361,12 +374,13 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
         return fail(nullptr, MPPI_EINVAL, "the lane-split rollout's LDS does not fit this heightfield");
     mppi_ctx* c = new (std::nothrow) mppi_ctx();
     if (!c) return fail(nullptr, MPPI_ENOMEM, "host allocation failed");
-    if (p->arith == MPPI_ARITH_MIXED && (p->lanes == MPPI_LANES_QUAD || !split_fits)) {
+    const bool needs_split = p->arith == MPPI_ARITH_MIXED || p->basis == MPPI_BASIS_DIRECT;
+    if (needs_split && (p->lanes == MPPI_LANES_QUAD || !split_fits)) {
         delete c;
-        return fail(nullptr, MPPI_EINVAL, "MPPI_ARITH_MIXED needs the lane-split rollout");
+        return fail(nullptr, MPPI_EINVAL, "MPPI_ARITH_MIXED and MPPI_BASIS_DIRECT need the lane-split rollout");
     }
     c->split = p->lanes == MPPI_LANES_SPLIT ||
-               (p->lanes == MPPI_LANES_DEFAULT && split_fits && (kSplitByDefault || p->arith == MPPI_ARITH_MIXED));
+               (p->lanes == MPPI_LANES_DEFAULT && split_fits && (kSplitByDefault || needs_split));
     c->model = *model;
     c->p = *p;
     c->D = 12 * p->n_knots;
@@ -386,6 +400,7 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     c->off_costs_p = o; o = align256(o + sizeof(float) * p->K);
     c->off_eps_p = o; o = align256(o + sizeof(float) * (size_t)c->D * p->K);
     c->off_pstats = o; o = align256(o + sizeof(int) * 2);
+    c->off_gate = o; o = align256(o + sizeof(float) * 4);
     if (p->cost == MPPI_COST_TRACKING) {
         c->off_traj = o;
         o = align256(o + sizeof(float) * (size_t)p->K * (p->H + 1) * model->nx);
@@ -496,7 +511,8 @@ mppi_status mppi_sample(mppi_ctx* c, float* d_eps, uint32_t* d_raw)
     return hip_check(c, mppi::launch_sample(P, c->D, d_eps, d_raw, c->stream), "sample launch");
 }
 
-static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, float* d_costs, float* d_traj)
+static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, float* d_costs, float* d_traj,
+                           const int* d_skip = nullptr)
 {
     const bool tracking = c->p.cost == MPPI_COST_TRACKING;
     if (tracking && !c->track_set) return fail(c, MPPI_ESTATE, "tracking cost not set (call mppi_set_tracking_cost)");
@@ -514,6 +530,8 @@ static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, f
     a.costs = d_costs;
     a.traj = d_traj;
     a.samples_per_block = 16;
+    a.direct = c->p.basis == MPPI_BASIS_DIRECT;
+    a.skip = d_skip;
     mppi_status s;
     if ((s = hip_check(c, launch_roll(c, P, a, c->stream),
                        "rollout launch")) ||
@@ -580,13 +598,17 @@ mppi_status mppi_update(mppi_ctx* c, const float* d_costs, const float* d_eps, f
 
 // Proposal step on the plain kernels: the k_prop samples theta_n = c + e_n are rolled out
 // through the explicit-noise path with unit scale, where e holds Philox noise scaled by
-// sd for n >= 2, zero for the centre (n = 0) and nominal - c for n = 1.  With the cost
-// gate the plain rollout of the step (K Philox samples around the nominal) runs at the
-// same time on the bound stream while the proposal rollout runs on the side stream; the
-// update kernel then reads the two leading proposal costs and updates over whichever set
-// the gate picks, so the step needs no host round trip.  Accepted: mu' = c + sum w_n e_n /
-// sum w_n, the weighted mean of theta (centre c, unit scale).  Ungated: the proposal
-// rollout alone.
+// sd for n >= 2, zero for the centre (n = 0) and nominal - c for n = 1.  A gated step
+// takes the proposal when its cost under the gate (the centre's, or the least of its
+// samples other than the nominal) is finite and not above the nominal's, and falls back to
+// a plain step with K samples around the nominal otherwise.  With the lane-split rollout
+// the gate is decided on the device right after the proposal rollout and the plain
+// rollout runs only on a fallback (it returns at once when the proposal was taken), so a
+// step rolls out k_prop + K samples only when it falls back; with the quad rollout the
+// plain rollout runs beside the proposal's on an internal stream.  The update kernel
+// reads the gate costs and updates over whichever set was chosen; no host round trip.
+// Accepted: mu' = c + sum w_n e_n / sum w_n, the weighted mean of theta (centre c, unit
+// scale).  Ungated: the proposal rollout alone.
 static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int kp,
                                  int gate, float* d_u0_out)
 {
@@ -596,6 +618,8 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
     Pp.sigma = 1.0f;
     float* e = wsf(c, c->off_eps_p);
     float* costs_p = wsf(c, c->off_costs_p);
+    float* g = wsf(c, c->off_gate);
+    int* skip = (int*)(g + 2);
     if ((s = hip_check(c, mppi::launch_sample(Pp, c->D, e, nullptr, c->stream), "proposal noise launch"))) return s;
     if ((s = hip_check(c, prop::launch_proposal_noise(kp, c->D, e, d_center, d_sd, wsf(c, c->off_mu), c->stream),
                        "proposal scale launch")))
@@ -610,22 +634,30 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
     a.eps_sd = 1;
     a.costs = costs_p;
     a.samples_per_block = 16;
-    const bool gated = gate == MPPI_PROPOSAL_GATE_COST;
+    a.direct = c->p.basis == MPPI_BASIS_DIRECT;
+    const bool gated = gate == MPPI_PROPOSAL_GATE_COST || gate == MPPI_PROPOSAL_GATE_BEST;
+    const int best = gate == MPPI_PROPOSAL_GATE_BEST;
     float* costs = wsf(c, c->off_costs);
-    if (gated) {
+    if (gated && c->split) {
+        // proposal rollout, the gate, then the plain rollout (skipped when the gate takes
+        // the proposal), all on the bound stream
+        if ((s = hip_check(c, launch_roll(c, Pp, a, c->stream), "proposal rollout launch")) ||
+            (s = hip_check(c, prop::launch_gate(kp, costs_p, best, g, skip, c->stream), "gate launch")) ||
+            (s = rollout(c, d_x0, nullptr, costs, nullptr, skip)))
+            return s;
+    } else if (gated) {
         if (!c->side) return fail(c, MPPI_ESTATE, "no side stream (bind the controller again)");
         if ((s = hip_check(c, hipEventRecord(c->ev_fork, c->stream), "fork record")) ||
             (s = hip_check(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "fork wait")) ||
-            (s = hip_check(c, launch_roll(c, Pp, a, c->side),
-                           "proposal rollout launch")) ||
+            (s = hip_check(c, launch_roll(c, Pp, a, c->side), "proposal rollout launch")) ||
             (s = hip_check(c, hipEventRecord(c->ev_join, c->side), "join record")))
             return s;
         mppi_status rs = rollout(c, d_x0, nullptr, costs, nullptr);
         // join before returning, also after a failed launch, so that no work is left on the side stream
         if ((s = hip_check(c, hipStreamWaitEvent(c->stream, c->ev_join, 0), "join wait"))) return s;
         if (rs) return rs;
-    } else if ((s = hip_check(c, launch_roll(c, Pp, a, c->stream),
-                              "proposal rollout launch"))) {
+        if ((s = hip_check(c, prop::launch_gate(kp, costs_p, best, g, skip, c->stream), "gate launch"))) return s;
+    } else if ((s = hip_check(c, launch_roll(c, Pp, a, c->stream), "proposal rollout launch"))) {
         return s;
     }
     const mppi::DevParams P = dev_params(c);
@@ -637,7 +669,7 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
     u.mu = wsf(c, c->off_mu);
     u.prop = 1;
     u.Kp = kp;
-    u.gate = gated ? costs_p : nullptr;
+    u.gate = gated ? g : nullptr;
     u.costs_p = costs_p;
     u.eps_p = e;
     u.mu_p = d_center;
@@ -741,7 +773,8 @@ mppi_status mppi_step_proposal(mppi_ctx* c, const float* d_x0, const float* d_ce
     if ((s = need_bound(c))) return s;
     if (!d_x0 || !d_center || !d_sd || !d_u0_out) return fail(c, MPPI_EINVAL, "null argument");
     if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
-    if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE) return fail(c, MPPI_EINVAL, "unknown gate");
+    if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE && gate != MPPI_PROPOSAL_GATE_BEST)
+        return fail(c, MPPI_EINVAL, "unknown gate");
     if (c->p.cost != MPPI_COST_RUNNING) return fail(c, MPPI_EINVAL, "the proposal step uses the running cost");
     return step_proposal(c, d_x0, d_center, d_sd, k_prop, gate, d_u0_out);
 }
@@ -759,7 +792,8 @@ mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, int gat
     if (c->p.cost != MPPI_COST_RUNNING) return fail(c, MPPI_EINVAL, "the proposal step uses the running cost");
     if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
     if (!cmd || !origin_xy) return fail(c, MPPI_EINVAL, "null command or origin");
-    if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE) return fail(c, MPPI_EINVAL, "unknown gate");
+    if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE && gate != MPPI_PROPOSAL_GATE_BEST)
+        return fail(c, MPPI_EINVAL, "unknown gate");
     if (!(c->p.sigma > 0.f)) return fail(c, MPPI_EINVAL, "the proposal needs sigma > 0 (upper std clamp)");
     for (int i = 0; i < 3; ++i) c->cmd_origin[i] = cmd[i];
     c->cmd_origin[3] = origin_xy[0];

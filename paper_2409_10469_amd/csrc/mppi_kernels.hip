@@ -180,11 +180,15 @@ __device__ __forceinline__ float block_reduce(float v, float* sh, bool is_min)
     return r;
 }
 
+// knots per joint up to kMaxUpdKnots (the direct representation has one per control
+// step): the weighted noise sums run over chunks of kMaxKnots knots, one pass over K each
+constexpr int kMaxUpdKnots = 256;
+
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, UpdateArgs a)
 {
     __shared__ float sh[kUpdWaves];
     __shared__ float acc_w[kMaxKnots][kUpdWaves];
-    __shared__ float mup[kMaxKnots];
+    __shared__ float mup[kMaxUpdKnots];
     const int j = blockIdx.x, t = threadIdx.x, nk = P.nk;
     // a proposal step whose gate accepts updates over the proposal's samples
     const bool prop = a.prop && (!a.gate || (fabsf(a.gate[0]) <= 3.0e38f && a.gate[0] <= a.gate[1]));
@@ -202,41 +206,43 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, Update
     lmin = block_reduce(lmin, sh, true);
     const bool none = !(fabsf(lmin) <= 3.0e38f);
     float s = 0.f;
-    float acc[kMaxKnots];
+    for (int c0 = 0; c0 < nk; c0 += kMaxKnots) {
+        float acc[kMaxKnots];
 #pragma unroll
-    for (int i = 0; i < kMaxKnots; ++i) acc[i] = 0.f;
-    if (!none) {
-        for (int n = t; n < K; n += kUpdThreads) {
-            const float c = costs[n];
-            const float e = (fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) : 0.f;
-            s += e;
-            if (n > 0) {
+        for (int i = 0; i < kMaxKnots; ++i) acc[i] = 0.f;
+        if (!none) {
+            for (int n = t; n < K; n += kUpdThreads) {
+                const float c = costs[n];
+                const float e = (fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) : 0.f;
+                if (c0 == 0) s += e;
+                if (n > 0) {
 #pragma unroll
-                for (int i = 0; i < kMaxKnots; ++i)
-                    if (i < nk) acc[i] += e * eps[(size_t)n * eps_sn + (size_t)(j * nk + i) * eps_sd];
+                    for (int i = 0; i < kMaxKnots; ++i)
+                        if (c0 + i < nk) acc[i] += e * eps[(size_t)n * eps_sn + (size_t)(j * nk + c0 + i) * eps_sd];
+                }
             }
         }
-    }
-    s = block_reduce(s, sh, false);
+        if (c0 == 0) s = block_reduce(s, sh, false);
 #pragma unroll
-    for (int i = 0; i < kMaxKnots; ++i) {
-        const float r = wave_reduce(acc[i], false);
-        if ((t & 63) == 0) acc_w[i][t >> 6] = r;
+        for (int i = 0; i < kMaxKnots; ++i) {
+            const float r = wave_reduce(acc[i], false);
+            if ((t & 63) == 0) acc_w[i][t >> 6] = r;
+        }
+        __syncthreads();
+        if (t < kMaxKnots && c0 + t < nk) {
+            float acc_t = acc_w[t][0];
+            for (int w = 1; w < kUpdWaves; ++w) acc_t += acc_w[t][w];
+            const float m = mu[j * nk + c0 + t];
+            mup[c0 + t] = none ? m : m + sigma * (acc_t / s);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (t < nk) {
-        float acc_t = acc_w[t][0];
-        for (int w = 1; w < kUpdWaves; ++w) acc_t += acc_w[t][w];
-        const float m = mu[j * nk + t];
-        mup[t] = none ? m : m + sigma * (acc_t / s);
-    }
-    __syncthreads();
-    if (t < nk) {
-        if (a.knots_out) a.knots_out[j * nk + t] = mup[t];
+    for (int q = t; q < nk; q += kUpdThreads) {
+        if (a.knots_out) a.knots_out[j * nk + q] = mup[q];
         if (a.nominal_out) {
             float v = 0.f;
-            for (int l = 0; l < nk; ++l) v += a.S[t * nk + l] * mup[l];
-            a.nominal_out[j * nk + t] = v;
+            for (int l = 0; l < nk; ++l) v += a.S[q * nk + l] * mup[l];
+            a.nominal_out[j * nk + q] = v;
         }
     }
     if (t == 0 && a.u0_out) a.u0_out[j] = mup[0];

@@ -29,6 +29,8 @@ struct RolloutArgs {
     float* costs;          // K
     float* traj;           // K x (H+1) x nx or null
     int samples_per_block; // samples per workgroup (4 lanes each)
+    int direct;            // lane-split rollout: one value per step (nk == H) instead of the basis
+    const int* skip;       // lane-split rollout: device flag; when set the launch does nothing
 };
 
 struct UpdateArgs {

@@ -6,6 +6,8 @@
 //                           then the command
 //   batch_features_kernel, batch_head_noise_kernel - the same for the learned-proposal
 //                           instances of a batch, one row per instance
+//   gate_kernel           - the fallback decision of a gated proposal step from the
+//                           proposal's costs, before the plain samples are rolled out
 #include <hip/hip_runtime.h>
 
 #include "mppi_device.h"
@@ -24,6 +26,42 @@ __global__ __launch_bounds__(256) void proposal_noise_kernel(int Kp, int D, floa
     if (n == 0) e[i] = 0.f;
     else if (n == 1) e[i] = nominal[d] - center[d];
     else e[i] = sd[d] * e[i];
+}
+
+// One workgroup: g[0] is the proposal's cost under the gate (its centre's, or the least
+// over its samples other than the nominal), g[1] the nominal's (sample 1); the proposal
+// is taken when g[0] is finite and not above g[1] -- the update kernel reads g and decides
+// by the same comparison -- and skip is set then, so the plain rollout returns at once.
+__global__ __launch_bounds__(256) void gate_kernel(int Kp, const float* __restrict__ costs_p, int best,
+                                                   float* __restrict__ g, int* __restrict__ skip)
+{
+    __shared__ float sh[4];
+    float m = __int_as_float(0x7f800000);
+    if (best) {
+        for (int n = threadIdx.x; n < Kp; n += 256) {
+            const float c = costs_p[n];
+            if (n != 1 && fabsf(c) <= 3.0e38f) m = fminf(m, c);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+        __syncthreads();
+        m = fminf(fminf(sh[0], sh[1]), fminf(sh[2], sh[3]));
+    } else {
+        m = costs_p[0];
+    }
+    if (threadIdx.x == 0) {
+        const float nom = costs_p[1];
+        g[0] = m;
+        g[1] = nom;
+        skip[0] = (fabsf(m) <= 3.0e38f && m <= nom) ? 1 : 0;
+    }
+}
+
+hipError_t launch_gate(int Kp, const float* costs_p, int best, float* g, int* skip, hipStream_t st)
+{
+    hipLaunchKernelGGL(gate_kernel, dim3(1), dim3(256), 0, st, Kp, costs_p, best, g, skip);
+    return hipGetLastError();
 }
 
 hipError_t launch_proposal_noise(int Kp, int D, float* e, const float* center, const float* sd, const float* nominal,

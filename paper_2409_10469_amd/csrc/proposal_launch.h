@@ -19,6 +19,10 @@ static_assert(sizeof(BatchPropRow) == 32, "BatchPropRow is 32 bytes");
 // row 1 is nominal - center and row n >= 2 is sd * e_n
 hipError_t launch_proposal_noise(int Kp, int D, float* e, const float* center, const float* sd, const float* nominal,
                                  hipStream_t st);
+// the gate of a proposal step from the proposal's Kp costs (best = 0: its centre's cost,
+// 1: the least cost of its samples other than the nominal, sample 1) against the
+// nominal's: g = {that cost, nominal's}, skip = 1 when the proposal is taken
+hipError_t launch_gate(int Kp, const float* costs_p, int best, float* g, int* skip, hipStream_t st);
 // state x (37 floats) and cmd_origin = (cmd[3], origin[2]) -> 40 raw features
 hipError_t launch_features(const float* x, const float* cmd_origin, float* feat, hipStream_t st);
 // raw features (np x 40) of the proposal rows' current states

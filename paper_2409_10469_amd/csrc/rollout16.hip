@@ -295,7 +295,7 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
                                 dB, nB);
         }
         if constexpr (SCENE == 3) {
-            V3<R> nl;
+            V3<R> nl = v3(R(0), R(0), R(1));  // left as is when the foot misses the box
             hitB = sphere_aabox(mulT(bf.Rb, pfw - bx.p), MR.foot_r, v3(MR.bx_hx, MR.bx_hy, MR.bx_hz), dB, nl);
             nB = mul(bf.Rb, nl);  // box -> foot (world)
         }
@@ -304,15 +304,18 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
         for (int it = 0; it < ((SCENE == 2 || SCENE == 3) ? 2 : 1); ++it) {
             if (!__builtin_amdgcn_ballot_w64(it < cnt)) break;
             const bool isB = (it == 0) ? !hitT : true;  // pass 0: terrain if touched, else the box
-            const R wgt = (it < cnt) ? R(1) : R(0);
-            const R delta = isB ? dB : dT;
-            const V3<R> nw = selv(isB, nB, nT);
+            // a lane without a contact in this pass takes a neutral one (zero depth, upward
+            // normal, zero weight), so nothing it adds can be non-finite
+            const bool on = it < cnt;
+            const R wgt = on ? R(1) : R(0);
+            const R delta = on ? (isB ? dB : dT) : R(0);
+            const V3<R> nw = on ? selv(isB, nB, nT) : v3(R(0), R(0), R(1));
             const V3<R> n = mulT(Rm, nw);
             V3<R> vo = zero;
             [[maybe_unused]] V3<R> pcw;
             if constexpr (SCENE == 3) {
                 pcw = pfw - MR.foot_r * nw;
-                vo = selv(isB, mulT(Rm, box_point_vel(bx, bf, pcw)), zero);
+                vo = selv(isB && on, mulT(Rm, box_point_vel(bx, bf, pcw)), zero);
             }
             leg_contact_w(MR, G, vb, w, lg.qd, delta, n, G.pf - MR.foot_r * n, vo, dt, wgt, Q, rb, L, F, eta);
             if constexpr (SCENE == 3) {
@@ -405,10 +408,13 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
             for (int it = 0; it < 2; ++it) {
                 if (!__builtin_amdgcn_ballot_w64(it < cnt)) break;
                 const bool pair = (it == 0) && hitP;  // pass 0: the pair if touching, else the terrain
-                const R wgt = (it < cnt) ? R(1) : R(0);
+                // a lane without a contact in this pass takes a neutral one (zero depth and
+                // velocity, zero weight), so nothing it adds can be non-finite
+                const bool on = it < cnt;
+                const R wgt = on ? R(1) : R(0);
                 const R wq = pair ? wgt : R(0);
-                const V3<R> n = selv(pair, nPw, nG);
-                contact_law(MR, pair ? dP : dG, n, selv(pair, vP - vQ, vP), F, eta);
+                const V3<R> n = on ? selv(pair, nPw, nG) : v3(R(0), R(0), R(1));
+                contact_law(MR, on ? (pair ? dP : dG) : R(0), n, on ? selv(pair, vP - vQ, vP) : zero, F, eta);
                 F = wgt * F;
                 eta = wgt * eta;
                 // P's side in P's frame (force +F), Q's side in Q's frame (force -F)
@@ -552,8 +558,11 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
                                                        const float* __restrict__ x0,
                                                        const float* __restrict__ eps_in, int eps_sn, int eps_sd,
                                                        float* __restrict__ eps_out, float* __restrict__ costs,
-                                                       float* __restrict__ traj)
+                                                       float* __restrict__ traj, int direct,
+                                                       const int* __restrict__ skip)
 {
+    // a plain fallback rollout whose proposal the gate took: nothing to do
+    if (skip && skip[0]) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     // the model's constants are read from LDS (values in vector registers), which keeps the
     // scalar registers for the kernel's pointers and loop state
@@ -584,12 +593,13 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
     const int nk = P.nk;
     const R sigma = P.sigma;
 
-    // knots of this lane's joint, theta = mu + sigma eps (sample 0 is the nominal)
+    // knots of this lane's joint, theta = mu + sigma eps (sample 0 is the nominal); the
+    // direct representation draws one value per step inside the step loop instead
     R th[kMaxKnots];
 #pragma unroll
     for (int i = 0; i < kMaxKnots; ++i) {
         th[i] = R(0);
-        if (i < nk) {
+        if (!direct && i < nk) {
             const int d = (3 * leg + jl) * nk + i;
             R e;
             if (eps_in) {
@@ -619,9 +629,22 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
     R L = R(0);
     for (int k = 0; k < P.H; ++k) {
         R uj = R(0);
+        if (direct) {
+            // value k of this lane's joint (nk == H): theta = mu + sigma eps
+            const int d = (3 * leg + jl) * nk + k;
+            R e;
+            if (eps_in) {
+                e = eps_in[(size_t)ns * eps_sn + (size_t)d * eps_sd];
+            } else {
+                e = gauss_elem<R>(P, (uint32_t)ns, (uint32_t)d);
+                if (valid && sub < 3 && eps_out) eps_out[(size_t)d * P.K + n] = (float)e;
+            }
+            uj = R(mu[d]) + (ns ? sigma * e : R(0));
+        } else {
 #pragma unroll
-        for (int i = 0; i < kMaxKnots; ++i)
-            if (i < nk) uj += R(gB[k * nk + i]) * th[i];
+            for (int i = 0; i < kMaxKnots; ++i)
+                if (i < nk) uj += R(gB[k * nk + i]) * th[i];
+        }
         R tau2;
         r16::step16<SCENE, R, S>(MR, MS, sHF, dt, kp, kd, g, b, lg, bx, uj, my_red, my_sum, tau2);
         round_state(b, lg);
@@ -656,7 +679,7 @@ hipError_t launch_t(const ModelT<R>& Mr, const ModelT<S>& Ms, const DevParams& P
     if (lds > 65536) return hipErrorInvalidValue;
 #define MPPI_LAUNCH_R16(SC)                                                                                     \
     hipLaunchKernelGGL((rollout16_kernel<SC, R, S>), dim3(blocks), dim3(64), lds, st, Mr, Ms, P, a.B, a.hf, a.mu, \
-                       a.x0, a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj)
+                       a.x0, a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj, a.direct, a.skip)
     switch (Mr.scene) {
     case 0: MPPI_LAUNCH_R16(0); break;
     case 1: MPPI_LAUNCH_R16(1); break;

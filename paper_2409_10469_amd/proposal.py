@@ -265,16 +265,16 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024, 2048, 4096), K_learned=10
         log(f"  plain K={K}: episode cost {np.mean(costs):.3f}, step latency p50 {np.percentile(lat, 50):.3f} "
             f"p99 {np.percentile(lat, 99):.3f} ms")
     kp = K_learned // ratio
-    for gate in ("cost", "none"):
+    for gate in ("cost", "best", "none"):
         lat = []
         res = [episode(model, dict(p, K=K_learned), s, steps, policy=policy, k_prop=kp, arith=arith, gate=gate,
                        lat=lat) for s in seeds]
         costs = [r[0] for r in res]
         acc = sum(r[2] for r in res)
         n = sum(r[3] for r in res)
-        # the gated step rolls out the proposal and the plain step's K samples side by side
-        # and lets the update pick one set; the ungated step rolls out the proposal only
-        samples = float(kp + K_learned) if gate == "cost" else float(kp)
+        # a gated step on the lane-split rollout rolls out the proposal and, only when the
+        # gate falls back, the plain step's K samples; the ungated step the proposal only
+        samples = float(kp + (1.0 - acc / max(n, 1)) * K_learned) if gate != "none" else float(kp)
         out["learned_" + gate] = dict(mean=float(np.mean(costs)), ci95=ci95(costs), costs=costs, k_prop=kp,
                                       K_fallback=K_learned,
                                       accepted=acc, steps=n, acceptance=acc / max(n, 1), samples_per_step=samples,

@@ -79,11 +79,13 @@ static void fill(int scene, mppi_model_desc& d, orc_model& o, std::vector<float>
 }
 
 static int g_lanes = 0;  // rollout decomposition of the controllers made here
+static int g_basis = 0;  // knot interpolation of the controllers made here
 
 static void params(int K, int H, int nk, float dt, mppi_params& p, orc_params& o)
 {
     p = mppi_params{};
     p.lanes = g_lanes;
+    p.basis = g_basis;
     p.K = K; p.H = H; p.n_knots = nk; p.dt = dt; p.sigma = 0.3f; p.lambda = 0.1f; p.kp = 40.f; p.kd = 1.f;
     p.w_height = 100.f; p.h_ref = 0.27f; p.w_upright = 10.f; p.w_vel = 1.f; p.v_ref = 0.5f; p.w_torque = 1e-3f;
     p.w_reach = 1.f; p.w_box = 2.f; p.goal[0] = 2.0f; p.goal[1] = -0.5f; p.seed = 0x1234abcdull; p.instance = 3;
@@ -92,6 +94,7 @@ static void params(int K, int H, int nk, float dt, mppi_params& p, orc_params& o
     o.w_h = p.w_height; o.h_ref = p.h_ref; o.w_o = p.w_upright; o.w_v = p.w_vel; o.v_ref = p.v_ref;
     o.w_tau = p.w_torque; o.w_reach = p.w_reach; o.w_box = p.w_box; o.goal[0] = p.goal[0]; o.goal[1] = p.goal[1];
     o.seed = p.seed; o.instance = p.instance;
+    o.basis = p.basis;
 }
 
 // standing pose with small deterministic joint offsets (and the box 1 m ahead)
@@ -384,11 +387,15 @@ int main(int argc, char** argv)
     g_lanes = MPPI_LANES_SPLIT;
     steps_case("split flat K=64 H=25", MPPI_SCENE_FLAT, 64, 25, 4, 0.02f, 1);
     rollout_case(MPPI_SCENE_FLAT, 21, 4);
+    rollout_case(MPPI_SCENE_FREE_BOX, 9, 8);  // the contact passes read only what the tests wrote
     if (!quick) {
         steps_case("split heightfield K=16 H=12", MPPI_SCENE_HEIGHTFIELD, 16, 12, 6, 0.01f, 1);
         steps_case("split free box K=18 H=10", MPPI_SCENE_FREE_BOX, 18, 10, 8, 0.01f, 1);
-        rollout_case(MPPI_SCENE_FREE_BOX, 9, 8);
     }
+    // direct per-step sampling (one value per step, drawn in the step loop)
+    g_basis = MPPI_BASIS_DIRECT;
+    steps_case("split direct flat K=21 H=12", MPPI_SCENE_FLAT, 21, 12, 12, 0.02f, 1);
+    g_basis = 0;
     g_lanes = 0;
     if (!no_batch) batch_case();
     for (void* p : g_mem) std::free(p);

@@ -84,7 +84,16 @@ hipError_t launch_rollout16(const DevModelF& Mf, const DevModelD& Md, int arith,
 {
     if (!rollout16_fits(arith, arith == 1 ? Mf.scene : Md.scene, arith == 1 ? Mf.hf_nx * Mf.hf_ny : Md.hf_nx * Md.hf_ny))
         fail("rollout16 LDS");
-    return launch_rollout(Mf, Md, arith, P, a, st);  // same ranges as the quad kernel
+    if (!a.direct) return launch_rollout(Mf, Md, arith, P, a, st);  // same ranges as the quad kernel
+    const int D = 12 * P.nk;  // direct: one value per step
+    if (P.K < 1 || P.H < 1 || P.nk != P.H) fail("rollout16 direct shape");
+    range_check(a.mu, 4ull * D, "rollout nominal");
+    range_check(a.x0, 4ull * P.nx, "rollout state");
+    range_check(a.costs, 4ull * P.K, "rollout costs");
+    if (a.eps_in) range_check(a.eps_in, 4 * strided_span(P.K, D, a.eps_sn, a.eps_sd), "rollout given noise");
+    CHK(a.eps_out, 4ull * D * P.K, "rollout noise out");
+    CHK(a.traj, 4ull * P.K * (P.H + 1) * P.nx, "rollout trajectories");
+    return hipSuccess;
 }
 
 bool rollout16_fits(int arith, int scene, int hf_cells)

@@ -224,10 +224,10 @@ def test_head_matches_oracle(B, nk):
 
 
 # ---------------------------------------------------------------------------- proposal step
-def _ctl(B, K=64, H=10):
+def _ctl(B, K=64, H=10, lanes=0):
     wl = W.FLAT_WALK
     md = round_model(W.model_dict(wl, 0))
-    p = round_params(W.params_dict(wl, 3, K=K, H=H))
+    p = round_params(W.params_dict(wl, 3, K=K, H=H, lanes=lanes))
     return md, p, O.Oracle(md), B.Controller(B.Model(md), p)
 
 
@@ -320,10 +320,14 @@ def test_training_pipeline_on_closed_loop_data(B):
 
 
 # ---------------------------------------------------------------------------- proposal step
-@pytest.mark.parametrize("accept,gate", [(True, "cost"), (False, "cost"), (False, "none")])
-def test_proposal_step_on_plain_kernels_matches_oracle(B, accept, gate):
-    """The proposal step in both branches, and ungated, against the oracle's proposal step."""
-    md, p, orc, ctl = _ctl(B)
+@pytest.mark.parametrize("lanes", [4, 16])
+@pytest.mark.parametrize("accept,gate", [(True, "cost"), (False, "cost"), (False, "none"), (True, "best"),
+                                         (False, "best")])
+def test_proposal_step_on_plain_kernels_matches_oracle(B, accept, gate, lanes):
+    """The proposal step in both branches of each gate, and ungated, against the oracle's
+    proposal step; with the lane-split rollout the plain fallback is rolled out only when
+    the gate rejects, with the quad rollout beside the proposal."""
+    md, p, orc, ctl = _ctl(B, lanes=lanes)
     D = 12 * p["nk"]
     rng = np.random.default_rng(2)
     mu = f32(W.stance_knots(p["nk"]))
@@ -342,7 +346,7 @@ def test_proposal_step_on_plain_kernels_matches_oracle(B, accept, gate):
     nom = ctl.get_nominal().cpu().numpy()
     acc, steps = ctl.proposal_stats()
     ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp,
-                                                         gate=0 if gate == "cost" else 1)
+                                                         gate={"cost": 0, "none": 1, "best": 2}[gate])
     taken = accept or gate == "none"
     assert oacc == taken and acc == int(taken) and steps == 1
     assert ctl.sync_status() == 0 and ctl.step_counter == 6

@@ -300,3 +300,61 @@ def test_split_box_push_chain_costs_sum_oracle_stage_costs(B, arith):
                 e = step_error(tr[n, k + 1], xn, box=True).max()
                 assert e <= bound(orc, xk, U[k], p["kp"], p["kd"], p["dt"]), (n, k, e)
         assert abs(c[n] - L) <= COST_TOL * max(abs(L), 1e-6), (n, c[n], L)
+
+
+# ---------------------------------------------------------------------------- direct sampling
+@pytest.mark.parametrize("workload,K,H", [(W.FLAT_WALK, 50, 10), (W.BOX_PUSH, 21, 10)])
+def test_split_direct_rollout_costs_10_steps(B, workload, K, H):
+    """Direct per-step sampling (basis 3, one value per step): 10-step costs against the
+    oracle's direct rollouts on the same noise."""
+    _say("split direct costs", workload["name"], K, H)
+    md, p, orc, model, ctl = _setup(B, workload, K=K, H=H, nk=H, basis=3)
+    x0 = f32(W.initial_state(3, workload["scene"]))
+    if workload["scene"] == W.SCENE_FREE_BOX:
+        x0 = box_contact_states(1, seed=5)[0]
+    mu = f32(W.stance_knots(H) + np.random.default_rng(2).uniform(-0.1, 0.1, 12 * H))
+    eps = f32(W.explicit_noise(5, K, H))
+    ctl.set_nominal(_dev(mu))
+    got = ctl.rollout_batch(_dev(x0), eps=_dev(eps)).cpu().numpy().astype(np.float64)
+    want = orc.rollout_batch(p, x0, mu, eps)
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-6)
+    assert rel.max() <= COST_TOL, (rel.max(), int(rel.argmax()))
+
+
+@pytest.mark.parametrize("K,H", [(256, 50), (1025, 60)])
+def test_split_direct_mppi_step_matches_oracle(B, K, H):
+    """Full control steps with direct sampling on the heightfield (Philox noise drawn in
+    the step loop, 12 H values updated over knot chunks): first control and shifted plan
+    against the oracle's Algorithm 1."""
+    _say("split direct control steps", K, H)
+    md, p, orc, model, ctl = _setup(B, W.TERRAIN_WALK, K=K, H=H, nk=H, basis=3)
+    for seed in range(2):
+        x0 = f32(W.initial_state(seed, W.SCENE_HEIGHTFIELD))
+        mu = f32(W.stance_knots(H))
+        ctl.set_nominal(_dev(mu))
+        ctl.set_step(seed)
+        u0 = ctl.step(_dev(x0)).cpu().numpy()
+        nominal = ctl.get_nominal().cpu().numpy()
+        assert ctl.sync_status() == 0
+        ou0, omu, ocosts, rc = orc.mppi_step(p, seed, x0, mu)
+        from tests.test_gpu_parity import r16_knot_sensitivity
+        assert r16_knot_sensitivity(p, seed, mu, ocosts) <= KNOT_TOL
+        assert np.abs(u0 - ou0).max() <= KNOT_TOL, seed
+        assert np.abs(nominal - omu).max() <= KNOT_TOL, seed
+
+
+def test_update_over_knot_chunks_matches_oracle(B):
+    """The update with 60 values per joint (eight chunks of the knot loop) against the
+    oracle's Eq. 1 / Eq. 2 on identical costs and noise."""
+    _say("update knot chunks")
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=700, H=60, nk=60, basis=3, dt=0.01)
+    rng = np.random.default_rng(9)
+    mu = f32(W.stance_knots(60) + rng.uniform(-0.2, 0.2, 720))
+    eps = f32(rng.standard_normal((700, 720)))
+    costs = f32(rng.uniform(0.5, 2.5, 700))
+    ctl.set_nominal(_dev(mu))
+    knots, w = ctl.update(_dev(costs), eps=_dev(eps), weights=True)
+    want, ww, rc = O.update(p, costs, mu, eps)
+    assert rc == 0
+    assert np.abs(knots.cpu().numpy() - want).max() <= 1e-5
+    np.testing.assert_allclose(w.cpu().numpy(), ww, rtol=1e-4, atol=1e-7)

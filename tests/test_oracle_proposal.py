@@ -118,3 +118,34 @@ def test_ungated_proposal_takes_the_proposal_samples():
     want_nom, want_u0 = O.shift(p, sum(wi * th for wi, th in zip(w, thetas)))
     np.testing.assert_allclose(nom, want_nom, rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(u0, want_u0, rtol=1e-12, atol=1e-14)
+
+
+def test_best_sample_gate_decides_on_the_least_proposal_cost():
+    """gate 2: the proposal is taken when its least cost over the samples other than the
+    nominal (sample 1) is not above the nominal's -- checked against per-sample rollouts --
+    and the step is then the weighted mean of the proposal samples, else the plain step."""
+    o, p, x0, mu = _setup()
+    D = 12 * p["nk"]
+    Kp = 6
+    seen = set()
+    for k, off in enumerate((0.02, 0.15, 0.3, 0.6, 0.9)):
+        rng = np.random.default_rng(20 + k)
+        center = mu + off * rng.choice([-1.0, 1.0], D)
+        sd = np.full(D, 0.08)
+        u0, nom, cp, cf, acc, rc = o.mppi_step_proposal(p, 4, x0, mu, center, sd, Kp, gate=2)
+        eps = O.sample_eps(dict(p, K=Kp), 4)
+        thetas = [center, mu] + [center + sd * eps[n] for n in range(2, Kp)]
+        L = np.array([o.rollout(p, x0, th) for th in thetas])
+        np.testing.assert_allclose(cp, L, rtol=1e-13)
+        want_acc = bool(np.delete(L, 1).min() <= L[1])
+        assert acc == want_acc
+        seen.add(acc)
+        if acc:
+            w = np.exp(-(L - L.min()) / p["lam"])
+            w /= w.sum()
+            want_nom, want_u0 = O.shift(p, sum(wi * th for wi, th in zip(w, thetas)))
+        else:
+            want_u0, want_nom, _, _ = o.mppi_step(p, 4, x0, mu)
+        np.testing.assert_allclose(nom, want_nom, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(u0, want_u0, rtol=1e-12, atol=1e-14)
+    assert seen == {True, False}  # both branches exercised
