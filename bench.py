@@ -478,6 +478,8 @@ def bench_ablation(args):
                                arith=args.arith, log=log)
     sweeps = AB.hyperparameter_sweeps(seeds=range(args.seed, args.seed + args.eval_seeds), steps=args.eval_steps,
                                       arith=args.arith, log=log)
+    sweeps["rate_hz_dt4ms"] = AB.control_rate_sweep(seeds=range(args.seed, args.seed + args.eval_seeds),
+                                                    arith=args.arith, log=log)
     walk = res["heightfield_walk_6_knots"]["bases"]
     out = {"metric": "closed-loop episode cost of the plain method's ablations", "value": walk["cubic"]["mean"],
            "unit": "episode cost (heightfield walk, cubic)", "n_gpus": 1, "steps": args.eval_steps,

@@ -95,6 +95,33 @@ def episode_held(model, p, seed, steps, hold, arith="fp64", trace=None):
     return float(cost.item()), x.cpu().numpy()
 
 
+RATE_FINE = dict(dt=0.004, H=125, holds=[1, 2, 3, 4, 5, 10, 20, 25], seconds=2.0)
+
+
+def control_rate_sweep(seeds=range(10), arith="fp64", fine=RATE_FINE, log=print):
+    """The control rate up to 250 Hz (Sec. IV-E sweeps 10-250 Hz): the heightfield walk with
+    plant and controller at dt = 4 ms (horizon 125 steps = 0.5 s, as the 50 x 10 ms
+    default), replanning every `hold` plant steps -- 250, 125, 83.3, 62.5, 50, 25, 12.5 and
+    10 Hz -- over episodes of the same 2 s as the default sweeps."""
+    wl = W.TERRAIN_WALK
+    model = B.Model(W.model_dict(wl, 0))
+    steps = int(round(fine["seconds"] / fine["dt"]))
+    res = {}
+    for hold in fine["holds"]:
+        rate = 1.0 / (fine["dt"] * hold)
+        costs, falls = [], 0
+        for sd in seeds:
+            p = dict(W.params_dict(wl, sd), dt=fine["dt"], H=fine["H"])
+            c, xf = episode_held(model, p, sd, steps, hold, arith=arith)
+            costs.append(c)
+            falls += int(not (xf[2] > FALL_Z))
+        res["%.4g" % rate] = dict(_summary(costs, falls), hold=hold)
+        log(f"  rate {rate:.4g} Hz (dt 4 ms, hold {hold}): episode cost {res['%.4g' % rate]['mean']:.3f}, "
+            f"falls {falls}/{len(costs)}")
+    best = min(res, key=lambda k: res[k]["mean"])
+    return dict(values=res, best=best, dt=fine["dt"], H=fine["H"], episode_seconds=fine["seconds"])
+
+
 SWEEPS = {
     "lam": [0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.3],
     "H": [5, 10, 20, 30, 40, 50, 75, 100],

@@ -78,7 +78,7 @@ static void fill(int scene, mppi_model_desc& d, orc_model& o, std::vector<float>
     o.box_mass = d.box_mass;
 }
 
-static int g_lanes = 0;  // rollout decomposition of the controllers made here
+static int g_lanes = MPPI_LANES_QUAD;  // rollout decomposition of the controllers made here
 static int g_basis = 0;  // knot interpolation of the controllers made here
 
 static void params(int K, int H, int nk, float dt, mppi_params& p, orc_params& o)
@@ -396,7 +396,7 @@ int main(int argc, char** argv)
     g_basis = MPPI_BASIS_DIRECT;
     steps_case("split direct flat K=21 H=12", MPPI_SCENE_FLAT, 21, 12, 12, 0.02f, 1);
     g_basis = 0;
-    g_lanes = 0;
+    g_lanes = MPPI_LANES_QUAD;
     if (!no_batch) batch_case();
     for (void* p : g_mem) std::free(p);
     std::printf("failures: %d\n", g_fail);

@@ -119,7 +119,7 @@ static void controller(mppi_model* m, mppi_policy* pol, int nx, int K, int H, in
     OK(mppi_update_shift(c, costs, u0, w));
     OK(mppi_step(c, x, u0));
     if (nx == 37 && K >= 2) {
-        for (int gate : {MPPI_PROPOSAL_GATE_COST, MPPI_PROPOSAL_GATE_NONE}) {
+        for (int gate : {MPPI_PROPOSAL_GATE_COST, MPPI_PROPOSAL_GATE_NONE, MPPI_PROPOSAL_GATE_BEST}) {
             OK(mppi_step_proposal(c, x, center, sd, 2, gate, u0));
             OK(mppi_step_proposal(c, x, center, sd, K, gate, u0));
         }

@@ -84,6 +84,7 @@ hipError_t launch_rollout16(const DevModelF& Mf, const DevModelD& Md, int arith,
 {
     if (!rollout16_fits(arith, arith == 1 ? Mf.scene : Md.scene, arith == 1 ? Mf.hf_nx * Mf.hf_ny : Md.hf_nx * Md.hf_ny))
         fail("rollout16 LDS");
+    CHK(a.skip, 4, "rollout skip flag");
     if (!a.direct) return launch_rollout(Mf, Md, arith, P, a, st);  // same ranges as the quad kernel
     const int D = 12 * P.nk;  // direct: one value per step
     if (P.K < 1 || P.H < 1 || P.nk != P.H) fail("rollout16 direct shape");
@@ -216,6 +217,15 @@ hipError_t launch_proposal_noise(int Kp, int D, float* e, const float* center, c
     range_check(center, 4ull * D, "proposal centre");
     range_check(sd, 4ull * D, "proposal std");
     range_check(nominal, 4ull * D, "proposal nominal");
+    return hipSuccess;
+}
+
+hipError_t launch_gate(int Kp, const float* costs_p, int best, float* g, int* skip, hipStream_t)
+{
+    if (Kp < 2 || (best != 0 && best != 1)) fail("gate shape");
+    range_check(costs_p, 4ull * Kp, "gate proposal costs");
+    range_check(g, 8, "gate costs");
+    range_check(skip, 4, "gate skip flag");
     return hipSuccess;
 }
 

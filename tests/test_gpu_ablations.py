@@ -65,3 +65,20 @@ def test_held_plan_follows_the_oracle_shift_chain(B, basis):
     assert replans == 4
     if basis == 2:  # the zeroth-order hold's shift is the identity: the replan's u0 is held
         np.testing.assert_array_equal(S, np.eye(p["nk"]))
+
+
+def test_fine_control_rate_sweep_runs_at_250_hz(B):
+    """The 4 ms plant and controller: replanning every step (250 Hz) is the plain closed
+    loop at dt = 4 ms, and a short sweep returns finite costs for every rate."""
+    from paper_2409_10469_amd import ablations as AB
+    from paper_2409_10469_amd import proposal as PR
+    wl = W.TERRAIN_WALK
+    model = B.Model(W.model_dict(wl, 0))
+    p = dict(W.params_dict(wl, 2, K=128), dt=0.004, H=125)
+    c1, x1, _, _ = PR.episode(model, p, 2, 40)
+    c2, x2 = AB.episode_held(model, p, 2, 40, hold=1)
+    assert c1 == c2 and np.array_equal(x1, x2)
+    res = AB.control_rate_sweep(seeds=range(1), fine=dict(AB.RATE_FINE, holds=[1, 2, 25], seconds=0.2),
+                                log=lambda *a: None)
+    assert set(res["values"]) == {"250", "125", "10"}
+    assert all(np.isfinite(v["mean"]) for v in res["values"].values())
