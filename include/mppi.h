@@ -38,12 +38,16 @@ extern "C" {
 
 typedef enum mppi_status {
     MPPI_OK = 0,
-    MPPI_WARN_ALL_NONFINITE = 1, /* every sample diverged: the nominal was kept (shifted) */
-    MPPI_EINVAL = -1,            /* bad argument; see mppi_last_error */
-    MPPI_ENOMEM = -2,            /* workspace too small */
-    MPPI_EHIP = -3,              /* a HIP runtime call failed */
-    MPPI_EBUDGET = -5,           /* batched serving: the instance does not fit in the HBM budget */
-    MPPI_ESTATE = -6             /* call out of order (e.g. no workspace bound) */
+    MPPI_WARN_ALL_NONFINITE = 1,   /* every sample diverged: the nominal was kept (shifted) */
+    MPPI_WARN_FALLBACK = 2,        /* the last (gated) proposal step fell back to plain MPPI */
+    MPPI_WARN_NONFINITE_INPUT = 3, /* the last step's device start state was not finite: no sample was
+                                      rolled out, every cost is +inf and the nominal was kept (shifted) */
+    MPPI_EINVAL = -1,              /* bad argument; see mppi_last_error */
+    MPPI_ENOMEM = -2,              /* workspace too small */
+    MPPI_EHIP = -3,                /* a HIP runtime call failed */
+    MPPI_ENONFINITE_INPUT = -4,    /* a host-visible start state is not finite: nothing was launched */
+    MPPI_EBUDGET = -5,             /* batched serving: the instance does not fit in the HBM budget */
+    MPPI_ESTATE = -6               /* call out of order (e.g. no workspace bound) */
 } mppi_status;
 
 enum {
@@ -224,7 +228,11 @@ mppi_status mppi_update(mppi_ctx *ctx, const float *d_costs, const float *d_eps,
 /* One full control step (Algorithm 1): sample, roll out, weight, update, take the first
  * control u = spline(mu', 0) into d_u0_out (12 floats), shift the nominal by dt, and
  * advance the step counter.  If every sample diverged the shifted old nominal is kept
- * and mppi_sync_status reports MPPI_WARN_ALL_NONFINITE. */
+ * and mppi_sync_status reports MPPI_WARN_ALL_NONFINITE.  The start state is checked for
+ * finiteness: when d_x0 is host-visible (managed or mapped host memory) on the host, and
+ * the call returns MPPI_ENONFINITE_INPUT without launching; otherwise on the device by
+ * the lane-split rollout, which then rolls out nothing and leaves
+ * MPPI_WARN_NONFINITE_INPUT for mppi_sync_status. */
 mppi_status mppi_step(mppi_ctx *ctx, const float *d_x0, float *d_u0_out);
 
 /* The second half of mppi_step, for callers that time or overlap the two kernels:
@@ -240,7 +248,9 @@ mppi_status mppi_update_shift(mppi_ctx *ctx, const float *d_costs, float *d_u0_o
  * or a non-zero reserved field. */
 mppi_status mppi_set_tracking_cost(mppi_ctx *ctx, const mppi_tracking_cost *cost);
 
-/* Synchronises the bound stream and returns the status of the last update. */
+/* Synchronises the bound stream and returns the status of the last step: MPPI_OK,
+ * MPPI_WARN_NONFINITE_INPUT, MPPI_WARN_ALL_NONFINITE or MPPI_WARN_FALLBACK (in that order
+ * of precedence). */
 mppi_status mppi_sync_status(mppi_ctx *ctx);
 
 /* One dynamics step for n independent states (the plant of a closed loop):

@@ -238,6 +238,26 @@ mppi_status need_bound(mppi_ctx* c)
     return MPPI_OK;
 }
 
+// a start state the host can read (managed or mapped host memory) is checked on the host;
+// device memory is checked by the lane-split rollout itself
+mppi_status check_host_state(mppi_ctx* c, const float* x0)
+{
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, x0) != hipSuccess) {
+        (void)hipGetLastError();  // unknown to the runtime: leave the check to the device
+        return MPPI_OK;
+    }
+    if (at.type != hipMemoryTypeHost && at.type != hipMemoryTypeManaged && !at.isManaged) return MPPI_OK;
+    const float* hx = at.type == hipMemoryTypeHost && at.hostPointer ? (const float*)at.hostPointer : x0;
+    if (at.type == hipMemoryTypeManaged || at.isManaged) {
+        mppi_status s;
+        if ((s = hip_check(c, hipStreamSynchronize(c->stream), "synchronise before reading the state"))) return s;
+    }
+    for (int i = 0; i < c->model.nx; ++i)
+        if (!std::isfinite(hx[i])) return fail(c, MPPI_ENONFINITE_INPUT, "the start state is not finite");
+    return MPPI_OK;
+}
+
 // the rollout launch of a controller: the lane-split or the quad kernel
 hipError_t launch_roll(const mppi_ctx* c, const mppi::DevParams& P, const mppi::RolloutArgs& a, hipStream_t st)
 {
@@ -280,6 +300,9 @@ const char* mppi_status_str(mppi_status s)
     switch (s) {
     case MPPI_OK: return "ok";
     case MPPI_WARN_ALL_NONFINITE: return "all samples non-finite; nominal kept";
+    case MPPI_WARN_FALLBACK: return "the proposal step fell back to plain MPPI";
+    case MPPI_WARN_NONFINITE_INPUT: return "start state not finite; nothing rolled out, nominal kept";
+    case MPPI_ENONFINITE_INPUT: return "start state not finite";
     case MPPI_EINVAL: return "invalid argument";
     case MPPI_ENOMEM: return "workspace too small";
     case MPPI_EHIP: return "HIP runtime error";
@@ -532,6 +555,7 @@ static mppi_status rollout(mppi_ctx* c, const float* d_x0, const float* d_eps, f
     a.samples_per_block = 16;
     a.direct = c->p.basis == MPPI_BASIS_DIRECT;
     a.skip = d_skip;
+    a.input_status = (int*)wsf(c, c->off_status) + 1;
     mppi_status s;
     if ((s = hip_check(c, launch_roll(c, P, a, c->stream),
                        "rollout launch")) ||
@@ -688,6 +712,7 @@ mppi_status mppi_step(mppi_ctx* c, const float* d_x0, float* d_u0_out)
     mppi_status s;
     if ((s = need_bound(c))) return s;
     if (!d_x0 || !d_u0_out) return fail(c, MPPI_EINVAL, "null state or control buffer");
+    if ((s = check_host_state(c, d_x0))) return s;
     if (c->policy) {
         float* center = wsf(c, c->off_center);
         float* sd = wsf(c, c->off_sd);
@@ -758,12 +783,14 @@ mppi_status mppi_sync_status(mppi_ctx* c)
 {
     mppi_status s;
     if ((s = need_bound(c))) return s;
-    int st = 0;
-    if ((s = hip_check(c, hipMemcpyAsync(&st, wsf(c, c->off_status), sizeof(int), hipMemcpyDeviceToHost, c->stream),
+    int st[3] = {0, 0, 0};  // all non-finite, non-finite start state, proposal fallback
+    if ((s = hip_check(c, hipMemcpyAsync(st, wsf(c, c->off_status), sizeof(st), hipMemcpyDeviceToHost, c->stream),
                        "read status")))
         return s;
     if ((s = hip_check(c, hipStreamSynchronize(c->stream), "synchronise"))) return s;
-    return st ? MPPI_WARN_ALL_NONFINITE : MPPI_OK;
+    if (st[1]) return MPPI_WARN_NONFINITE_INPUT;
+    if (st[0]) return MPPI_WARN_ALL_NONFINITE;
+    return st[2] ? MPPI_WARN_FALLBACK : MPPI_OK;
 }
 
 mppi_status mppi_step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int k_prop,

@@ -254,7 +254,10 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, Update
         }
     }
     if (j == 0 && t == 0) {
-        if (a.status) a.status[0] = none ? 1 : 0;
+        if (a.status) {
+            a.status[0] = none ? 1 : 0;
+            a.status[2] = (a.prop && !prop) ? 1 : 0;
+        }
         if (a.prop && a.pstats) {
             a.pstats[0] += prop ? 1 : 0;
             a.pstats[1] += 1;

@@ -31,6 +31,8 @@ struct RolloutArgs {
     int samples_per_block; // samples per workgroup (4 lanes each)
     int direct;            // lane-split rollout: one value per step (nk == H) instead of the basis
     const int* skip;       // lane-split rollout: device flag; when set the launch does nothing
+    int* input_status;     // lane-split rollout: set to 1 when x0 is not finite (then nothing is
+                           // rolled out and every cost is +inf), to 0 otherwise; or null
 };
 
 struct UpdateArgs {
@@ -43,7 +45,7 @@ struct UpdateArgs {
     float* nominal_out;    // shifted update or null
     float* u0_out;         // first control (12) or null
     float* weights_out;    // K or null
-    int* status;           // 1 if no finite cost
+    int* status;           // [0]: 1 if no finite cost; [2]: 1 if a gated proposal step fell back
     // learned-proposal step (prop = 1): when the gate accepts, the update runs over the
     // proposal's Kp samples instead (costs_p, noise eps_p[n * D + d], centre mu_p, unit
     // scale); the gate accepts when gate is null (ungated) or gate[0] (the centre's cost)

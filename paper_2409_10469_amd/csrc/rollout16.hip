@@ -547,8 +547,8 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
 // ------------------------------------------------------------------------------
 // rollout kernel: workgroup of 64 lanes = 4 samples x 16 lanes.  R: geometry and state
 // type, S: system type (FP32/FP32, FP64/FP64, or FP32 geometry with the FP64 system).
-// LDS: the summation rows [4][kNVMax][kPitch] and sums [4][kSumPitch] (type S), then the
-// heightfield (scene 1).  eps addressing as in the quad kernel: eps_in[n * eps_sn + d *
+// LDS: the summation rows [4][NV][kPitch] (NV summed values of the scene) and sums
+// [4][kSumPitch] (type S), then the heightfield (scene 1).  eps addressing as in the quad kernel: eps_in[n * eps_sn + d *
 // eps_sd] when given, otherwise Philox noise stored to eps_out[d * K + n].
 // ------------------------------------------------------------------------------
 template <int SCENE, typename R, typename S>
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
                                                        const float* __restrict__ eps_in, int eps_sn, int eps_sd,
                                                        float* __restrict__ eps_out, float* __restrict__ costs,
                                                        float* __restrict__ traj, int direct,
-                                                       const int* __restrict__ skip)
+                                                       const int* __restrict__ skip, int* __restrict__ input_status)
 {
     // a plain fallback rollout whose proposal the gate took: nothing to do
     if (skip && skip[0]) return;
@@ -568,8 +568,9 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
     // scalar registers for the kernel's pointers and loop state
     __shared__ ModelT<R> sMr;
     __shared__ ModelT<S> sMs;
+    constexpr int NV = r16::n_summed<SCENE>();
     S* red = reinterpret_cast<S*>(lds_raw);
-    S* sred = red + r16::kSamples * r16::kNVMax * r16::kPitch;
+    S* sred = red + r16::kSamples * NV * r16::kPitch;
     float* sHF = reinterpret_cast<float*>(sred + r16::kSamples * r16::kSumPitch);
     if (threadIdx.x == 0) {
         sMr = Mr;
@@ -612,6 +613,17 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
         }
     }
 
+    // a start state that is not finite: no rollout, every cost +inf, and the flag set
+    {
+        bool bad = false;
+        for (int i = tid; i < P.nx; i += 64) bad |= !(fabsf(x0[i]) <= 3.0e38f);
+        const bool any_bad = __builtin_amdgcn_ballot_w64(bad) != 0;
+        if (input_status && blockIdx.x == 0 && tid == 0) input_status[0] = any_bad ? 1 : 0;
+        if (any_bad) {
+            if (valid && g == 0) costs[n] = __int_as_float(0x7f800000);
+            return;
+        }
+    }
     Base<R> b;
     Leg<R> lg;
     BoxS<R> bx{};
@@ -623,7 +635,7 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
         if (SCENE == 3 && leg == 0) store_box(tr, bx);
     }
 
-    S* my_red = red + grp * r16::kNVMax * r16::kPitch;
+    S* my_red = red + grp * NV * r16::kPitch;
     S* my_sum = sred + grp * r16::kSumPitch;
     const S dt = P.dt, kp = P.kp, kd = P.kd;
     R L = R(0);
@@ -665,7 +677,8 @@ namespace r16 {
 template <typename S>
 size_t lds_bytes(int scene, int hf_cells)
 {
-    size_t b = sizeof(S) * ((size_t)kSamples * kNVMax * kPitch + (size_t)kSamples * kSumPitch);
+    const size_t nv = scene == 3 ? 55 : 28;  // n_summed<scene>()
+    size_t b = sizeof(S) * ((size_t)kSamples * nv * kPitch + (size_t)kSamples * kSumPitch);
     if (scene == 1) b += sizeof(float) * (size_t)hf_cells;
     return b;
 }
@@ -679,7 +692,8 @@ hipError_t launch_t(const ModelT<R>& Mr, const ModelT<S>& Ms, const DevParams& P
     if (lds > 65536) return hipErrorInvalidValue;
 #define MPPI_LAUNCH_R16(SC)                                                                                     \
     hipLaunchKernelGGL((rollout16_kernel<SC, R, S>), dim3(blocks), dim3(64), lds, st, Mr, Ms, P, a.B, a.hf, a.mu, \
-                       a.x0, a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj, a.direct, a.skip)
+                       a.x0, a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj, a.direct, a.skip, \
+                       a.input_status)
     switch (Mr.scene) {
     case 0: MPPI_LAUNCH_R16(0); break;
     case 1: MPPI_LAUNCH_R16(1); break;

@@ -239,7 +239,8 @@ def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="co
     return float(cost.item()), x.cpu().numpy(), acc, n
 
 
-def evaluate(policy, K_plain=(64, 128, 256, 512, 1024, 2048, 4096), K_learned=1024, ratio=4, seeds=range(100, 110),
+def evaluate(policy, K_plain=(64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384), K_learned=1024, ratio=4,
+             seeds=range(100, 110),
              steps=200, v_ref=0.5, arith="fp64", log=print):
     """Plain MPPI at each K against the learned proposal with K_learned / ratio samples
     (K_learned on fallback steps) over the same seeds; episode costs, fallback rate and the

@@ -71,6 +71,26 @@ inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 1.f; return hipSuccess; }
 inline const char* hipGetErrorString(hipError_t) { return "emulation"; }
 hipError_t hipGetLastError();
+// pointer attributes: every buffer here is reported as device memory (the start-state
+// finiteness check then falls to the device code)
+enum hipMemoryType { hipMemoryTypeUnregistered = 0, hipMemoryTypeHost = 1, hipMemoryTypeDevice = 2,
+                     hipMemoryTypeManaged = 3 };
+struct hipPointerAttribute_t {
+    hipMemoryType type;
+    int device;
+    void* devicePointer;
+    void* hostPointer;
+    int isManaged;
+    unsigned allocationFlags;
+};
+inline hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p)
+{
+    *a = hipPointerAttribute_t{};
+    a->type = hipMemoryTypeDevice;
+    a->devicePointer = const_cast<void*>(p);
+    return hipSuccess;
+}
+
 // one emulated device of two compute units (the persistent batch grid is blocks_per_cu x 2)
 enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount };
 inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }

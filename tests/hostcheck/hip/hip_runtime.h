@@ -73,3 +73,23 @@ inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t, void*, void
 inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { capture_replay(); return hipSuccess; }
 inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
+
+// pointer attributes: every buffer here is reported as device memory (the start-state
+// finiteness check then falls to the device code)
+enum hipMemoryType { hipMemoryTypeUnregistered = 0, hipMemoryTypeHost = 1, hipMemoryTypeDevice = 2,
+                     hipMemoryTypeManaged = 3 };
+struct hipPointerAttribute_t {
+    hipMemoryType type;
+    int device;
+    void* devicePointer;
+    void* hostPointer;
+    int isManaged;
+    unsigned allocationFlags;
+};
+inline hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p)
+{
+    *a = hipPointerAttribute_t{};
+    a->type = hipMemoryTypeDevice;
+    a->devicePointer = const_cast<void*>(p);
+    return hipSuccess;
+}

@@ -85,6 +85,7 @@ hipError_t launch_rollout16(const DevModelF& Mf, const DevModelD& Md, int arith,
     if (!rollout16_fits(arith, arith == 1 ? Mf.scene : Md.scene, arith == 1 ? Mf.hf_nx * Mf.hf_ny : Md.hf_nx * Md.hf_ny))
         fail("rollout16 LDS");
     CHK(a.skip, 4, "rollout skip flag");
+    CHK(a.input_status, 4, "rollout start-state flag");
     if (!a.direct) return launch_rollout(Mf, Md, arith, P, a, st);  // same ranges as the quad kernel
     const int D = 12 * P.nk;  // direct: one value per step
     if (P.K < 1 || P.H < 1 || P.nk != P.H) fail("rollout16 direct shape");
@@ -99,7 +100,7 @@ hipError_t launch_rollout16(const DevModelF& Mf, const DevModelD& Md, int arith,
 
 bool rollout16_fits(int arith, int scene, int hf_cells)
 {
-    const size_t rows = (4 * 55 * 20 + 4 * 64) * (arith == 1 ? 4 : 8);
+    const size_t rows = (4 * (scene == 3 ? 55 : 28) * 20 + 4 * 64) * (arith == 1 ? 4 : 8);
     return rows + (scene == 1 ? 4ull * hf_cells : 0) <= 65536;
 }
 
@@ -114,7 +115,7 @@ hipError_t launch_update(const DevParams& P, const UpdateArgs& a, hipStream_t)
     CHK(a.nominal_out, 4ull * D, "update shifted nominal");
     CHK(a.u0_out, 48, "update first control");
     CHK(a.weights_out, 4ull * P.K, "update weights");
-    range_check(a.status, 4, "update status");
+    range_check(a.status, 12, "update status");
     if (a.prop) {
         if (a.Kp < 2 || a.Kp > P.K) fail("proposal sample count");
         range_check(a.costs_p, 4ull * a.Kp, "update proposal costs");

@@ -6,6 +6,7 @@ Tolerances (stated by the method's specification for this build):
   updated knots within 1e-3;
   Philox words bitwise equal.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -225,14 +226,18 @@ def test_closed_loop_prefix_terrain(B):
         ctl.set_nominal(_dev(mu))
 
 
-def test_all_samples_diverge_keeps_nominal(B):
-    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=16)
+@pytest.mark.parametrize("lanes,status", [(4, 1), (16, 3)])
+def test_all_samples_diverge_keeps_nominal(B, lanes, status):
+    """A start state that is not finite: the quad rollout lets every sample diverge
+    (MPPI_WARN_ALL_NONFINITE), the lane-split rollout detects it and rolls out nothing
+    (MPPI_WARN_NONFINITE_INPUT); both keep the shifted nominal."""
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=16, lanes=lanes)
     x0 = f32(W.initial_state(0))
     x0[19] = np.nan
     mu = f32(W.stance_knots(4))
     ctl.set_nominal(_dev(mu))
     u0 = ctl.step(_dev(x0))
-    assert ctl.sync_status() == 1
+    assert ctl.sync_status() == status
     S = O.shift_matrix(4, p["H"], p["dt"])
     np.testing.assert_allclose(ctl.get_nominal().cpu().numpy(), (mu.reshape(12, 4) @ S.T).ravel(), atol=1e-6)
     np.testing.assert_allclose(u0.cpu().numpy(), mu.reshape(12, 4)[:, 0], atol=0)
@@ -449,3 +454,19 @@ def test_closed_loop_resumes_bitwise_from_nominal_and_step(B):
         x = model.sim_step(x[None], u0[None].contiguous(), p["kp"], p["kd"], p["dt"])[0]
         assert np.array_equal(u0.cpu().numpy(), controls[s]), s
         assert np.array_equal(x.cpu().numpy(), states[s]), s
+
+
+def test_host_visible_nonfinite_start_state_is_refused(B):
+    """A start state in pinned host memory is checked on the host: not finite, the step
+    returns MPPI_ENONFINITE_INPUT and launches nothing (the step counter stays).  No
+    kernel is given the host pointer."""
+    md, p, orc, model, ctl = _setup(B, W.FLAT_WALK, K=16)
+    x0 = torch.tensor(W.initial_state(0), dtype=torch.float32).pin_memory()
+    x0[2] = float("inf")
+    ctl.set_nominal(_dev(W.stance_knots(4)))
+    u0 = torch.empty(12, dtype=torch.float32, device="cuda")
+    # the binding passes device tensors only: the host pointer goes through the C ABI itself
+    rc = B.lib().mppi_step(ctl.h, ctypes.c_void_p(x0.data_ptr()), ctypes.c_void_p(u0.data_ptr()))
+    assert rc == -4
+    assert "finite" in B.lib().mppi_last_error(ctl.h).decode()
+    assert ctl.step_counter == 0

@@ -349,7 +349,7 @@ def test_proposal_step_on_plain_kernels_matches_oracle(B, accept, gate, lanes):
                                                          gate={"cost": 0, "none": 1, "best": 2}[gate])
     taken = accept or gate == "none"
     assert oacc == taken and acc == int(taken) and steps == 1
-    assert ctl.sync_status() == 0 and ctl.step_counter == 6
+    assert ctl.sync_status() == (0 if taken else 2) and ctl.step_counter == 6  # 2: MPPI_WARN_FALLBACK
     assert np.abs(u0 - ou0).max() <= KNOT_TOL
     assert np.abs(nom - onom).max() <= KNOT_TOL
 
@@ -451,6 +451,23 @@ def test_trained_proposal_gains_over_plain_and_untrained_at_equal_samples(B):
     c = evb["controllers"]
     assert c["learned_K256"]["episode_cost"] < 0.8 * c["plain_K256"]["episode_cost"], c
     assert c["learned_K256"]["latency_ms"]["p99"] < c["plain_K1024"]["latency_ms"]["p99"], c
+    # with plain MPPI kept as the fallback (best-sample gate, K = 1024 on a fallback):
+    # the K/4 proposal reaches plain MPPI's cost at K with fewer samples rolled out per
+    # step, counting every fallback's K samples
+    lat_p, lat_l = [], []
+    seeds = tuple(range(100, 106))
+    plain_k = [PR.episode(model, dict(p, K=1024), s, steps, lat=lat_p)[0] for s in seeds]
+    res = [PR.episode(model, dict(p, K=1024), s, steps, policy=trained, k_prop=256, gate="best", lat=lat_l)
+           for s in seeds]
+    learned_g = [r[0] for r in res]
+    acc, n = sum(r[2] for r in res), sum(r[3] for r in res)
+    samples = 256 + (1.0 - acc / n) * 1024
+    half = lambda v: 1.96 * np.std(v, ddof=1) / np.sqrt(len(v))
+    print("gated learned %.3f +- %.3f at %.0f samples/step (acceptance %.2f); plain K=1024 %.3f +- %.3f; "
+          "p99 %.3f vs %.3f ms" % (np.mean(learned_g), half(learned_g), samples, acc / n, np.mean(plain_k),
+                                   half(plain_k), np.percentile(lat_l, 99), np.percentile(lat_p, 99)))
+    assert np.mean(learned_g) + half(learned_g) < np.mean(plain_k), (learned_g, plain_k)
+    assert samples < 0.75 * 1024, samples
 
 
 def test_corrupted_proposal_falls_back_to_the_plain_step(B):
