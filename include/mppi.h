@@ -260,6 +260,22 @@ mppi_status mppi_sync_status(mppi_ctx *ctx);
 mppi_status mppi_sim_step(const mppi_model *model, int arith, int n, const float *d_x, const float *d_u, float kp,
                           float kd, float dt, float *d_x_out, float *d_tau_out, const float *d_hf, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): one plain control step, as mppi_step,
+ * of a controller created with mppi_create and NOT bound, with its whole workspace in a
+ * static device array of MPPI_STATIC_SCRATCH_BYTES that the library holds per GPU until
+ * the process ends.  d_nominal (12 * n_knots floats, device) holds the nominal plan on
+ * entry and the shifted plan on return (the scratch keeps nothing the caller needs);
+ * d_u0_out receives the first control; the controller's step counter advances.  The
+ * spline matrices and heightfield are uploaded from host memory on every call.  Calls on
+ * one GPU share its array: calls that overlap in time on one GPU race (serialise them,
+ * e.g. on one stream).  Errors: EINVAL when the controller's workspace
+ * (mppi_workspace_bytes) exceeds the array, it uses the learned proposal or the tracking
+ * cost, or a pointer is null; ESTATE when it is bound; EHIP when the array's address
+ * cannot be looked up.  No device memory is allocated or freed. */
+#define MPPI_STATIC_SCRATCH_BYTES (16u << 20)
+mppi_status mppi_step_static(mppi_ctx *ctx, const float *d_x0, float *d_nominal, float *d_u0_out, void *hip_stream);
+
 const char *mppi_status_str(mppi_status s);
 const char *mppi_last_error(const mppi_ctx *ctx);
 

@@ -87,6 +87,7 @@ def lib():
             "mppi_model_destroy": (None, [vp]),
             "mppi_model_nx": (C.c_int, [vp]),
             "mppi_create": (C.c_int, [vp, C.POINTER(Params), C.POINTER(C.c_void_p)]),
+            "mppi_step_static": (C.c_int, [vp, vp, vp, vp, vp]),
             "mppi_destroy": (None, [vp]),
             "mppi_workspace_bytes": (C.c_size_t, [vp]),
             "mppi_get_basis": (C.c_int, [vp, vp, vp]),
@@ -256,7 +257,7 @@ class Model:
 class Controller:
     """One MPPI instance bound to a torch-allocated device workspace."""
 
-    def __init__(self, model: Model, p: dict, stream=None):
+    def __init__(self, model: Model, p: dict, stream=None, bind=True):
         import torch
         self.model = model
         self.p = dict(p)
@@ -266,6 +267,10 @@ class Controller:
         self.h = h
         self.K, self.H, self.nk = int(p["K"]), int(p["H"]), int(p["nk"])
         self.D = 12 * self.nk
+        self.stream = stream
+        if not bind:  # for mppi_step_static, which needs an unbound controller
+            self.ws = None
+            return
         nbytes = lib().mppi_workspace_bytes(h)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         off = (-self.ws.data_ptr()) % 256
@@ -320,6 +325,15 @@ class Controller:
         w = torch.empty(self.K, dtype=torch.float32, device="cuda") if weights else None
         self._s(lib().mppi_update(self.h, _ptr(costs), _ptr(eps), _ptr(out), _ptr(w)))
         return (out, w) if weights else out
+
+    def step_static(self, x0, nominal, u0=None):
+        """mppi_step_static: one plain control step of an unbound controller in the
+        library's static device scratch; `nominal` (device) is updated in place."""
+        import torch
+        if u0 is None:
+            u0 = torch.empty(12, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_step_static(self.h, _ptr(x0), _ptr(nominal), _ptr(u0), _stream(self.stream)))
+        return u0
 
     def step(self, x0, u0=None):
         import torch

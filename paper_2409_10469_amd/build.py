@@ -13,7 +13,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmppi.so")
 OBJ = os.path.join(PKG, "_build")
 SOURCES = ["mppi_kernels.hip", "rollout16.hip", "mlp_kernels.hip", "proposal_kernels.hip", "tracking_kernels.hip",
-           "mppi_api.cpp", "mppi_batch.cpp", "mppi_policy.cpp"]
+           "mppi_api.cpp", "mppi_batch.cpp", "mppi_policy.cpp",
+           "mppi_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # the lane-split rollout's FP32 arithmetic: division and square root within about 2 ulp
 # (the hardware reciprocal and square-root sequences instead of the correctly rounded

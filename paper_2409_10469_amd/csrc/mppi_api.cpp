@@ -738,6 +738,58 @@ mppi_status mppi_update_shift(mppi_ctx* c, const float* d_costs, float* d_u0_out
     return MPPI_OK;
 }
 
+}  // extern "C"
+
+namespace mppi_host {
+// One plain control step of an unbound controller with its whole workspace placed in the
+// device region [region, region + bytes) (the library's static scratch): the spline
+// matrices and heightfield are uploaded, the nominal is copied in from d_nominal, the
+// step runs as mppi_step does, and the shifted nominal is copied back to d_nominal.  The
+// controller is left unbound.  Nothing is allocated.  Nothing in the region has to start
+// at zero: every buffer the step reads is written earlier in the same step (the status
+// words too, which nothing reads on this path), so the previous call's contents do no harm.
+mppi_status step_in_region(mppi_ctx* c, void* region, size_t bytes, const float* d_x0, float* d_nominal,
+                           float* d_u0_out, hipStream_t st)
+{
+    if (!c) return fail(nullptr, MPPI_EINVAL, "null context");
+    if (!region) return fail(c, MPPI_EHIP, "no device region for the step");
+    if (!d_x0 || !d_nominal || !d_u0_out) return fail(c, MPPI_EINVAL, "null state, nominal or control buffer");
+    if (c->ws) return fail(c, MPPI_ESTATE, "the controller has a bound workspace (use mppi_step)");
+    if (c->policy || c->p.cost != MPPI_COST_RUNNING)
+        return fail(c, MPPI_EINVAL, "the static step runs the plain method with the running cost");
+    if (c->total > bytes)
+        return fail(c, MPPI_EINVAL, "the controller's workspace (" + std::to_string(c->total) +
+                                        " bytes) exceeds the static scratch (" + std::to_string(bytes) + " bytes)");
+    c->ws = region;
+    c->ws_bytes = bytes;
+    c->stream = st;
+    mppi_status s;
+    float* mu = wsf(c, c->off_mu);
+    float* costs = wsf(c, c->off_costs);
+    if (!(s = hip_check(c, hipMemcpyAsync(wsf(c, c->off_B), c->B.data(), sizeof(double) * c->B.size(),
+                                          hipMemcpyHostToDevice, st), "upload spline basis")) &&
+        !(s = hip_check(c, hipMemcpyAsync(wsf(c, c->off_S), c->S.data(), sizeof(float) * c->S.size(),
+                                          hipMemcpyHostToDevice, st), "upload shift matrix")) &&
+        !(s = c->model.hf.empty() ? MPPI_OK
+                                  : hip_check(c, hipMemcpyAsync(wsf(c, c->off_hf), c->model.hf.data(),
+                                                                sizeof(float) * c->model.hf.size(),
+                                                                hipMemcpyHostToDevice, st), "upload heightfield")) &&
+        !(s = hip_check(c, hipMemcpyAsync(mu, d_nominal, sizeof(float) * c->D, hipMemcpyDeviceToDevice, st),
+                        "copy nominal in")) &&
+        !(s = rollout(c, d_x0, nullptr, costs, nullptr)) &&
+        !(s = update(c, costs, nullptr, nullptr, mu, d_u0_out, nullptr)) &&
+        !(s = hip_check(c, hipMemcpyAsync(d_nominal, mu, sizeof(float) * c->D, hipMemcpyDeviceToDevice, st),
+                        "copy nominal out")))
+        c->step += 1;
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->stream = nullptr;
+    return s;
+}
+}  // namespace mppi_host
+
+extern "C" {
+
 mppi_status mppi_set_tracking_cost(mppi_ctx* c, const mppi_tracking_cost* t)
 {
     if (!c || !t) return fail(c, MPPI_EINVAL, "null argument");

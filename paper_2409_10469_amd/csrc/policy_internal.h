@@ -20,4 +20,8 @@ mppi_status policy_out_norm(mppi_policy* p, const float** omean, const float** o
 void policy_resample_table(float* rtab);
 // value at t of the not-a-knot spline through nk knots on [0, T] with knot k = 1, others 0
 double spline_basis_at(int nk, double T, int k, double t);
+// one plain control step of an unbound controller with its workspace in a given device
+// region (the static scratch of mppi_step_static); see mppi_api.cpp
+mppi_status step_in_region(mppi_ctx* c, void* region, size_t bytes, const float* d_x0, float* d_nominal,
+                           float* d_u0_out, hipStream_t st);
 }  // namespace mppi_host
