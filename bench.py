@@ -39,6 +39,7 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("mppi_device.h", "mppi_kernels.hip", "rollout16.hip"):
         h.update(open(os.path.join(ROOT, "paper_2409_10469_amd", "csrc", f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2409_10469_amd", "build.py"), "rb").read())  # compile flags
     return h.hexdigest()[:16]
 
 
