@@ -47,6 +47,16 @@ def _kernel_tag(lanes: int) -> str:
     return "rollout16" if lanes == 16 else "rollout"
 
 
+def _kernel_name(scene: int, arith: str, lanes: int) -> str:
+    r = "double" if arith == "fp64" else "float"
+    s = "float" if arith == "fp32" else "double"
+    return f"rollout16_kernel<{scene}, {r}, {s}>" if lanes == 16 else f"rollout_kernel<{scene}, {r}>"
+
+
+def _dtype(arith: str) -> str:
+    return {"fp64": "f64", "fp32": "f32", "mixed": "f32+f64"}[arith]
+
+
 def traffic_from_profile(workload: str, arith: str, lanes: int = 16):
     """Counter-measured HBM bytes per rollout launch, if the committed counter summary
     was taken on the current kernel source."""
@@ -147,7 +157,9 @@ def main():
     ap.add_argument("--workload", default="box_push",
                     help="box_push (default), heightfield_walk, flat_walk, box_climb, batched_serving, "
                          "proposal_training, ablations or tracking")
-    ap.add_argument("--arith", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--arith", default="fp32", choices=["fp64", "fp32", "mixed"],
+                    help="step arithmetic: fp64, fp32, or mixed (FP32 geometry, FP64 implicit system; lane-split "
+                         "kernel, single-controller workloads)")
     ap.add_argument("--lanes", type=int, default=16, choices=[4, 16],
                     help="rollout kernel: 16 lanes per sample (lane-split, default) or 4 (one lane per leg)")
     ap.add_argument("--no-learned", action="store_true",
@@ -181,6 +193,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.arith == "mixed" and args.workload in ("batched_serving", "proposal_training", "tracking"):
+        print(json.dumps({"error": "mixed arithmetic runs in single controllers only (the lane-split rollout)"}))
+        sys.exit(2)
     if args.workload == "batched_serving":
         return bench_serving(args)
     if args.workload == "proposal_training":
@@ -261,7 +276,8 @@ def main():
     value = K * H * args.steps / elapsed
     flops = flops_per_rollout_step(wl["scene"], nk) * K * H
     achieved = flops / (roll_ms.mean() * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.arith]
+    # mixed arithmetic is priced against the FP32 peak, the higher of the two it uses
+    peak = PEAK_TFLOPS["fp32" if args.arith == "mixed" else args.arith]
     out = {
         "metric": "rollout-steps/sec + p99 MPPI step latency; learned-proposal vs plain at equal cost",
         "value": value,
@@ -273,7 +289,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.arith == "fp64" else "f32",
+        "dtype": _dtype(args.arith),
         "data": "synthetic",
         "config": {"workload": wl["name"], "K": K, "H": H, "dt": p["dt"], "n_knots": nk,
                    "scene": SCENE_NAMES[wl["scene"]], "closed_loop": True, "state": "f32",
@@ -285,8 +301,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic_from_profile(wl["name"], args.arith, args.lanes),
                      "flops_per_rollout_step": flops_per_rollout_step(wl["scene"], nk),
-                     "kernel": f"{_kernel_tag(args.lanes)}_kernel<{wl['scene']}, "
-                               f"{'float' if args.arith == 'fp32' else 'double'}>"},
+                     "kernel": _kernel_name(wl["scene"], args.arith, args.lanes)},
         "counter_flops": counter_rate(counter_flops_from_profile(wl["name"], args.arith, args.lanes), roll_ms.mean(),
                                       peak),
         "hbm_gbs": hbm_rate(traffic_from_profile(wl["name"], args.arith, args.lanes), roll_ms.mean()),
@@ -356,7 +371,7 @@ def bench_serving(args):
         "metric": "rollout-steps/sec + p99 MPPI step latency",
         "value": value, "unit": "rollout-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["elapsed"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.arith == "fp64" else "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": _dtype(args.arith), "data": "synthetic",
         "config": {"workload": "batched_serving", "target_instances": 256, "K": "log-uniform [256, 4096]",
                    "H": "uniform [20, 80]", "tasks": "flat, heightfield, box climb, box push",
                    "arrivals": "Poisson, lifetime 200 steps", "hbm_budget_mib": 64, "state": "f32",
@@ -485,7 +500,7 @@ def bench_ablation(args):
     out = {"metric": "closed-loop episode cost of the plain method's ablations", "value": walk["cubic"]["mean"],
            "unit": "episode cost (heightfield walk, cubic)", "n_gpus": 1, "steps": args.eval_steps,
            "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if args.arith == "fp64" else "f32", "data": "synthetic",
+           "dtype": _dtype(args.arith), "data": "synthetic",
            "config": {"workload": "ablations", "seeds": [args.seed, args.seed + args.eval_seeds - 1],
                       "episode_steps": args.eval_steps},
            "tasks": res, "sweeps": sweeps, "seconds": time.perf_counter() - t0}
@@ -534,7 +549,7 @@ def bench_tracking(args):
     out = {"metric": "closed-loop forward-velocity error with the Eq. 3 trotting reference (heightfield)",
            "value": trot["v_err"], "unit": "m/s", "n_gpus": 1, "steps": 300, "warmup": 0,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if args.arith == "fp64" else "f32", "data": "synthetic",
+           "dtype": _dtype(args.arith), "data": "synthetic",
            "config": {"workload": "tracking", "seeds": [args.seed, args.seed + args.eval_seeds - 1],
                       "walk_steps": 300, "push_steps": 400, "controller": "K 1024, H 50, dt 0.01, 6 knots (walk); "
                       "K 4096, H 60, 8 knots (push)"},
