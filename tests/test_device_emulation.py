@@ -56,7 +56,8 @@ def _build(tmp, cxx, cc, san, extra=()):
     def run(job):
         return subprocess.run(job[0], capture_output=True, text=True)
 
-    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+    # three builds run at once (see `runs`), so each takes a third of the cores
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1) // 3)) as ex:
         results = list(ex.map(run, jobs))
     for r, (cmd, src) in zip(results, jobs):
         assert r.returncode == 0, (src, r.stderr[-3000:])
@@ -79,26 +80,55 @@ def _run(exe, mode, env, extra=()):
     return r.stdout
 
 
-def test_kernels_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+def _asan(tmp):
     if shutil.which("g++") is None:
-        pytest.skip("g++ is not available")
-    exe = _build(str(tmp_path), "g++", "gcc", "address,undefined", ["-fno-sanitize-recover=undefined"])
+        return "g++ is not available"
+    exe = _build(tmp, "g++", "gcc", "address,undefined", ["-fno-sanitize-recover=undefined"])
     out = _run(exe, None, {"ASAN_OPTIONS": "detect_leaks=1", "UBSAN_OPTIONS": "print_stacktrace=1"})
     assert out.count(" ok") >= 13
 
 
-def test_kernels_under_memory_sanitizer(tmp_path):
+def _msan(tmp):
     if not os.path.exists(CLANG):
-        pytest.skip("clang is not available")
-    exe = _build(str(tmp_path), CLANG, CLANG_C, "memory", ["-fsanitize-memory-track-origins"])
+        return "clang is not available"
+    exe = _build(tmp, CLANG, CLANG_C, "memory", ["-fsanitize-memory-track-origins"])
     # without the batch case: its runtime's std::map rebalances inside the uninstrumented
     # C++ library, which MemorySanitizer cannot follow (the batch kernels run under the
     # address and thread sanitizers)
     _run(exe, "quick", {}, ["no-batch"])
 
 
-def test_kernels_under_thread_sanitizer(tmp_path):
+def _tsan(tmp):
     if shutil.which("g++") is None:
-        pytest.skip("g++ is not available")
-    exe = _build(str(tmp_path), "g++", "gcc", "thread")
+        return "g++ is not available"
+    exe = _build(tmp, "g++", "gcc", "thread")
     _run(exe, "quick", {"TSAN_OPTIONS": "halt_on_error=1"})
+
+
+@pytest.fixture(scope="module")
+def runs(tmp_path_factory):
+    """The three sanitizer builds and runs, started together (each is a separate process
+    tree), so the module takes about as long as the slowest of them."""
+    ex = ThreadPoolExecutor(max_workers=3)
+    futs = {name: ex.submit(fn, str(tmp_path_factory.mktemp(name))) for name, fn in
+            (("asan", _asan), ("msan", _msan), ("tsan", _tsan))}
+    yield futs
+    ex.shutdown(wait=True)
+
+
+def _outcome(fut):
+    skip = fut.result()  # re-raises the run's assertion
+    if skip:
+        pytest.skip(skip)
+
+
+def test_kernels_under_address_and_undefined_behaviour_sanitizers(runs):
+    _outcome(runs["asan"])
+
+
+def test_kernels_under_memory_sanitizer(runs):
+    _outcome(runs["msan"])
+
+
+def test_kernels_under_thread_sanitizer(runs):
+    _outcome(runs["tsan"])
