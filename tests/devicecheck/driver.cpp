@@ -98,7 +98,8 @@ static void params(int K, int H, int nk, float dt, mppi_params& p, orc_params& o
 }
 
 // standing pose with small deterministic joint offsets (and the box 1 m ahead)
-static std::vector<float> start_state(int nx, int seed)
+// free box at box_x ahead (1 m: away from the feet; 0.4 m: against the front feet)
+static std::vector<float> start_state(int nx, int seed, float box_x = 1.f)
 {
     std::vector<float> x(nx, 0.f);
     x[2] = 0.2835f; x[3] = 1.f;
@@ -111,7 +112,7 @@ static std::vector<float> start_state(int nx, int seed)
         }
     }
     if (nx == 50) {
-        x[37] = 1.f; x[39] = 0.15f - 2.f * 9.81f / 8e4f; x[40] = 1.f;
+        x[37] = box_x; x[39] = 0.15f - 2.f * 9.81f / 8e4f; x[40] = 1.f;
     }
     return x;
 }
@@ -181,7 +182,7 @@ static void steps_case(const char* name, int scene, int K, int H, int nk, float 
 
 // 10-step rollouts with caller noise and trajectories, and with Philox noise and
 // trajectories, against the oracle's rollouts
-static void rollout_case(int scene, int K, int nk)
+static void rollout_case(int scene, int K, int nk, float box_x = 1.f)
 {
     mppi_model_desc d; orc_model o; std::vector<float> hf; std::vector<double> hfd;
     fill(scene, d, o, hf, hfd);
@@ -192,7 +193,7 @@ static void rollout_case(int scene, int K, int nk)
     mppi_ctx* c = controller(m, p);
     const int nx = mppi_model_nx(m), D = 12 * nk;
     float *x = dev(nx), *mu = dev(D), *eps = dev((size_t)K * D), *costs = dev(K), *traj = dev((size_t)K * 11 * nx);
-    std::vector<float> xs = start_state(nx, 7), ms = stance_knots(nk, 7);
+    std::vector<float> xs = start_state(nx, 7, box_x), ms = stance_knots(nk, 7);
     std::memcpy(x, xs.data(), 4 * nx);
     std::memcpy(mu, ms.data(), 4 * D);
     must("set nominal", mppi_set_nominal(c, mu));
@@ -210,7 +211,8 @@ static void rollout_case(int scene, int K, int nk)
         double e = 0;
         for (int n = 0; n < K; ++n) e = std::fmax(e, std::fabs(costs[n] - oc[n]) / std::fabs(oc[n]));
         char what[128];
-        std::snprintf(what, sizeof what, "scene %d rollout, %s noise, 10-step costs", scene, given ? "caller" : "Philox");
+        std::snprintf(what, sizeof what, "scene %d rollout%s, %s noise, 10-step costs", scene,
+                      box_x < 0.5f ? " (feet on the box)" : "", given ? "caller" : "Philox");
         check(what, e, 1e-4);
     }
     mppi_destroy(c);
@@ -388,6 +390,7 @@ int main(int argc, char** argv)
     steps_case("split flat K=64 H=25", MPPI_SCENE_FLAT, 64, 25, 4, 0.02f, 1);
     rollout_case(MPPI_SCENE_FLAT, 21, 4);
     rollout_case(MPPI_SCENE_FREE_BOX, 9, 8);  // the contact passes read only what the tests wrote
+    rollout_case(MPPI_SCENE_FREE_BOX, 9, 8, 0.4f);  // front feet on the ground and against the box
     if (!quick) {
         steps_case("split heightfield K=16 H=12", MPPI_SCENE_HEIGHTFIELD, 16, 12, 6, 0.01f, 1);
         steps_case("split free box K=18 H=10", MPPI_SCENE_FREE_BOX, 18, 10, 8, 0.01f, 1);
