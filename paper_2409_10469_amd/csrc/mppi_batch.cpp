@@ -141,6 +141,11 @@ struct mppi_batch {
     bool rtab_ready = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // what the graph's proposal launches were captured with: their row count and the
+    // policy's workspace (a change of either makes the graph stale)
+    int cap_n_prop = 0;
+    const mppi_policy* cap_policy = nullptr;
+    const void* cap_policy_ws = nullptr;
     std::string err;
 };
 
@@ -178,6 +183,9 @@ void drop_graph(mppi_batch* b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+    b->cap_n_prop = 0;
+    b->cap_policy = nullptr;
+    b->cap_policy_ws = nullptr;
 }
 
 size_t batch_lds(const mppi_batch* b)
@@ -294,6 +302,27 @@ mppi_status upload_table(mppi_batch* b)
     return MPPI_OK;
 }
 
+// learned-proposal instances: features, one forward over all of them, head and noise
+mppi_status proposal_prestep(mppi_batch* b, hipStream_t st)
+{
+    mppi_status s;
+    const auto* table = (const mppi::InstDesc*)wsp(b, b->o_table);
+    const auto* rows = (const prop::BatchPropRow*)wsp(b, b->o_prows);
+    float* feat = (float*)wsp(b, b->o_feat);
+    float* out = (float*)wsp(b, b->o_pout);
+    if ((s = bhip(b, prop::launch_batch_features(b->n_prop, table, rows, feat, st), "proposal features launch")))
+        return s;
+    if (mppi_host::policy_forward_rows(b->policy, feat, b->n_prop, out, st) != MPPI_OK)
+        return bfail(b, MPPI_EINVAL, std::string("proposal forward: ") + mppi_host::policy_error(b->policy));
+    const float *omean, *ostd;
+    if (mppi_host::policy_out_norm(b->policy, &omean, &ostd) != MPPI_OK)
+        return bfail(b, MPPI_ESTATE, std::string("proposal: ") + mppi_host::policy_error(b->policy));
+    return bhip(b, prop::launch_batch_head_noise(b->n_prop, table, rows, out, omean, ostd,
+                                                 (const float*)wsp(b, b->o_rtab), std::log(0.02f), st),
+                "proposal head launch");
+}
+
+
 // one persistent kernel per scene in use, in one graph
 mppi_status capture(mppi_batch* b)
 {
@@ -310,10 +339,12 @@ mppi_status capture(mppi_batch* b)
         return s;
     hipStream_t st = b->cap_stream;
     if ((s = bhip(b, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture"))) return s;
-    // the scenes' kernels run one after another in the graph, or one kernel takes the
-    // combined queue of every scene's tiles
+    // the learned-proposal instances' features, network pass and head come first; then the
+    // scenes' kernels run one after another, or one kernel takes the combined queue of
+    // every scene's tiles
+    const mppi_status ps = b->n_prop ? proposal_prestep(b, st) : MPPI_OK;
     hipError_t le = hipSuccess;
-    if (b->mode == 1) {
+    if (b->mode == 1 && !ps) {
         const int q = 4;
         if (b->arith == 1) {
             mppi::BatchArgs<float> a{(const mppi::InstDesc*)wsp(b, b->o_table),
@@ -329,7 +360,7 @@ mppi_status capture(mppi_batch* b)
             le = mppi::launch_batch_all(0, &a, b->grid, lds, st);
         }
     }
-    for (int sc = 0; sc < 4 && le == hipSuccess && b->mode == 0; ++sc) {
+    for (int sc = 0; sc < 4 && !ps && le == hipSuccess && b->mode == 0; ++sc) {
         if (!b->scene_used[sc]) continue;
         hipStream_t ss = st;
         if (b->arith == 1) {
@@ -348,31 +379,18 @@ mppi_status capture(mppi_batch* b)
     }
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(st, &g);
-    if ((s = bhip(b, le, "batch launch"))) return s;
-    if ((s = bhip(b, ee, "end capture"))) return s;
+    if (ps || le != hipSuccess || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (ps) return ps;
+        if ((s = bhip(b, le, "batch launch"))) return s;
+        return bhip(b, ee, "end capture");
+    }
     b->graph = g;
-    return bhip(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "instantiate graph");
-}
-
-// learned-proposal instances: features, one forward over all of them, head and noise
-mppi_status proposal_prestep(mppi_batch* b)
-{
-    mppi_status s;
-    hipStream_t st = b->stream;
-    const auto* table = (const mppi::InstDesc*)wsp(b, b->o_table);
-    const auto* rows = (const prop::BatchPropRow*)wsp(b, b->o_prows);
-    float* feat = (float*)wsp(b, b->o_feat);
-    float* out = (float*)wsp(b, b->o_pout);
-    if ((s = bhip(b, prop::launch_batch_features(b->n_prop, table, rows, feat, st), "proposal features launch")))
-        return s;
-    if (mppi_host::policy_forward_rows(b->policy, feat, b->n_prop, out, st) != MPPI_OK)
-        return bfail(b, MPPI_EINVAL, std::string("proposal forward: ") + mppi_host::policy_error(b->policy));
-    const float *omean, *ostd;
-    if (mppi_host::policy_out_norm(b->policy, &omean, &ostd) != MPPI_OK)
-        return bfail(b, MPPI_ESTATE, std::string("proposal: ") + mppi_host::policy_error(b->policy));
-    return bhip(b, prop::launch_batch_head_noise(b->n_prop, table, rows, out, omean, ostd,
-                                                 (const float*)wsp(b, b->o_rtab), std::log(0.02f), st),
-                "proposal head launch");
+    if ((s = bhip(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "instantiate graph"))) return s;
+    b->cap_n_prop = b->n_prop;
+    b->cap_policy = b->n_prop ? b->policy : nullptr;
+    b->cap_policy_ws = b->n_prop ? mppi_host::policy_workspace(b->policy) : nullptr;
+    return MPPI_OK;
 }
 
 }  // namespace
@@ -638,8 +656,13 @@ mppi_status mppi_batch_step(mppi_batch* b)
     mppi_status s;
     if (b->dirty && (s = upload_table(b))) return s;
     if (b->total_tiles == 0) return MPPI_OK;
+    // the graph holds the proposal launches for the row count and policy workspace it was
+    // captured with
+    if (b->exec && (b->n_prop != b->cap_n_prop ||
+                    (b->n_prop && (b->policy != b->cap_policy ||
+                                   mppi_host::policy_workspace(b->policy) != b->cap_policy_ws))))
+        drop_graph(b);
     if (!b->exec && (s = capture(b))) return s;
-    if (b->n_prop && (s = proposal_prestep(b))) return s;
     return bhip(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
 }
 

@@ -343,6 +343,8 @@ mppi_status policy_forward_rows(mppi_policy* p, const float* d_in, int B, float*
     return forward(p, d_in, nullptr, B, d_out, false, st);
 }
 
+const void* policy_workspace(const mppi_policy* p) { return p ? p->ws : nullptr; }
+
 // device pointers of the output standardisation (mean and std of the 72 means)
 mppi_status policy_out_norm(mppi_policy* p, const float** omean, const float** ostd)
 {

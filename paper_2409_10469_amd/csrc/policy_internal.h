@@ -14,6 +14,9 @@ mppi_status policy_infer(mppi_policy* p, const float* d_x, const float* d_cmd_or
 const char* policy_error(const mppi_policy* p);
 // output rows (B x 144) of raw feature rows (B x 40), B <= max_batch, on stream st
 mppi_status policy_forward_rows(mppi_policy* p, const float* d_in, int B, float* d_out, hipStream_t st);
+// the bound workspace (null when unbound): a graph that captured the policy's launches
+// is stale once it changes
+const void* policy_workspace(const mppi_policy* p);
 // device pointers of the output standardisation: mean and std of the 72 knot means
 mppi_status policy_out_norm(mppi_policy* p, const float** omean, const float** ostd);
 // the head's knot-resampling matrices for every knot count, rtab[nk][i][k] (9 x 8 x 6)

@@ -204,9 +204,21 @@ hipError_t launch_batch_all(int, const void* args, int grid, size_t lds, hipStre
 }
 }  // namespace mppi
 
-void capture_begin() { mppi::g_captured.clear(); }
+namespace prop {
+struct CapturedFeatures;
+struct CapturedHead;
+void clear_captured();
+void replay_captured();
+}  // namespace prop
+
+void capture_begin()
+{
+    mppi::g_captured.clear();
+    prop::clear_captured();
+}
 void capture_replay()
 {
+    prop::replay_captured();
     for (const auto& c : mppi::g_captured) mppi::check_batch(c.scene, c.a);
 }
 
@@ -238,8 +250,25 @@ hipError_t launch_features(const float* x, const float* co, float* f, hipStream_
     return hipSuccess;
 }
 
-hipError_t launch_batch_features(int np, const mppi::InstDesc* table, const BatchPropRow* rows, float* feat,
-                                 hipStream_t)
+// the batched proposal's launches are captured into the batch graph: each is checked when
+// issued and again at every graph launch (capture_replay), against the live table
+struct CapturedFeatures {
+    int np;
+    const mppi::InstDesc* table;
+    const BatchPropRow* rows;
+    float* feat;
+};
+struct CapturedHead {
+    int np;
+    const mppi::InstDesc* table;
+    const BatchPropRow* rows;
+    const float *out, *omean, *ostd, *rtab;
+    float log_lo;
+};
+std::vector<CapturedFeatures> g_cap_features;
+std::vector<CapturedHead> g_cap_head;
+
+hipError_t check_batch_features(int np, const mppi::InstDesc* table, const BatchPropRow* rows, float* feat)
 {
     range_check(rows, sizeof(BatchPropRow) * np, "proposal rows");
     range_check(feat, 160ull * np, "batch features");
@@ -252,8 +281,15 @@ hipError_t launch_batch_features(int np, const mppi::InstDesc* table, const Batc
     return hipSuccess;
 }
 
-hipError_t launch_batch_head_noise(int np, const mppi::InstDesc* table, const BatchPropRow* rows, const float* out,
-                                   const float* omean, const float* ostd, const float* rtab, float, hipStream_t)
+hipError_t launch_batch_features(int np, const mppi::InstDesc* table, const BatchPropRow* rows, float* feat,
+                                 hipStream_t)
+{
+    g_cap_features.push_back({np, table, rows, feat});
+    return check_batch_features(np, table, rows, feat);
+}
+
+hipError_t check_batch_head_noise(int np, const mppi::InstDesc* table, const BatchPropRow* rows, const float* out,
+                                  const float* omean, const float* ostd, const float* rtab)
 {
     range_check(out, 576ull * np, "proposal network outputs");
     range_check(omean, 4 * 72, "output mean");
@@ -275,6 +311,25 @@ hipError_t launch_batch_head_noise(int np, const mppi::InstDesc* table, const Ba
         if (!std::isfinite(pr.log_hi)) fail("proposal std clamp");
     }
     return hipSuccess;
+}
+
+hipError_t launch_batch_head_noise(int np, const mppi::InstDesc* table, const BatchPropRow* rows, const float* out,
+                                   const float* omean, const float* ostd, const float* rtab, float log_lo,
+                                   hipStream_t)
+{
+    g_cap_head.push_back({np, table, rows, out, omean, ostd, rtab, log_lo});
+    return check_batch_head_noise(np, table, rows, out, omean, ostd, rtab);
+}
+
+void clear_captured()
+{
+    g_cap_features.clear();
+    g_cap_head.clear();
+}
+void replay_captured()
+{
+    for (const auto& c : g_cap_features) check_batch_features(c.np, c.table, c.rows, c.feat);
+    for (const auto& c : g_cap_head) check_batch_head_noise(c.np, c.table, c.rows, c.out, c.omean, c.ostd, c.rtab);
 }
 }  // namespace prop
 

@@ -3,6 +3,9 @@ the policy (ungated) against the single-instance controller with the same policy
 gate, and against the oracle's chain (features, BF16-operand forward, head, proposal
 step, plant step).
 
+The batch step, proposal launches included, is one captured graph: the test replays it
+four times and checks every replay.
+
 Tolerances: against the controller 1e-5 absolute on the first control and the nominal
 and STEP_TOL on the plant state (the same kernels up to the rollout's launch shape);
 against the oracle KNOT_TOL and STEP_TOL, as for the plain batch.
@@ -69,7 +72,14 @@ def test_batched_proposal_matches_controller_and_oracle(B, mode):
             batch.set_proposal(i, pol, cmd=cmd, origin=origin)
         ids.append(i)
         refs.append([wl, p, cmd, origin, x0, mu])
-    for step in range(2):
+    # four graph replays, with eager controller steps and synchronisations between them;
+    # before the third the policy's weights change in place, which the captured network
+    # pass must pick up (it reads the weights, it did not copy them)
+    for step in range(4):
+        if step == 2:
+            P = pol.get_params()
+            pol.set_params(P * 1.01 + 1e-3)
+            torch.cuda.synchronize()
         batch.step()
         torch.cuda.synchronize()
         for i, ref in zip(ids, refs):
