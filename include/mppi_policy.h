@@ -82,6 +82,12 @@ mppi_status mppi_policy_forward(mppi_policy *pol, const float *d_in, int B, floa
  * and an index outside the caller's rows makes the kernels read outside those buffers. */
 mppi_status mppi_policy_grad(mppi_policy *pol, const float *d_in, const float *d_target, const int *d_index, int B,
                              float *d_grad, float *d_loss);
+/* The loss alone (the held-out negative log-likelihood): d_loss receives one float, the
+ * loss mppi_policy_grad would report for the same rows, bit for bit (same forward pass,
+ * loss kernel and summation order); nothing is trained.  Same index rule as
+ * mppi_policy_grad; d_loss must not be NULL. */
+mppi_status mppi_policy_nll(mppi_policy *pol, const float *d_in, const float *d_target, const int *d_index, int B,
+                            float *d_loss);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; Kingma and Ba) with
  * the given gradient (n_params floats, device) and learning rate. */
 mppi_status mppi_policy_adam(mppi_policy *pol, const float *d_grad, float lr);
@@ -102,6 +108,24 @@ mppi_status mppi_policy_save(mppi_policy *pol, const char *path);
 mppi_status mppi_policy_head(mppi_policy *pol, const float *d_out, int n_knots, float sigma_max, float *d_center,
                              float *d_sd);
 const char *mppi_policy_last_error(const mppi_policy *pol);
+
+/* ---- training data ----------------------------------------------------------------
+ * Training pairs from closed-loop records (the rows mppi_batch_record writes, all of one
+ * knot count), on the given stream; needs no policy.  d_records holds n_rec records of
+ * steps rows, record r at d_records + r * steps * (37 + 12 * n_knots): the state, then
+ * the unshifted knots (joint-major).  A record's pairs are its rows before the first row
+ * with a non-finite value or a base height (state index 2) not above fall_z; d_count[r]
+ * receives their number.  Row k < d_count[r] of record r gives, at index r * steps + k,
+ *   d_feat (x 40): the raw features above -- the state with base x, y taken relative to
+ *     the record's origin -- and the command (v, 0, 0);
+ *   d_target (x 72): the knots resampled to 6 per joint at the same fractions of the
+ *     horizon (the not-a-knot spline through the record's n_knots knots; the identity
+ *     for 6), joint-major.
+ * Later rows of d_feat and d_target are not written.  d_origin_cmd: n_rec x 3 floats
+ * (origin x, origin y, v).  2 <= n_knots <= 8.  Errors: EINVAL (sizes, null buffers, a
+ * non-finite fall_z; mppi_policy_last_error(NULL) says which), EHIP. */
+mppi_status mppi_policy_pairs(int n_rec, int steps, int n_knots, const float *d_records, const float *d_origin_cmd,
+                              float fall_z, float *d_feat, float *d_target, int *d_count, void *hip_stream);
 
 /* ---- controller side -------------------------------------------------------------
  * One control step with an explicit proposal (mean d_center, std d_sd; 12 * n_knots

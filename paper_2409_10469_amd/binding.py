@@ -121,6 +121,8 @@ def lib():
             "mppi_policy_set_params": (C.c_int, [vp, fp]),
             "mppi_policy_forward": (C.c_int, [vp, fp, C.c_int, fp]),
             "mppi_policy_grad": (C.c_int, [vp, fp, fp, vp, C.c_int, fp, fp]),
+            "mppi_policy_nll": (C.c_int, [vp, fp, fp, vp, C.c_int, fp]),
+            "mppi_policy_pairs": (C.c_int, [C.c_int, C.c_int, C.c_int, fp, fp, C.c_float, fp, fp, vp, vp]),
             "mppi_policy_adam": (C.c_int, [vp, fp, C.c_float]),
             "mppi_policy_train_step": (C.c_int, [vp, fp, fp, vp, C.c_int, C.c_float, fp]),
             "mppi_policy_steps": (C.c_int, [vp]),
@@ -388,6 +390,24 @@ class Controller:
 N_POLICY_PARAMS = 882832
 
 
+def policy_pairs(records, origin_cmd, n_knots, fall_z, stream=None):
+    """mppi_policy_pairs: training pairs of closed-loop records (device tensor
+    n_rec x steps x (37 + 12 n_knots)) with origins and commands (n_rec x 3).  Returns
+    features (n_rec x steps x 40), targets (n_rec x steps x 72) and the pair count of each
+    record (device tensors; rows past a record's count are not written)."""
+    import torch
+    n_rec, steps, w = records.shape
+    assert w == 37 + 12 * n_knots and tuple(origin_cmd.shape) == (n_rec, 3)
+    feat = torch.empty((n_rec, steps, 40), dtype=torch.float32, device="cuda")
+    tgt = torch.empty((n_rec, steps, 72), dtype=torch.float32, device="cuda")
+    count = torch.empty(n_rec, dtype=torch.int32, device="cuda")
+    status = lib().mppi_policy_pairs(n_rec, steps, n_knots, _ptr(records), _ptr(origin_cmd), float(fall_z),
+                                     _ptr(feat), _ptr(tgt), _ptr(count), _stream(stream))
+    if status < 0:
+        raise MppiError(status, lib().mppi_policy_last_error(None).decode())
+    return feat, tgt, count
+
+
 class Policy:
     """Learned proposal network (include/mppi_policy.h) on a torch-allocated workspace."""
 
@@ -450,6 +470,16 @@ class Policy:
         loss = torch.empty(1, dtype=torch.float32, device="cuda")
         self._s(lib().mppi_policy_grad(self.h, _ptr(X), _ptr(Y), _ptr(index), B, _ptr(G), _ptr(loss)))
         return loss, G
+
+    def nll(self, X, Y, index=None, B=None):
+        """The loss alone (mppi_policy_nll) over rows index[:B] of X and Y (as grad): a
+        device tensor of one float."""
+        import torch
+        assert index is None or index.dtype == torch.int32
+        B = int(B if B is not None else (index.shape[0] if index is not None else X.shape[0]))
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        self._s(lib().mppi_policy_nll(self.h, _ptr(X), _ptr(Y), _ptr(index), B, _ptr(loss)))
+        return loss
 
     def adam(self, G, lr):
         self._s(lib().mppi_policy_adam(self.h, _ptr(G), float(lr)))

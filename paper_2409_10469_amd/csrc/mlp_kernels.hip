@@ -563,4 +563,76 @@ hipError_t launch_head(const HeadArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void loss_sum_kernel(const float* __restrict__ lpart, int nl, float lscale,
+                                                      float* __restrict__ loss)
+{
+    __shared__ float sl[64];
+    const int t = threadIdx.x;
+    float s = 0.f;
+    for (int k = t; k < nl; k += 64) s += lpart[k];
+    sl[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        float tot = 0.f;
+        for (int k = 0; k < 64; ++k) tot += sl[k];
+        loss[0] = tot * lscale;
+    }
+}
+
+hipError_t launch_loss_sum(const float* lpart, int nl, float lscale, float* loss, hipStream_t st)
+{
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(64), 0, st, lpart, nl, lscale, loss);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Training pairs of one closed-loop record per workgroup.  A row is usable while every
+// value of it is finite and the base is above the fall height: the first row that is not
+// ends the record (the smallest such index, found with an LDS minimum).  Rows before it
+// give the features -- the state with the base x, y taken relative to the origin, then the
+// command (v, 0, 0) -- and the targets, each joint's knots resampled to 6 with R.
+__global__ __launch_bounds__(256) void pairs_kernel(PairsArgs a)
+{
+    __shared__ int first_bad;
+    const int t = threadIdx.x, r = blockIdx.x;
+    const int W = 37 + 12 * a.nk;
+    const float* rec = a.rec + (size_t)r * a.steps * W;
+    if (t == 0) first_bad = a.steps;
+    __syncthreads();
+    for (int k = t; k < a.steps; k += 256) {
+        const float* row = rec + (size_t)k * W;
+        bool ok = row[2] > a.fall_z;  // false for a NaN height too
+        for (int c = 0; c < W; ++c) ok = ok && isfinite(row[c]);
+        if (!ok) atomicMin(&first_bad, k);
+    }
+    __syncthreads();
+    const int n = first_bad;
+    if (t == 0) a.count[r] = n;
+    const float ox = a.oc[3 * r], oy = a.oc[3 * r + 1], v = a.oc[3 * r + 2];
+    float* feat = a.feat + (size_t)r * a.steps * 40;
+    for (int e = t; e < n * 40; e += 256) {
+        const int k = e / 40, c = e - k * 40;
+        float x = 0.f;
+        if (c < 37) x = rec[(size_t)k * W + c] - (c == 0 ? ox : c == 1 ? oy : 0.f);
+        else if (c == 37) x = v;
+        feat[e] = x;
+    }
+    float* tgt = a.tgt + (size_t)r * a.steps * 72;
+    for (int e = t; e < n * 72; e += 256) {
+        const int k = e / 72, d = e - k * 72, j = d / kKnots, i = d - j * kKnots;
+        const float* kn = rec + (size_t)k * W + 37 + j * a.nk;
+        float y = 0.f;
+        for (int q = 0; q < a.nk; ++q) y += a.R[i][q] * kn[q];
+        tgt[e] = y;
+    }
+}
+
+hipError_t launch_pairs(const PairsArgs& a, hipStream_t st)
+{
+    if (a.n_rec < 1 || a.steps < 1 || a.nk < 2 || a.nk > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pairs_kernel, dim3(a.n_rec), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 }  // namespace mlp

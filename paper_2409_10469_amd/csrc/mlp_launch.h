@@ -135,4 +135,22 @@ struct HeadArgs {
 };
 hipError_t launch_head(const HeadArgs& a, hipStream_t st);
 
+// the mean loss from the loss kernel's partials, summed in the order of the parameter
+// pass (lane t adds partials t, t + 64, ...; then the 64 lane sums in order), so it equals
+// the loss a gradient or training step reports for the same rows
+hipError_t launch_loss_sum(const float* lpart, int nl, float lscale, float* loss, hipStream_t st);
+
+// closed-loop records -> training pairs (one workgroup per record)
+struct PairsArgs {
+    const float* rec;   // n_rec x steps x (37 + 12 nk): state, then the unshifted knots
+    const float* oc;    // n_rec x 3: origin x, origin y, commanded forward velocity
+    int n_rec, steps, nk;
+    float fall_z;       // a row whose base height is not above this ends the record's pairs
+    float R[kKnots][8]; // target knot i from record knot k, 6 x nk
+    float* feat;        // n_rec x steps x 40
+    float* tgt;         // n_rec x steps x 72
+    int* count;         // n_rec: pairs of each record
+};
+hipError_t launch_pairs(const PairsArgs& a, hipStream_t st);
+
 }  // namespace mlp

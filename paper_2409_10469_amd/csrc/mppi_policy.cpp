@@ -531,6 +531,53 @@ mppi_status mppi_policy_grad(mppi_policy* p, const float* d_in, const float* d_t
     return grad(p, d_in, d_target, d_index, B, d_grad ? d_grad : at<float>(p, p->o_G), d_loss, p->stream);
 }
 
+mppi_status mppi_policy_nll(mppi_policy* p, const float* d_in, const float* d_target, const int* d_index, int B,
+                            float* d_loss)
+{
+    mppi_status s;
+    if ((s = need_bound(p))) return s;
+    if (!d_in || !d_target || !d_loss) return pfail(p, MPPI_EINVAL, "null input, target or loss");
+    if ((s = check_batch(p, B))) return s;
+    const int bp = pad64(B);
+    float* out = at<float>(p, p->o_out);
+    if ((s = forward(p, d_in, d_index, B, out, false, p->stream))) return s;
+    const float* nrm = at<float>(p, p->o_norm);
+    // the loss kernel of a gradient step; its error outputs are scratch here
+    LossArgs la{out, d_target, d_index, B, bp, nrm + 80, nrm + 152, at<__bf16>(p, p->o_dZ[0]),
+                at<__bf16>(p, p->o_dZt[0]), at<float>(p, p->o_bpart[kLayers - 1]), at<float>(p, p->o_lpart)};
+    if ((s = phip(p, launch_loss(la, p->stream), "loss launch"))) return s;
+    return phip(p, launch_loss_sum(at<float>(p, p->o_lpart), bp / loss_rows_per_block(),
+                                   (float)(1.0 / ((double)B * 72.0)), d_loss, p->stream),
+                "loss sum launch");
+}
+
+mppi_status mppi_policy_pairs(int n_rec, int steps, int n_knots, const float* d_records, const float* d_origin_cmd,
+                              float fall_z, float* d_feat, float* d_target, int* d_count, void* hip_stream)
+{
+    if (n_rec < 1 || steps < 1) return pfail(nullptr, MPPI_EINVAL, "n_rec and steps must be >= 1");
+    if (n_knots < 2 || n_knots > 8) return pfail(nullptr, MPPI_EINVAL, "n_knots must be in [2, 8]");
+    if (!d_records || !d_origin_cmd || !d_feat || !d_target || !d_count)
+        return pfail(nullptr, MPPI_EINVAL, "null buffer");
+    if (!std::isfinite(fall_z)) return pfail(nullptr, MPPI_EINVAL, "fall_z must be finite");
+    PairsArgs a{};
+    a.rec = d_records;
+    a.oc = d_origin_cmd;
+    a.n_rec = n_rec;
+    a.steps = steps;
+    a.nk = n_knots;
+    a.fall_z = fall_z;
+    // knot i of 6 at fraction i / 5 of the horizon from the not-a-knot spline through the
+    // record's knots (the identity for 6 knots)
+    for (int i = 0; i < kKnots; ++i)
+        for (int k = 0; k < n_knots; ++k)
+            a.R[i][k] = n_knots == kKnots ? (i == k ? 1.f : 0.f)
+                                          : (float)mppi_host::spline_basis_at(n_knots, 1.0, k, i / (kKnots - 1.0));
+    a.feat = d_feat;
+    a.tgt = d_target;
+    a.count = d_count;
+    return phip(nullptr, launch_pairs(a, (hipStream_t)hip_stream), "pairs launch");
+}
+
 mppi_status mppi_policy_adam(mppi_policy* p, const float* d_grad, float lr)
 {
     mppi_status s;

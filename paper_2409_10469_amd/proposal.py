@@ -32,24 +32,6 @@ V_RANGE = (0.0, 0.8)
 FALL_Z = 0.12
 
 
-def resample_matrix(nk_from: int, nk_to: int = 6) -> np.ndarray:
-    """Knots of a plan at nk_to evenly spaced fractions of the horizon from its nk_from
-    knots.  For 4 knots the not-a-knot cubic spline is the interpolating cubic, so the
-    map is the Lagrange basis; 6 -> 6 is the identity."""
-    if nk_from == nk_to:
-        return np.eye(nk_to)
-    if nk_from != 4:
-        raise ValueError("training data comes from 4- and 6-knot plans")
-    src = np.linspace(0.0, 1.0, nk_from)
-    dst = np.linspace(0.0, 1.0, nk_to)
-    R = np.ones((nk_to, nk_from))
-    for j in range(nk_from):
-        for m in range(nk_from):
-            if m != j:
-                R[:, j] *= (dst - src[m]) / (src[j] - src[m])
-    return R
-
-
 def generate(n_pairs=1_000_000, episode_steps=200, instances=256, seed=0, arith="fp64", budget=1 << 30,
              log=print):
     """Closed-loop pairs from both configs, half each.  Returns dict of float32 device
@@ -65,7 +47,6 @@ def generate(n_pairs=1_000_000, episode_steps=200, instances=256, seed=0, arith=
         got = 0
         nk, K, H = wl["nk"], wl["K"], wl["H"]
         nx, D = 37, 12 * nk
-        R = torch.as_tensor(resample_matrix(nk), dtype=torch.float32, device="cuda")
         batch = B.Batch(max_instances=instances, budget_bytes=budget, max_horizon=H,
                         max_hf_cells=W.HF_N * W.HF_N, arith=arith)
         model = B.Model(W.model_dict(wl, 0))
@@ -73,6 +54,8 @@ def generate(n_pairs=1_000_000, episode_steps=200, instances=256, seed=0, arith=
         while got < target:
             n_inst = min(instances, math.ceil((target - got) / episode_steps))
             recs, meta = [], []
+            # one record per instance, consecutive, as the pairs kernel reads them
+            rec_all = torch.empty((n_inst, episode_steps, nx + D), dtype=torch.float32, device="cuda")
             for k in range(n_inst):
                 s = int(rng.integers(1 << 30))
                 v = float(rng.uniform(*V_RANGE))
@@ -82,7 +65,7 @@ def generate(n_pairs=1_000_000, episode_steps=200, instances=256, seed=0, arith=
                 i = batch.admit(slot, p, x0, W.stance_knots(nk))
                 if i is None:
                     raise RuntimeError("instance does not fit in the generation budget")
-                rec = torch.empty((episode_steps, nx + D), dtype=torch.float32, device="cuda")
+                rec = rec_all[k]
                 batch.record(i, rec)
                 recs.append((i, rec))
                 meta.append((v, origin))
@@ -93,26 +76,19 @@ def generate(n_pairs=1_000_000, episode_steps=200, instances=256, seed=0, arith=
             stats["seconds"] += time.perf_counter() - t0
             stats["control_steps"] += n_inst * episode_steps
             stats["rollout_steps"] += n_inst * episode_steps * K * H
-            for (i, rec), (v, origin) in zip(recs, meta):
+            for i, _ in recs:
                 batch.record(i, None)
                 batch.remove(i)
-                x, mup = rec[:, :nx], rec[:, nx:]
-                ok = torch.isfinite(rec).all(1) & (x[:, 2] > FALL_Z)
-                bad = (~ok).nonzero()
-                n_ok = int(bad[0, 0]) if bad.numel() else episode_steps
+            # fall cut, features and 6-knot targets in the library's pairs kernel
+            oc = torch.tensor([[o[0], o[1], v] for v, o in meta], dtype=torch.float32, device="cuda")
+            feat, tgt, count = B.policy_pairs(rec_all, oc, nk, FALL_Z, stream=stream)
+            for k, n_ok in enumerate(count.cpu().tolist()):
                 if n_ok < episode_steps:
                     stats["falls"] += 1
                 if n_ok == 0:
                     continue
-                feat = torch.empty((n_ok, 40), dtype=torch.float32, device="cuda")
-                feat[:, :nx] = x[:n_ok]
-                feat[:, 0] -= origin[0]
-                feat[:, 1] -= origin[1]
-                feat[:, 37] = v
-                feat[:, 38:] = 0.0
-                tgt = (mup[:n_ok].reshape(n_ok, 12, nk) @ R.T).reshape(n_ok, 72)
-                Xs.append(feat)
-                Ys.append(tgt)
+                Xs.append(feat[k, :n_ok])
+                Ys.append(tgt[k, :n_ok])
                 Es.append(torch.full((n_ok,), ep_id, dtype=torch.int32, device="cuda"))
                 got += n_ok
                 ep_id += 1
@@ -146,21 +122,14 @@ def normalization(data, rows, floor=1e-3):
 
 
 def nll(policy, data, rows, chunk=4096):
-    """Held-out Gaussian NLL (mean over rows and outputs) from forward passes."""
-    import torch
-    X, Y = data["X"], data["Y"]
-    om, osd = policy._norm[2], policy._norm[3]
-    om = torch.as_tensor(om, dtype=torch.float32, device="cuda")
-    osd = torch.as_tensor(osd, dtype=torch.float32, device="cuda")
+    """Held-out Gaussian NLL (mean over rows and outputs): the library's loss over chunks
+    of at most max_batch rows, weighted by their row counts."""
     tot, n = 0.0, 0
     chunk = min(chunk, policy.max_batch)
     for a in range(0, rows.numel(), chunk):
-        r = rows[a:a + chunk].long()
-        out = policy.forward(X[r].contiguous())
-        y = (Y[r] - om) / osd
-        m, s = out[:, :72], out[:, 72:]
-        tot += float((0.5 * (y - m) ** 2 * torch.exp(-2 * s) + s).sum())
-        n += r.numel() * 72
+        r = rows[a:a + chunk].contiguous()
+        tot += float(policy.nll(data["X"], data["Y"], index=r).item()) * r.numel()
+        n += r.numel()
     return tot / n
 
 

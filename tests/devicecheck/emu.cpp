@@ -159,4 +159,6 @@ hipError_t launch_reduce(const ReduceArgs&, hipStream_t) { return hipErrorInvali
 hipError_t launch_adam(const AdamArgs&, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_reduce_adam(const ReduceArgs&, const AdamArgs&, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_head(const HeadArgs&, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_loss_sum(const float*, int, float, float*, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_pairs(const PairsArgs&, hipStream_t) { return hipErrorInvalidValue; }
 }  // namespace mlp

@@ -145,6 +145,8 @@ static void policy(mppi_policy* p)
         OK(mppi_policy_grad(p, X, Y, nullptr, B, G, L));
         OK(mppi_policy_grad(p, X, Y, idx, B, G, L));
         OK(mppi_policy_train_step(p, X, Y, idx, B, 1e-3f, L));
+        OK(mppi_policy_nll(p, X, Y, nullptr, B, L));
+        OK(mppi_policy_nll(p, X, Y, idx, B, L));
         float *c = devf(96), *s = devf(96);
         for (int nk = 2; nk <= 8; ++nk) OK(mppi_policy_head(p, out, nk, 0.25f, c, s));
     }
@@ -152,6 +154,18 @@ static void policy(mppi_policy* p)
     OK(mppi_policy_get_params(p, P));
     OK(mppi_policy_set_params(p, P));
     REFUSED(mppi_policy_forward(p, X, 513, devf(513 * 144)));
+    REFUSED(mppi_policy_nll(p, X, Y, nullptr, 4, nullptr));
+    // training pairs of closed-loop records (no policy involved)
+    for (int nk : {2, 4, 6, 8}) {
+        const int n_rec = 3, steps = 17;
+        float *rec = devf((size_t)n_rec * steps * (37 + 12 * nk)), *oc = devf(3 * n_rec);
+        float *feat = devf((size_t)n_rec * steps * 40), *tgt = devf((size_t)n_rec * steps * 72);
+        int* cnt = static_cast<int*>(dev(4 * n_rec));
+        OK(mppi_policy_pairs(n_rec, steps, nk, rec, oc, 0.12f, feat, tgt, cnt, nullptr));
+        REFUSED(mppi_policy_pairs(n_rec, steps, 9, rec, oc, 0.12f, feat, tgt, cnt, nullptr));
+        REFUSED(mppi_policy_pairs(0, steps, nk, rec, oc, 0.12f, feat, tgt, cnt, nullptr));
+        REFUSED(mppi_policy_pairs(n_rec, steps, nk, rec, oc, 0.12f, feat, tgt, nullptr, nullptr));
+    }
 }
 
 static void batch(mppi_model* flat, mppi_model* terrain, mppi_model* push, mppi_policy* pol, int arith)

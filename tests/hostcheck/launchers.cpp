@@ -416,6 +416,26 @@ hipError_t launch_loss(const LossArgs& a, hipStream_t)
     return hipSuccess;
 }
 
+hipError_t launch_loss_sum(const float* lpart, int nl, float, float* loss, hipStream_t)
+{
+    if (nl < 1) fail("loss partial count");
+    range_check(lpart, 4ull * nl, "loss partials");
+    range_check(loss, 4, "loss");
+    return hipSuccess;
+}
+
+hipError_t launch_pairs(const PairsArgs& a, hipStream_t)
+{
+    if (a.n_rec < 1 || a.steps < 1 || a.nk < 2 || a.nk > 8) fail("pairs shape");
+    const size_t rows = (size_t)a.n_rec * a.steps;
+    range_check(a.rec, 4 * rows * (37 + 12 * a.nk), "pairs records");
+    range_check(a.oc, 12ull * a.n_rec, "pairs origins and commands");
+    range_check(a.feat, 160 * rows, "pairs features");
+    range_check(a.tgt, 288 * rows, "pairs targets");
+    range_check(a.count, 4ull * a.n_rec, "pairs counts");
+    return hipSuccess;
+}
+
 static void check_reduce(const ReduceArgs& a)
 {
     for (int l = 0; l < kLayers; ++l) {

@@ -298,6 +298,66 @@ def test_learned_step_matches_oracle_chain(B):
     assert ctl.proposal_stats()[1] == 1  # plain steps are not counted
 
 
+def test_nll_is_the_gradient_steps_loss_and_the_formula(B):
+    """mppi_policy_nll: bit for bit the loss mppi_policy_grad reports for the same rows
+    (same forward, loss kernel and summation order), and the Gaussian NLL of the network's
+    own outputs computed here in FP64."""
+    pol = B.Policy(max_batch=512, seed=4)
+    rng = np.random.default_rng(12)
+    norm = (rng.normal(size=40) * 0.1, rng.uniform(0.5, 2.0, 40), rng.normal(size=72) * 0.2,
+            rng.uniform(0.05, 0.3, 72))
+    pol.set_normalization(*norm)
+    X = torch.as_tensor(rng.normal(size=(700, 40)), dtype=torch.float32).cuda()
+    Y = torch.as_tensor(rng.normal(size=(700, 72)) * 0.2, dtype=torch.float32).cuda()
+    for idx in (None, torch.as_tensor(rng.choice(700, 333, replace=False).astype(np.int32)).cuda()):
+        B_ = 500 if idx is None else None
+        loss = pol.nll(X, Y, index=idx, B=B_).item()
+        lg, _ = pol.grad(X, Y, index=idx, B=B_)
+        assert np.float32(loss).tobytes() == np.float32(lg.item()).tobytes(), (loss, lg.item())
+        rows = np.arange(500) if idx is None else idx.cpu().numpy()
+        out = pol.forward(X[torch.as_tensor(rows).long().cuda()].contiguous()).cpu().numpy().astype(np.float64)
+        y = (Y.cpu().numpy()[rows].astype(np.float64) - norm[2].astype(np.float32)) / norm[3].astype(np.float32)
+        m, s = out[:, :72], out[:, 72:]
+        want = np.mean(0.5 * (y - m) ** 2 * np.exp(-2 * s) + s)
+        assert abs(loss - want) <= 1e-5 * max(1.0, abs(want)), (loss, want)
+
+
+@pytest.mark.parametrize("nk", [4, 6, 3])
+def test_pairs_from_records_match_a_reference(B, nk):
+    """mppi_policy_pairs against a reference written here: the fall cut (first row not
+    finite or not above the fall height), features (state minus origin, command) bit for
+    bit, and 6-knot targets against the oracle's not-a-knot spline evaluated at the six
+    fractions of the horizon (FP32 sums: 1e-5)."""
+    rng = np.random.default_rng(nk)
+    n_rec, steps, W_ = 6, 30, 37 + 12 * nk
+    rec = rng.normal(size=(n_rec, steps, W_)).astype(np.float32)
+    rec[:, :, 2] = rng.uniform(0.2, 0.3, (n_rec, steps))
+    fall = 0.12
+    rec[1, 7, 2] = 0.05                 # falls at row 7
+    rec[2, 0, 37 + 5] = np.nan          # a knot not finite at row 0: no pair
+    rec[3, 29, 20] = np.inf             # the last row not finite
+    rec[4, 12, 2] = np.float32(fall)    # at the fall height (not above): cut
+    rec[5, 3, 2] = np.nan               # a non-finite height
+    want_n = [30, 7, 0, 29, 12, 3]
+    oc = np.c_[rng.uniform(-0.5, 0.5, (n_rec, 2)), rng.uniform(0, 0.8, n_rec)].astype(np.float32)
+    feat, tgt, count = B.policy_pairs(torch.as_tensor(rec).cuda(), torch.as_tensor(oc).cuda(), nk, fall)
+    torch.cuda.synchronize()
+    assert count.cpu().tolist() == want_n
+    feat, tgt = feat.cpu().numpy(), tgt.cpu().numpy()
+    for r in range(n_rec):
+        n = want_n[r]
+        f = np.zeros((n, 40), np.float32)
+        f[:, :37] = rec[r, :n, :37]
+        f[:, 0] -= oc[r, 0]
+        f[:, 1] -= oc[r, 1]
+        f[:, 37] = oc[r, 2]
+        assert np.array_equal(feat[r, :n], f), r
+        for k in range(n):
+            kn = rec[r, k, 37:].reshape(12, nk).astype(np.float64)
+            ref = np.array([[O.spline_eval(kn[j], 1.0, i / 5) for i in range(6)] for j in range(12)]).reshape(72)
+            assert np.abs(tgt[r, k] - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max()), (r, k)
+
+
 def test_training_pipeline_on_closed_loop_data(B):
     """Pairs from GPU closed loops of both walking configs, then a few Adam epochs: the
     held-out NLL falls well below the untrained network's."""
