@@ -37,6 +37,7 @@ class ServingSim:
     def __init__(self, seed=0, n_target=256, budget_bytes=64 << 20, lifetime=200, arith="fp64", max_instances=512):
         import torch
         self.rng = np.random.default_rng(seed)
+        self.age_rng = np.random.default_rng([seed, 1])  # ages of the prefilled instances
         self.lifetime = lifetime
         self.rate = n_target / lifetime
         self.arith = arith
@@ -79,8 +80,15 @@ class ServingSim:
             self.next_rid += 1
 
     def prefill(self, n):
+        """n requests as a snapshot of the steady state: the admitted ones get ages drawn
+        uniformly from [0, lifetime), so their departures spread over one lifetime
+        instead of coinciding while the Poisson arrivals continue."""
+        before = set(self.live)
         self.arrive(n)
         self._try_admit()
+        for iid in sorted(set(self.live) - before):
+            req, t0 = self.live[iid]
+            self.live[iid] = (req, t0 - int(self.age_rng.integers(self.lifetime)))
 
     def host_tick(self):
         """Departures, Poisson arrivals and admissions before a control step."""
