@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from oracle import oracle as O
 from paper_2409_10469_amd import workloads as W
 
 # state blocks compared separately (robot): p, quat, q_joint, v_world, omega_body, qd_joint
@@ -144,3 +145,14 @@ def mixed_step_bound(orc, x, u, kp, kd, dt):
     inputs by at most ULP_FACTOR ulps; the FP64 system adds nothing at this scale.  So
     ULP_FACTOR times the oracle's one-ulp sensitivity, or the FP64 step's 1e-5 if larger."""
     return max(STEP_TOL, ULP_FACTOR * ulp_sensitivity(orc, x, u, kp, kd, dt))
+
+
+def r16_knot_sensitivity(p, step, mu, costs):
+    """First-order change of the updated knots when every cost moves by the cost
+    tolerance: sum_n (w_n / lambda) |L_n| COST_TOL |theta_n - mu'|, max over knots."""
+    w, _ = O.weights(costs, p["lam"])
+    theta = mu + p["sigma"] * O.sample_eps(p, step)
+    theta[0] = mu
+    mup = w @ theta
+    ok = np.isfinite(costs)
+    return float((w[ok, None] * np.abs(costs[ok, None]) * np.abs(theta[ok] - mup)).sum(0).max() / p["lam"] * COST_TOL)

@@ -5,7 +5,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2409_10469_amd import workloads as W
-from tests.parity_utils import KNOT_TOL, STEP_TOL, f32, round_model, round_params, step_error
+from tests.parity_utils import KNOT_TOL, STEP_TOL, f32, r16_knot_sensitivity, round_model, round_params, step_error
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -204,8 +204,9 @@ def test_full_size_serving_batch_sampled_instances(B):
     """The serving workload at full size: 256 requests drawn as the serving driver draws
     them (mixed tasks, K log-uniform in [256, 4096], H uniform in [20, 80]), all admitted,
     one step in the persistent launch.  Sampled instances (the largest and smallest K of
-    each task) against the single-instance controller, the two smallest also against the
-    oracle."""
+    each task, up to K = 4096 and H = 80) against the single-instance controller and
+    against the oracle's step, the knots wherever a cost error at the cost bar moves them
+    by less than the knot bar (reading of R16; the two smallest must qualify)."""
     from paper_2409_10469_amd import serving as SV
     rng = np.random.default_rng(2024)
     reqs = [SV.draw_request(rng, i) for i in range(256)]
@@ -236,6 +237,7 @@ def test_full_size_serving_batch_sampled_instances(B):
         picks.add(max(of_task, key=lambda k: reqs[k]["K"]))
         picks.add(min(of_task, key=lambda k: reqs[k]["K"]))
     smallest = sorted(picks, key=lambda k: reqs[k]["K"] * reqs[k]["H"])[:2]
+    checked = 0
     for k in sorted(picks):
         name, p, x0, mu = refs[k]
         model = models[name]
@@ -251,11 +253,18 @@ def test_full_size_serving_batch_sampled_instances(B):
         assert np.abs(bu0 - u0.cpu().numpy()).max() <= 1e-5, (name, p["K"], p["H"])
         assert np.abs(bmu - nominal).max() <= 1e-5, (name, p["K"], p["H"])
         assert step_error(bx.astype(np.float64), x1.astype(np.float64), box=box).max() <= STEP_TOL, name
-        if k in smallest:
-            orc = O.Oracle(mds[name])
-            ou0, omu, _, _ = orc.mppi_step(p, 0, x0, mu)
+        orc = O.Oracle(mds[name])
+        ou0, omu, ocosts, _ = orc.mppi_step(p, 0, x0, mu)
+        sens = r16_knot_sensitivity(p, 0, mu, ocosts)
+        print("case: %s K=%d H=%d knot sensitivity %.2e" % (name, p["K"], p["H"], sens), flush=True)
+        assert sens <= KNOT_TOL or k not in smallest, (name, sens)
+        if sens <= KNOT_TOL:
             assert np.abs(bu0 - ou0).max() <= KNOT_TOL, (name, p["K"], p["H"])
             assert np.abs(bmu - omu).max() <= KNOT_TOL, (name, p["K"], p["H"])
+            checked += 1
+        ox, _, _ = orc.step(x0, f32(bu0), p["kp"], p["kd"], p["dt"])
+        assert step_error(bx.astype(np.float64), ox, box=box).max() <= STEP_TOL, name
+    assert checked >= 2
 
 
 @pytest.mark.parametrize("arith", ["fp64", "fp32"])

@@ -15,7 +15,7 @@ import pytest
 from oracle import oracle as O
 from paper_2409_10469_amd import workloads as W
 from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, box_contact_states, f32, fp32_step_bound,
-                                random_walk_states, round_model, round_params, step_error)
+                                r16_knot_sensitivity, random_walk_states, round_model, round_params, step_error)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -173,17 +173,6 @@ def test_update_nonfinite_costs(B):
 
 
 # ---------------------------------------------------------------------------- a1-a11
-def r16_knot_sensitivity(p, step, mu, costs):
-    """First-order change of the updated knots when every cost moves by the cost
-    tolerance: sum_n (w_n / lambda) |L_n| COST_TOL |theta_n - mu'|, max over knots."""
-    w, _ = O.weights(costs, p["lam"])
-    theta = mu + p["sigma"] * O.sample_eps(p, step)
-    theta[0] = mu
-    mup = w @ theta
-    ok = np.isfinite(costs)
-    return float((w[ok, None] * np.abs(costs[ok, None]) * np.abs(theta[ok] - mup)).sum(0).max() / p["lam"] * COST_TOL)
-
-
 def test_mppi_step_flat_walk_matches_oracle(B):
     """One full control step of the flat walking workload (K=64, H=25, dt=0.02, nk=4)."""
     md, p, orc, model, ctl = _setup(B, W.FLAT_WALK)

@@ -17,7 +17,8 @@ import pytest
 from oracle import oracle as O
 from paper_2409_10469_amd import workloads as W
 from tests.parity_utils import (COST_TOL, KNOT_TOL, STEP_TOL, box_contact_states, f32, fp32_step_bound,
-                                mixed_step_bound, random_walk_states, round_model, round_params, step_error)
+                                mixed_step_bound, r16_knot_sensitivity, random_walk_states, round_model,
+                                round_params, step_error)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -172,7 +173,6 @@ def test_split_box_push_control_step_matches_oracle(B):
     assert ctl.sync_status() == 0
     ou0, omu, ocosts, rc = orc.mppi_step(p, 0, x0, mu)
     assert rc == 0
-    from tests.test_gpu_parity import r16_knot_sensitivity
     assert r16_knot_sensitivity(p, 0, mu, ocosts) <= KNOT_TOL  # the comparison is robust to cost errors
     assert np.abs(u0 - ou0).max() <= KNOT_TOL
     assert np.abs(nominal - omu).max() <= KNOT_TOL
@@ -337,7 +337,7 @@ def test_split_direct_mppi_step_matches_oracle(B, K, H):
         nominal = ctl.get_nominal().cpu().numpy()
         assert ctl.sync_status() == 0
         ou0, omu, ocosts, rc = orc.mppi_step(p, seed, x0, mu)
-        from tests.test_gpu_parity import r16_knot_sensitivity
+        assert rc == 0
         assert r16_knot_sensitivity(p, seed, mu, ocosts) <= KNOT_TOL
         assert np.abs(u0 - ou0).max() <= KNOT_TOL, seed
         assert np.abs(nominal - omu).max() <= KNOT_TOL, seed
