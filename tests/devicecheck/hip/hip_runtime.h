@@ -175,6 +175,8 @@ inline unsigned long long __builtin_amdgcn_ballot_w64(bool p)
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
 inline float __int_as_float(int i) { float f; std::memcpy(&f, &i, 4); return f; }
+// the fast exponential (the hardware's base-2 exponential on the GPU); the host's expf here
+inline float __expf(float x) { return std::exp(x); }
 inline int __float_as_int(float f) { int i; std::memcpy(&i, &f, 4); return i; }
 inline int __double2loint(double d) { int64_t i; std::memcpy(&i, &d, 8); return (int)(i & 0xffffffff); }
 inline int __double2hiint(double d) { int64_t i; std::memcpy(&i, &d, 8); return (int)(i >> 32); }
