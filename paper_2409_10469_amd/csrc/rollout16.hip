@@ -178,6 +178,54 @@ __device__ __forceinline__ V3<T> cv(V3<U> a)
 // a contact on the leg's calf with weight wgt (1: applied, 0: nothing added).  The contact
 // velocity and the law are evaluated in the geometry type R; the force and damping terms
 // on the trunk's base rows and on the leg's joint rows accumulate in the system type S.
+// The contact terms of a body's 6x6 system (the same quantities as base_contact in
+// mppi_device.h, arranged for fewer instructions): with J = [-(r x), I] and g = [r x n; n]
+// the damping block is dt (eta J^T J + (c - eta) g g^T) and the right side gains
+// dt [r x F; F].  dt eta and dt (c - eta) are folded into the operands first, so each
+// entry is one or two fused multiply-adds.
+template <typename S>
+__device__ __forceinline__ void base_contact_g(S eta, S c, V3<S> r, V3<S> n, V3<S> F, S dt, S* Q, S* rb)
+{
+    const V3<S> g0 = cross(r, n);
+    const S de = dt * eta, dce = dt * (c - eta);
+    const S ga[6] = {g0.x, g0.y, g0.z, n.x, n.y, n.z};
+    S gs[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) gs[i] = dce * ga[i];
+    const S rv[3] = {r.x, r.y, r.z};
+    const S er[3] = {de * r.x, de * r.y, de * r.z};
+    const S drr = de * dot(r, r);
+    // angular block: de (|r|^2 I - r r^T) + dce g0 g0^T
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            const S q = Q[s6(i, j)] + gs[i] * ga[j] - er[i] * rv[j];
+            Q[s6(i, j)] = (i == j) ? q + drr : q;
+        }
+    // coupling block: de [r x] + dce g0 n^T ([r x] = {{0, -rz, ry}, {rz, 0, -rx}, {-ry, rx, 0}})
+    Q[s6(0, 3)] += gs[0] * ga[3];
+    Q[s6(0, 4)] += gs[0] * ga[4] - er[2];
+    Q[s6(0, 5)] += gs[0] * ga[5] + er[1];
+    Q[s6(1, 3)] += gs[1] * ga[3] + er[2];
+    Q[s6(1, 4)] += gs[1] * ga[4];
+    Q[s6(1, 5)] += gs[1] * ga[5] - er[0];
+    Q[s6(2, 3)] += gs[2] * ga[3] - er[1];
+    Q[s6(2, 4)] += gs[2] * ga[4] + er[0];
+    Q[s6(2, 5)] += gs[2] * ga[5];
+    // linear block: de I + dce n n^T
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            const S q = Q[s6(3 + i, 3 + j)] + gs[3 + i] * ga[3 + j];
+            Q[s6(3 + i, 3 + j)] = (i == j) ? q + de : q;
+        }
+    const V3<S> m = cross(r, F);
+    rb[0] += dt * m.x; rb[1] += dt * m.y; rb[2] += dt * m.z;
+    rb[3] += dt * F.x; rb[4] += dt * F.y; rb[5] += dt * F.z;
+}
+
 template <typename R, typename S>
 __device__ __forceinline__ void leg_contact_w(const ModelT<R>& M, const LegGeo<R>& G, V3<R> vb, V3<R> w,
                                               const R qd[3], R delta, V3<R> n, V3<R> r, V3<R> vo, S dt, R wgt, S* Q,
@@ -192,9 +240,13 @@ __device__ __forceinline__ void leg_contact_w(const ModelT<R>& M, const LegGeo<R
     const S e = S(eta), cw = S(wgt) * S(M.cc);
     const S ce = cw - e;
     const V3<S> rs = cv<S>(r), ns = cv<S>(n), Fs = cv<S>(F);
-    base_contact(e, cw, rs, ns, Fs, dt, Q, rb);
+    base_contact_g(e, cw, rs, ns, Fs, dt, Q, rb);
+    // the leg's rows: dt (e J_l^T J + ce g_l g^T) with g_l = J_l^T n, dt e and dt ce folded
+    // into the operands
+    const S de = dt * e;
     const V3<S> jv[3] = {cv<S>(ja), cv<S>(jf), cv<S>(jk)};
     const S gj[3] = {dot(jv[0], ns), dot(jv[1], ns), dot(jv[2], ns)};
+    const S dg[3] = {dt * ce * gj[0], dt * ce * gj[1], dt * ce * gj[2]};
     const V3<S> gA = cross(rs, ns);
     const S g0[6] = {gA.x, gA.y, gA.z, ns.x, ns.y, ns.z};
 #pragma unroll
@@ -202,15 +254,15 @@ __device__ __forceinline__ void leg_contact_w(const ModelT<R>& M, const LegGeo<R
         const V3<S> rxj = cross(rs, jv[j]);
         const S jb[6] = {rxj.x, rxj.y, rxj.z, jv[j].x, jv[j].y, jv[j].z};
 #pragma unroll
-        for (int i = 0; i < 6; ++i) L.C[j][i] += dt * (e * jb[i] + ce * g0[i] * gj[j]);
+        for (int i = 0; i < 6; ++i) L.C[j][i] += de * jb[i] + dg[j] * g0[i];
         L.rl[j] += dt * dot(jv[j], Fs);
     }
-    L.A00 += dt * (e * dot(jv[0], jv[0]) + ce * gj[0] * gj[0]);
-    L.A01 += dt * (e * dot(jv[0], jv[1]) + ce * gj[0] * gj[1]);
-    L.A02 += dt * (e * dot(jv[0], jv[2]) + ce * gj[0] * gj[2]);
-    L.A11 += dt * (e * dot(jv[1], jv[1]) + ce * gj[1] * gj[1]);
-    L.A12 += dt * (e * dot(jv[1], jv[2]) + ce * gj[1] * gj[2]);
-    L.A22 += dt * (e * dot(jv[2], jv[2]) + ce * gj[2] * gj[2]);
+    L.A00 += de * dot(jv[0], jv[0]) + dg[0] * gj[0];
+    L.A01 += de * dot(jv[0], jv[1]) + dg[0] * gj[1];
+    L.A02 += de * dot(jv[0], jv[2]) + dg[0] * gj[2];
+    L.A11 += de * dot(jv[1], jv[1]) + dg[1] * gj[1];
+    L.A12 += de * dot(jv[1], jv[2]) + dg[1] * gj[2];
+    L.A22 += de * dot(jv[2], jv[2]) + dg[2] * gj[2];
 }
 
 // contact terms of a force F at body-frame point r with normal n and secant eta (all in
@@ -218,7 +270,7 @@ __device__ __forceinline__ void leg_contact_w(const ModelT<R>& M, const LegGeo<R
 template <typename R, typename S>
 __device__ __forceinline__ void body_contact(R eta, R c, V3<R> r, V3<R> n, V3<R> F, S dt, S* Q, S* rb)
 {
-    base_contact(S(eta), S(c), cv<S>(r), cv<S>(n), cv<S>(F), dt, Q, rb);
+    base_contact_g(S(eta), S(c), cv<S>(r), cv<S>(n), cv<S>(F), dt, Q, rb);
 }
 
 // ------------------------------------------------------------------------------
