@@ -155,6 +155,7 @@ __global__ __launch_bounds__(256) void rollout_kernel(ModelT<R> M, DevParams P, 
 // four at 4096): the kernel is bound by the latency of those passes, not by bandwidth.
 // ---------------------------------------------------------------------------------
 constexpr int kUpdThreads = 1024;
+constexpr int kUpdUnroll = 2;  // samples per thread whose loads are issued together
 constexpr int kUpdWaves = kUpdThreads / 64;
 
 __device__ __forceinline__ float wave_reduce(float v, bool is_min)
@@ -198,10 +199,20 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, Update
     const int eps_sn = prop ? 12 * nk : a.eps_sn, eps_sd = prop ? 1 : a.eps_sd;
     const float* mu = prop ? a.mu_p : a.mu;
     const float sigma = prop ? 1.f : P.sigma;
+    // the passes over K take kUpdUnroll samples per thread at a time and issue all their
+    // loads before using any, so a pass costs one memory round trip per kUpdUnroll
+    // samples; each thread still visits its samples in increasing order
     float lmin = __int_as_float(0x7f800000);
-    for (int n = t; n < K; n += kUpdThreads) {
-        const float c = costs[n];
-        if (fabsf(c) <= 3.0e38f) lmin = fminf(lmin, c);
+    for (int n0 = t; n0 < K; n0 += kUpdUnroll * kUpdThreads) {
+        float c[kUpdUnroll];
+#pragma unroll
+        for (int u = 0; u < kUpdUnroll; ++u) {
+            const int n = n0 + u * kUpdThreads;
+            c[u] = n < K ? costs[n] : __int_as_float(0x7f800000);
+        }
+#pragma unroll
+        for (int u = 0; u < kUpdUnroll; ++u)
+            if (fabsf(c[u]) <= 3.0e38f) lmin = fminf(lmin, c[u]);
     }
     lmin = block_reduce(lmin, sh, true);
     const bool none = !(fabsf(lmin) <= 3.0e38f);
@@ -211,14 +222,29 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, Update
 #pragma unroll
         for (int i = 0; i < kMaxKnots; ++i) acc[i] = 0.f;
         if (!none) {
-            for (int n = t; n < K; n += kUpdThreads) {
-                const float c = costs[n];
-                const float e = (fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) : 0.f;
-                if (c0 == 0) s += e;
-                if (n > 0) {
+            for (int n0 = t; n0 < K; n0 += kUpdUnroll * kUpdThreads) {
+                float c[kUpdUnroll], ev[kUpdUnroll][kMaxKnots];
+#pragma unroll
+                for (int u = 0; u < kUpdUnroll; ++u) {
+                    const int n = n0 + u * kUpdThreads;
+                    c[u] = n < K ? costs[n] : __int_as_float(0x7f800000);
 #pragma unroll
                     for (int i = 0; i < kMaxKnots; ++i)
-                        if (c0 + i < nk) acc[i] += e * eps[(size_t)n * eps_sn + (size_t)(j * nk + c0 + i) * eps_sd];
+                        ev[u][i] = (n < K && n > 0 && c0 + i < nk)
+                                       ? eps[(size_t)n * eps_sn + (size_t)(j * nk + c0 + i) * eps_sd]
+                                       : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < kUpdUnroll; ++u) {
+                    const int n = n0 + u * kUpdThreads;
+                    if (n >= K) continue;
+                    const float e = (fabsf(c[u]) <= 3.0e38f) ? expf(-(c[u] - lmin) * P.inv_lambda) : 0.f;
+                    if (c0 == 0) s += e;
+                    if (n > 0) {
+#pragma unroll
+                        for (int i = 0; i < kMaxKnots; ++i)
+                            if (c0 + i < nk) acc[i] += e * ev[u][i];
+                    }
                 }
             }
         }
@@ -248,9 +274,20 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(DevParams P, Update
     if (t == 0 && a.u0_out) a.u0_out[j] = mup[0];
     if (j == 0 && a.weights_out) {
         const float is = none ? 0.f : 1.f / s;
-        for (int n = t; n < K; n += kUpdThreads) {
-            const float c = costs[n];
-            a.weights_out[n] = (!none && fabsf(c) <= 3.0e38f) ? expf(-(c - lmin) * P.inv_lambda) * is : 0.f;
+        for (int n0 = t; n0 < K; n0 += kUpdUnroll * kUpdThreads) {
+            float c[kUpdUnroll];
+#pragma unroll
+            for (int u = 0; u < kUpdUnroll; ++u) {
+                const int n = n0 + u * kUpdThreads;
+                c[u] = n < K ? costs[n] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kUpdUnroll; ++u) {
+                const int n = n0 + u * kUpdThreads;
+                if (n < K)
+                    a.weights_out[n] =
+                        (!none && fabsf(c[u]) <= 3.0e38f) ? expf(-(c[u] - lmin) * P.inv_lambda) * is : 0.f;
+            }
         }
     }
     if (j == 0 && t == 0) {
