@@ -1,6 +1,6 @@
 """GPU parity of the HIP hot path against the FP64 oracle, through the C ABI.
 
-Tolerances (stated by the method's specification for this build):
+Tolerances (the bars of the method's parity specification):
   per-step state error <= 1e-5 relative per block, from identical FP32 input states;
   rollout costs within 1e-4 relative over 10-step horizons;
   updated knots within 1e-3;
