@@ -176,9 +176,9 @@ def main():
     ap.add_argument("--batch-tuning", default=None, metavar="BPC,ORDER,MODE",
                     help="batched_serving: fixed tuning instead of the autotuner (blocks per CU, tile order "
                          "0 admission / 1 longest first, launch mode 0 per scene / 1 one kernel for every scene)")
-    ap.add_argument("--budget-mib", type=int, default=64,
-                    help="batched_serving: the HBM budget that admits instances (MiB); 64 binds admission, "
-                         "256 admits every instance of the 256-instance target")
+    ap.add_argument("--budget-mib", type=int, default=256,
+                    help="batched_serving: the HBM budget that admits instances (MiB); 256 (default) admits every "
+                         "request, about 256 live; 64 binds admission")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -352,7 +352,7 @@ def learned_vs_plain(args):
 
 def bench_serving(args):
     """256 MPPI instances (mixed tasks, K log-uniform in [256, 4096], H uniform in
-    [20, 80]) under a seeded Poisson stream admitted by an HBM budget (64 MiB by default)."""
+    [20, 80]) under a seeded Poisson stream admitted by an HBM budget (256 MiB by default)."""
     import numpy as np
     from paper_2409_10469_amd.serving import ServingSim
     sim = ServingSim(seed=args.seed, arith=args.arith, budget_bytes=args.budget_mib << 20)

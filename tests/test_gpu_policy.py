@@ -358,6 +358,30 @@ def test_pairs_from_records_match_a_reference(B, nk):
             assert np.abs(tgt[r, k] - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max()), (r, k)
 
 
+def test_pairs_edges(B):
+    """One-row records, a single record, eight knots, and a record whose first row has
+    fallen: counts 1, 1 and 0; one record of one row; targets at eight knots against the
+    oracle's spline."""
+    rng = np.random.default_rng(99)
+    nk = 8
+    rec = rng.normal(size=(3, 1, 37 + 12 * nk)).astype(np.float32)
+    rec[:, :, 2] = 0.25
+    rec[2, 0, 2] = 0.01
+    oc = np.zeros((3, 3), np.float32)
+    feat, tgt, count = B.policy_pairs(torch.as_tensor(rec).cuda(), torch.as_tensor(oc).cuda(), nk, 0.12)
+    assert count.cpu().tolist() == [1, 1, 0]
+    t = tgt.cpu().numpy()
+    for r in range(2):
+        kn = rec[r, 0, 37:].reshape(12, nk).astype(np.float64)
+        ref = np.array([[O.spline_eval(kn[j], 1.0, i / 5) for i in range(6)] for j in range(12)]).reshape(72)
+        assert np.abs(t[r, 0] - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    one = torch.as_tensor(rec[:1]).cuda()
+    _, _, c1 = B.policy_pairs(one, torch.zeros((1, 3), device="cuda"), nk, 0.12)
+    assert c1.cpu().tolist() == [1]
+    with pytest.raises(B.MppiError):
+        B.policy_pairs(one, torch.zeros((1, 3), device="cuda"), nk, float("nan"))
+
+
 def test_training_pipeline_on_closed_loop_data(B):
     """Pairs from GPU closed loops of both walking configs, then a few Adam epochs: the
     held-out NLL falls well below the untrained network's."""
