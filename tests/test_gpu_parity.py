@@ -7,7 +7,6 @@ Tolerances (the bars of the method's parity specification):
   Philox words bitwise equal.
 """
 import ctypes
-import math
 
 import numpy as np
 import pytest

@@ -17,7 +17,6 @@ Tolerances (relative L2 over the compared array unless stated):
   head                                     <= 1e-5
   proposal step: costs COST_TOL, knots and first control KNOT_TOL (as the plain step).
 """
-import math
 
 import numpy as np
 import pytest

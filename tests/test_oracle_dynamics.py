@@ -9,7 +9,6 @@ conservation and momentum conservation under RK4 integration, and closed forms.
 import math
 
 import numpy as np
-import pytest
 
 from oracle import oracle as O
 from paper_2409_10469_amd import workloads as W

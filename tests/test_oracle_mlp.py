@@ -4,7 +4,6 @@ closed form, and the BF16-rounding variant against the exact one."""
 import math
 
 import numpy as np
-import pytest
 
 from oracle import oracle as O
 
