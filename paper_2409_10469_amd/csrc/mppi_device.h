@@ -71,20 +71,73 @@ __device__ __forceinline__ float m_sin(float x) { return sinf(x); }
 __device__ __forceinline__ double m_sin(double x) { return sin(x); }
 __device__ __forceinline__ float m_cos(float x) { return cosf(x); }
 __device__ __forceinline__ double m_cos(double x) { return cos(x); }
-__device__ __forceinline__ void m_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+// FP32 sine and cosine written out without branches (the device library's sincosf
+// carries a large-argument path and branches that cost a wave about 45 instructions):
+// x = k pi/2 + r with k = rint(2x/pi) and pi/2 taken in two parts (the float nearest pi/2
+// and the remainder), so r is exact to a few ulps for the joint and rotation angles met
+// here (|x| up to a few hundred); then the Taylor series of sin and cos on |r| <= pi/4 up
+// to r^9 and r^10 (truncation below 3e-9 relative) and the quadrant's swap and signs.
+// About 2 ulp (relative to max(|value|, 2^-10)) on a host check of 4 million arguments.
+__device__ __forceinline__ void m_sincos(float x, float* sn, float* cs)
+{
+    const float k = rintf(x * 0.63661977236758134f);
+    float r = fmaf(-k, 1.57079637050628662f, x);
+    r = fmaf(-k, -4.37113900018624283e-8f, r);
+    const float r2 = r * r;
+    const float sp = r + r * r2 * fmaf(r2, fmaf(r2, fmaf(r2, 1.f / 362880.f, -1.f / 5040.f), 1.f / 120.f), -1.f / 6.f);
+    const float cp =
+        fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.f / 3628800.f, 1.f / 40320.f), -1.f / 720.f), 1.f / 24.f), -0.5f),
+             1.f);
+    const int q = int(k) & 3;
+    const float s0 = (q & 1) ? cp : sp, c0 = (q & 1) ? sp : cp;
+    *sn = (q & 2) ? -s0 : s0;
+    *cs = ((q + 1) & 2) ? -c0 : c0;
+}
 __device__ __forceinline__ void m_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+
+// tanh(s) / s for s >= 0 (the friction law's secant factor).  FP32: below s = 1/2 its
+// Taylor series in s^2 through s^14 (coefficients 1, -1/3, 2/15, -17/315, 62/2835,
+// -1382/155925, 21844/6081075, -929569/638512875; the next term is under 1e-8), else
+// (1 - e^-2s) / ((1 + e^-2s) s), where e^-2s <= 0.37 keeps the difference well
+// conditioned; both are evaluated and one selected, so lanes do not diverge (about 3 ulp).
+// FP64: the device library's tanh, and the series' first two terms below 1e-4.
+__device__ __forceinline__ float tanh_ratio(float s)
+{
+    const float s2 = s * s;
+    float ser = fmaf(s2, -929569.f / 638512875.f, 21844.f / 6081075.f);
+    ser = fmaf(s2, ser, -1382.f / 155925.f);
+    ser = fmaf(s2, ser, 62.f / 2835.f);
+    ser = fmaf(s2, ser, -17.f / 315.f);
+    ser = fmaf(s2, ser, 2.f / 15.f);
+    ser = fmaf(s2, ser, -1.f / 3.f);
+    ser = fmaf(s2, ser, 1.f);
+    const float t = __expf(-2.f * s);
+    const float big = (1.f - t) / ((1.f + t) * s);
+    return s < 0.5f ? ser : big;
+}
+__device__ __forceinline__ double tanh_ratio(double s)
+{
+    return (s < 1e-4) ? 1.0 - s * s * (1.0 / 3.0) : tanh(s) / s;
+}
 __device__ __forceinline__ float m_log(float x) { return logf(x); }
 __device__ __forceinline__ double m_log(double x) { return log(x); }
 __device__ __forceinline__ void m_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
 __device__ __forceinline__ void m_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
 
-// sin(a)/a for the quaternion exponential
-__device__ __forceinline__ float sinc_q(float a)
+// sin(a)/a and cos(a) for the quaternion exponential.  FP32: one sine-cosine evaluation,
+// sin(a)/a from its series below a = 1e-2; FP64: the library's sin and cos.
+__device__ __forceinline__ void quat_exp(float a, float* sinc, float* c)
 {
+    float s;
+    m_sincos(a, &s, c);
     const float a2 = a * a;
-    return (a < 1e-2f) ? 1.f - a2 * (1.f / 6.f) + a2 * a2 * (1.f / 120.f) : sinf(a) / a;
+    *sinc = (a < 1e-2f) ? 1.f - a2 * (1.f / 6.f) + a2 * a2 * (1.f / 120.f) : s / a;
 }
-__device__ __forceinline__ double sinc_q(double a) { return (a > 0.0) ? sin(a) / a : 1.0; }
+__device__ __forceinline__ void quat_exp(double a, double* sinc, double* c)
+{
+    *sinc = (a > 0.0) ? sin(a) / a : 1.0;
+    *c = cos(a);
+}
 
 // ------------------------------------------------------------------------------
 // small vector algebra
@@ -309,8 +362,7 @@ __device__ __forceinline__ void contact_law(const ModelT<R>& M, R delta, V3<R> n
     const R Fn = M.ck * delta - M.cc * vn;
     const V3<R> vt = vrel - vn * n;
     const R s = m_sqrt(dot(vt, vt)) * M.inv_vs;
-    const R phi = (s < R(1e-4)) ? R(1) - s * s * R(1.0 / 3.0) : m_tanh(s) / s;
-    eta = M.cmu * m_max(Fn, R(0)) * M.inv_vs * phi;
+    eta = M.cmu * m_max(Fn, R(0)) * M.inv_vs * tanh_ratio(s);
     F = Fn * n - eta * vt;
 }
 
@@ -377,6 +429,54 @@ __device__ __forceinline__ void store_state(float* __restrict__ o, int leg, cons
     }
 }
 
+// The contact terms of base_contact below, arranged for fewer instructions: with
+// J = [-(r x), I] and g = [r x n; n]
+// the damping block is dt (eta J^T J + (c - eta) g g^T) and the right side gains
+// dt [r x F; F].  dt eta and dt (c - eta) are folded into the operands first, so each
+// entry is one or two fused multiply-adds.
+template <typename S>
+__device__ __forceinline__ void base_contact_folded(S eta, S c, V3<S> r, V3<S> n, V3<S> F, S dt, S* Q, S* rb)
+{
+    const V3<S> g0 = cross(r, n);
+    const S de = dt * eta, dce = dt * (c - eta);
+    const S ga[6] = {g0.x, g0.y, g0.z, n.x, n.y, n.z};
+    S gs[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) gs[i] = dce * ga[i];
+    const S rv[3] = {r.x, r.y, r.z};
+    const S er[3] = {de * r.x, de * r.y, de * r.z};
+    const S drr = de * dot(r, r);
+    // angular block: de (|r|^2 I - r r^T) + dce g0 g0^T
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            const S q = Q[s6(i, j)] + gs[i] * ga[j] - er[i] * rv[j];
+            Q[s6(i, j)] = (i == j) ? q + drr : q;
+        }
+    // coupling block: de [r x] + dce g0 n^T ([r x] = {{0, -rz, ry}, {rz, 0, -rx}, {-ry, rx, 0}})
+    Q[s6(0, 3)] += gs[0] * ga[3];
+    Q[s6(0, 4)] += gs[0] * ga[4] - er[2];
+    Q[s6(0, 5)] += gs[0] * ga[5] + er[1];
+    Q[s6(1, 3)] += gs[1] * ga[3] + er[2];
+    Q[s6(1, 4)] += gs[1] * ga[4];
+    Q[s6(1, 5)] += gs[1] * ga[5] - er[0];
+    Q[s6(2, 3)] += gs[2] * ga[3] - er[1];
+    Q[s6(2, 4)] += gs[2] * ga[4] + er[0];
+    Q[s6(2, 5)] += gs[2] * ga[5];
+    // linear block: de I + dce n n^T
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            const S q = Q[s6(3 + i, 3 + j)] + gs[3 + i] * ga[3 + j];
+            Q[s6(3 + i, 3 + j)] = (i == j) ? q + de : q;
+        }
+    const V3<S> m = cross(r, F);
+    rb[0] += dt * m.x; rb[1] += dt * m.y; rb[2] += dt * m.z;
+    rb[3] += dt * F.x; rb[4] += dt * F.y; rb[5] += dt * F.z;
+}
+
 // contribution of a contact at trunk-frame point r (normal n, force F, secant eta) to
 // the base rows: 6x6 damping block and generalized force
 template <typename R>
@@ -405,6 +505,13 @@ __device__ __forceinline__ void base_contact(R eta, R c, V3<R> r, V3<R> n, V3<R>
     const V3<R> m = cross(r, F);
     rb[0] += dt * m.x; rb[1] += dt * m.y; rb[2] += dt * m.z;
     rb[3] += dt * F.x; rb[4] += dt * F.y; rb[5] += dt * F.z;
+}
+
+// FP32: the folded form above (FP64 keeps the original order of operations)
+__device__ __forceinline__ void base_contact(float eta, float c, V3<float> r, V3<float> n, V3<float> F, float dt,
+                                             float* Q, float* rb)
+{
+    base_contact_folded(eta, c, r, n, F, dt, Q, rb);
 }
 
 // 3x3 SPD Cholesky (lower) and solves
@@ -591,8 +698,9 @@ __device__ __forceinline__ void quat_step(R& qw, R& qx, R& qy, R& qz, V3<R> w, R
 {
     const V3<R> ph = (R(0.5) * dt) * w;
     const R a = m_sqrt(dot(ph, ph));
-    const R sc = sinc_q(a);
-    const R dw = m_cos(a), dx = sc * ph.x, dy = sc * ph.y, dz = sc * ph.z;
+    R sc, dw;
+    quat_exp(a, &sc, &dw);
+    const R dx = sc * ph.x, dy = sc * ph.y, dz = sc * ph.z;
     const R nw = qw * dw - qx * dx - qy * dy - qz * dz;
     const R nx = qw * dx + qx * dw + qy * dz - qz * dy;
     const R ny = qw * dy - qx * dz + qy * dw + qz * dx;

@@ -87,88 +87,6 @@ __device__ __forceinline__ Pose<R> sel_pose(bool c, const Pose<R>& a, const Pose
     return o;
 }
 
-// ---- elementary functions of the FP32 geometry type, written out here without branches
-// (the device library's sincosf and tanhf carry a large-argument path and branches that
-// cost a wave about 45 and 40 instructions); the FP64 type keeps the library's.
-//
-// sine and cosine: x = k pi/2 + r with k = rint(2x/pi) and pi/2 taken in two parts (the
-// float nearest pi/2 and the remainder), so r is exact to a few ulps for the joint angles
-// and rotation angles met here (|x| up to a few hundred); then the Taylor series of sin
-// and cos on |r| <= pi/4 up to r^9 and r^10 (truncation below 3e-9 relative) and the
-// quadrant's swap and signs.
-__device__ __forceinline__ void sincos_g(float x, float* sn, float* cs)
-{
-    const float k = rintf(x * 0.63661977236758134f);
-    float r = fmaf(-k, 1.57079637050628662f, x);
-    r = fmaf(-k, -4.37113900018624283e-8f, r);
-    const float r2 = r * r;
-    const float sp = r + r * r2 * fmaf(r2, fmaf(r2, fmaf(r2, 1.f / 362880.f, -1.f / 5040.f), 1.f / 120.f), -1.f / 6.f);
-    const float cp =
-        fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.f / 3628800.f, 1.f / 40320.f), -1.f / 720.f), 1.f / 24.f), -0.5f),
-             1.f);
-    const int q = int(k) & 3;
-    const float s0 = (q & 1) ? cp : sp, c0 = (q & 1) ? sp : cp;
-    *sn = (q & 2) ? -s0 : s0;
-    *cs = ((q + 1) & 2) ? -c0 : c0;
-}
-__device__ __forceinline__ void sincos_g(double x, double* sn, double* cs) { m_sincos(x, sn, cs); }
-
-// tanh(s) / s for s >= 0 (the friction law's secant factor): below s = 1/2 its Taylor
-// series in s^2 through s^14 (coefficients 1, -1/3, 2/15, -17/315, 62/2835,
-// -1382/155925, 21844/6081075, -929569/638512875; the next term is under 1e-8), else
-// (1 - e^-2s) / ((1 + e^-2s) s), where e^-2s <= 0.37 keeps the difference well
-// conditioned.  Both are evaluated and one is selected, so the lanes do not diverge.
-__device__ __forceinline__ float tanh_ratio(float s)
-{
-    const float s2 = s * s;
-    float ser = fmaf(s2, -929569.f / 638512875.f, 21844.f / 6081075.f);
-    ser = fmaf(s2, ser, -1382.f / 155925.f);
-    ser = fmaf(s2, ser, 62.f / 2835.f);
-    ser = fmaf(s2, ser, -17.f / 315.f);
-    ser = fmaf(s2, ser, 2.f / 15.f);
-    ser = fmaf(s2, ser, -1.f / 3.f);
-    ser = fmaf(s2, ser, 1.f);
-    const float t = __expf(-2.f * s);
-    const float big = (1.f - t) / ((1.f + t) * s);
-    return s < 0.5f ? ser : big;
-}
-__device__ __forceinline__ double tanh_ratio(double s)
-{
-    return (s < 1e-4) ? 1.0 - s * s * (1.0 / 3.0) : m_tanh(s) / s;
-}
-
-// the penalty contact law of mppi_device.h with the secant factor above
-template <typename R>
-__device__ __forceinline__ void contact_law_g(const ModelT<R>& M, R delta, V3<R> n, V3<R> vrel, V3<R>& F, R& eta)
-{
-    const R vn = dot(n, vrel);
-    const R Fn = M.ck * delta - M.cc * vn;
-    const V3<R> vt = vrel - vn * n;
-    const R s = m_sqrt(dot(vt, vt)) * M.inv_vs;
-    eta = M.cmu * m_max(Fn, R(0)) * M.inv_vs * tanh_ratio(s);
-    F = Fn * n - eta * vt;
-}
-
-// the body-frame exponential-map quaternion step of mppi_device.h with one sine-cosine
-// evaluation: sin(a)/a from its series below a = 1e-2
-template <typename R>
-__device__ __forceinline__ void quat_step_g(R& qw, R& qx, R& qy, R& qz, V3<R> w, R dt)
-{
-    const V3<R> ph = (R(0.5) * dt) * w;
-    const R a = m_sqrt(dot(ph, ph));
-    R sa, ca;
-    sincos_g(a, &sa, &ca);
-    const R a2 = a * a;
-    const R sc = (a < R(1e-2)) ? R(1) - a2 * R(1.0 / 6.0) + a2 * a2 * R(1.0 / 120.0) : sa / a;
-    const R dw = ca, dx = sc * ph.x, dy = sc * ph.y, dz = sc * ph.z;
-    const R nw = qw * dw - qx * dx - qy * dy - qz * dz;
-    const R nx = qw * dx + qx * dw + qy * dz - qz * dy;
-    const R ny = qw * dy - qx * dz + qy * dw + qz * dx;
-    const R nz = qw * dz + qx * dy - qy * dx + qz * dw;
-    const R inv = R(1) / m_sqrt(nw * nw + nx * nx + ny * ny + nz * nz);
-    qw = nw * inv; qx = nx * inv; qy = ny * inv; qz = nz * inv;
-}
-
 template <typename T, typename U>
 __device__ __forceinline__ V3<T> cv(V3<U> a)
 {
@@ -178,54 +96,6 @@ __device__ __forceinline__ V3<T> cv(V3<U> a)
 // a contact on the leg's calf with weight wgt (1: applied, 0: nothing added).  The contact
 // velocity and the law are evaluated in the geometry type R; the force and damping terms
 // on the trunk's base rows and on the leg's joint rows accumulate in the system type S.
-// The contact terms of a body's 6x6 system (the same quantities as base_contact in
-// mppi_device.h, arranged for fewer instructions): with J = [-(r x), I] and g = [r x n; n]
-// the damping block is dt (eta J^T J + (c - eta) g g^T) and the right side gains
-// dt [r x F; F].  dt eta and dt (c - eta) are folded into the operands first, so each
-// entry is one or two fused multiply-adds.
-template <typename S>
-__device__ __forceinline__ void base_contact_g(S eta, S c, V3<S> r, V3<S> n, V3<S> F, S dt, S* Q, S* rb)
-{
-    const V3<S> g0 = cross(r, n);
-    const S de = dt * eta, dce = dt * (c - eta);
-    const S ga[6] = {g0.x, g0.y, g0.z, n.x, n.y, n.z};
-    S gs[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) gs[i] = dce * ga[i];
-    const S rv[3] = {r.x, r.y, r.z};
-    const S er[3] = {de * r.x, de * r.y, de * r.z};
-    const S drr = de * dot(r, r);
-    // angular block: de (|r|^2 I - r r^T) + dce g0 g0^T
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) {
-            const S q = Q[s6(i, j)] + gs[i] * ga[j] - er[i] * rv[j];
-            Q[s6(i, j)] = (i == j) ? q + drr : q;
-        }
-    // coupling block: de [r x] + dce g0 n^T ([r x] = {{0, -rz, ry}, {rz, 0, -rx}, {-ry, rx, 0}})
-    Q[s6(0, 3)] += gs[0] * ga[3];
-    Q[s6(0, 4)] += gs[0] * ga[4] - er[2];
-    Q[s6(0, 5)] += gs[0] * ga[5] + er[1];
-    Q[s6(1, 3)] += gs[1] * ga[3] + er[2];
-    Q[s6(1, 4)] += gs[1] * ga[4];
-    Q[s6(1, 5)] += gs[1] * ga[5] - er[0];
-    Q[s6(2, 3)] += gs[2] * ga[3] - er[1];
-    Q[s6(2, 4)] += gs[2] * ga[4] + er[0];
-    Q[s6(2, 5)] += gs[2] * ga[5];
-    // linear block: de I + dce n n^T
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) {
-            const S q = Q[s6(3 + i, 3 + j)] + gs[3 + i] * ga[3 + j];
-            Q[s6(3 + i, 3 + j)] = (i == j) ? q + de : q;
-        }
-    const V3<S> m = cross(r, F);
-    rb[0] += dt * m.x; rb[1] += dt * m.y; rb[2] += dt * m.z;
-    rb[3] += dt * F.x; rb[4] += dt * F.y; rb[5] += dt * F.z;
-}
-
 template <typename R, typename S>
 __device__ __forceinline__ void leg_contact_w(const ModelT<R>& M, const LegGeo<R>& G, V3<R> vb, V3<R> w,
                                               const R qd[3], R delta, V3<R> n, V3<R> r, V3<R> vo, S dt, R wgt, S* Q,
@@ -234,13 +104,13 @@ __device__ __forceinline__ void leg_contact_w(const ModelT<R>& M, const LegGeo<R
     const V3<R> ex = v3(R(1), R(0), R(0));
     const V3<R> ja = cross(ex, r - G.h), jf = cross(G.ey, r - G.h), jk = cross(G.ey, r - G.pk);
     const V3<R> vc = vb + cross(w, r) + qd[0] * ja + qd[1] * jf + qd[2] * jk - vo;
-    contact_law_g(M, delta, n, vc, F, eta);
+    contact_law(M, delta, n, vc, F, eta);
     F = wgt * F;
     eta = wgt * eta;
     const S e = S(eta), cw = S(wgt) * S(M.cc);
     const S ce = cw - e;
     const V3<S> rs = cv<S>(r), ns = cv<S>(n), Fs = cv<S>(F);
-    base_contact_g(e, cw, rs, ns, Fs, dt, Q, rb);
+    base_contact_folded(e, cw, rs, ns, Fs, dt, Q, rb);
     // the leg's rows: dt (e J_l^T J + ce g_l g^T) with g_l = J_l^T n, dt e and dt ce folded
     // into the operands
     const S de = dt * e;
@@ -270,7 +140,7 @@ __device__ __forceinline__ void leg_contact_w(const ModelT<R>& M, const LegGeo<R
 template <typename R, typename S>
 __device__ __forceinline__ void body_contact(R eta, R c, V3<R> r, V3<R> n, V3<R> F, S dt, S* Q, S* rb)
 {
-    base_contact_g(S(eta), S(c), cv<S>(r), cv<S>(n), cv<S>(F), dt, Q, rb);
+    base_contact_folded(S(eta), S(c), cv<S>(r), cv<S>(n), cv<S>(F), dt, Q, rb);
 }
 
 // ------------------------------------------------------------------------------
@@ -303,7 +173,7 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
     R sn, cs;
     {
         const R ang = (sub == 0) ? lg.q[0] : (sub == 1) ? lg.q[1] : lg.q[1] + lg.q[2];
-        sincos_g(ang, &sn, &cs);
+        m_sincos(ang, &sn, &cs);
     }
     const R sa = dpp<0x00>(sn), ca = dpp<0x00>(cs);
     const R sf = dpp<0x55>(sn), cf = dpp<0x55>(cs);
@@ -502,13 +372,13 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
             V3<R> nw;
             if (terrain<SCENE>(MR, hf, pw, R(0), delta, nw)) {
                 const V3<R> n = mulT(Rm, nw);
-                contact_law_g(MR, delta, n, vb + cross(w, rloc), F, eta);
+                contact_law(MR, delta, n, vb + cross(w, rloc), F, eta);
                 body_contact(eta, MR.cc, rloc, n, F, dt, Q, rb);
             }
             if constexpr (SCENE == 2) {
                 if (point_aabox(pw - v3(MR.sb_cx, MR.sb_cy, MR.sb_cz), v3(MR.sb_hx, MR.sb_hy, MR.sb_hz), delta, nw)) {
                     const V3<R> n = mulT(Rm, nw);
-                    contact_law_g(MR, delta, n, vb + cross(w, rloc), F, eta);
+                    contact_law(MR, delta, n, vb + cross(w, rloc), F, eta);
                     body_contact(eta, MR.cc, rloc, n, F, dt, Q, rb);
                 }
             }
@@ -548,7 +418,7 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
                 const R wgt = on ? R(1) : R(0);
                 const R wq = pair ? wgt : R(0);
                 const V3<R> n = on ? selv(pair, nPw, nG) : v3(R(0), R(0), R(1));
-                contact_law_g(MR, on ? (pair ? dP : dG) : R(0), n, on ? selv(pair, vP - vQ, vP) : zero, F, eta);
+                contact_law(MR, on ? (pair ? dP : dG) : R(0), n, on ? selv(pair, vP - vQ, vP) : zero, F, eta);
                 F = wgt * F;
                 eta = wgt * eta;
                 // P's side in P's frame (force +F), Q's side in Q's frame (force -F)
@@ -655,7 +525,7 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
     b.vw = cv<R>(cv<S>(b.vw) + mul(Rs, v3(rb[3], rb[4], rb[5])));
     b.p = b.p + dtr * b.vw;
     if constexpr (SCENE != 3) {
-        quat_step_g(b.qw, b.qx, b.qy, b.qz, b.w, dtr);
+        quat_step(b.qw, b.qx, b.qy, b.qz, b.w, dtr);
     } else {
         M33<S> Rbs;
 #pragma unroll
@@ -666,7 +536,7 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
         // one quaternion step per lane: the trunk's on even lanes, the box's on odd lanes
         const bool odd = (g & 1) != 0;
         R q[4] = {sel(odd, bx.qw, b.qw), sel(odd, bx.qx, b.qx), sel(odd, bx.qy, b.qy), sel(odd, bx.qz, b.qz)};
-        quat_step_g(q[0], q[1], q[2], q[3], selv(odd, bx.w, b.w), dtr);
+        quat_step(q[0], q[1], q[2], q[3], selv(odd, bx.w, b.w), dtr);
         R o[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) o[i] = dpp<0xB1>(q[i]);
