@@ -1,3 +1,10 @@
+// Algorithmic flops of one rollout-step: the device step (mppi_device.h) compiled on the
+// host with a counting number type.  Adds, multiplies, divisions, square roots and
+// transcendental calls count one each.  Build (the runtime header is a host stand-in):
+//   mkdir -p shim/hip && echo '#include "flop_count_stub.h"' > shim/hip/hip_runtime.h
+//   g++ -O1 -std=c++17 -I shim -I paper_2409_10469_amd/csrc -I include \
+//       paper_2409_10469_amd/csrc/flop_count.cpp -o flop_count && ./flop_count <scene>
+// tests/test_roofline_counts.py builds it and checks the counts the bench uses.
 #include <cstdio>
 #include <algorithm>
 #include <cmath>
@@ -35,6 +42,13 @@ inline CountD m_cos(CountD x) { ++n_trans; return std::cos(x.v); }
 inline void m_sincos(CountD x, CountD* s, CountD* c) { n_trans += 2; *s = std::sin(x.v); *c = std::cos(x.v); }
 inline CountD m_log(CountD x) { ++n_trans; return std::log(x.v); }
 inline CountD sinc_q(CountD a) { ++n_trans; ++n_div; return a.v > 0 ? std::sin(a.v) / a.v : 1.0; }
+// the friction factor tanh(s)/s and the quaternion exponential's sin(a)/a and cos(a)
+inline CountD tanh_ratio(CountD s) { ++n_trans; ++n_div; return s.v > 0 ? std::tanh(s.v) / s.v : 1.0; }
+inline void quat_exp(CountD a, CountD* sinc, CountD* c)
+{
+    *sinc = sinc_q(a);
+    *c = m_cos(a);
+}
 template <int C> inline CountD dpp(CountD v) { return v; }
 #include "mppi_device.h"
 using namespace mppi;

@@ -16,6 +16,7 @@ inline int __double2loint(double d) { int64_t i; std::memcpy(&i, &d, 8); return 
 inline int __double2hiint(double d) { int64_t i; std::memcpy(&i, &d, 8); return (int)(i >> 32); }
 inline double __hiloint2double(int hi, int lo) { int64_t i = ((int64_t)hi << 32) | (uint32_t)lo; double d; std::memcpy(&d, &i, 8); return d; }
 inline int __builtin_amdgcn_update_dpp(int, int v, int, int, int, bool) { return v; }
+inline float __expf(float x) { return expf(x); }
 inline void sincospif(float x, float* s, float* c) { *s = sinf(M_PI * x); *c = cosf(M_PI * x); }
 inline void sincospi(double x, double* s, double* c) { *s = sin(M_PI * x); *c = cos(M_PI * x); }
 using std::min; using std::max;
