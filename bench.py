@@ -324,7 +324,9 @@ def learned_vs_plain(args):
     """Bounded learned-proposal comparison (the full one is --workload proposal_training):
     2e5 closed-loop pairs from the flat and heightfield walks, 6 Adam epochs, then the
     heightfield walk (v_ref 0.5, 5 held-out seeds x 100 steps) with plain MPPI at K in
-    {256, 512, 1024} against the proposal at 256 samples (gated and ungated)."""
+    {256, 512, 1024, 2048, 4096} against the proposal at 256 samples with plain MPPI at
+    K = 1024 as the fallback (cost gate, best-sample gate, best-sample gate with the
+    fallback rolled out concurrently) and ungated."""
     from paper_2409_10469_amd import binding as B
     from paper_2409_10469_amd import proposal as PR
     log = lambda m: print(m, file=sys.stderr, flush=True)
@@ -334,15 +336,16 @@ def learned_vs_plain(args):
     pol = B.Policy(max_batch=4096, seed=args.seed)
     pol.set_normalization(*PR.normalization(data, tr))
     PR.train(pol, data, tr, epochs=6, batch=4096, lr=1e-3, seed=args.seed, held=ho, log=log)
-    ev = PR.evaluate(pol, K_plain=(256, 512, 1024), K_learned=1024, seeds=range(100, 105), steps=100, log=log)
+    ev = PR.evaluate(pol, K_plain=(256, 512, 1024, 2048, 4096), K_learned=1024, seeds=range(100, 105), steps=100,
+                     log=log)
     res = {"task": "heightfield walk, v_ref 0.5, closed loop", "seeds": ev["seeds"], "steps": ev["steps"],
            "training": "2e5 pairs, 6 epochs", "seconds": time.perf_counter() - t0,
            "plain": {str(k): {"episode_cost": v["mean"], "ci95": v["ci95"], "samples_per_step": k,
                               "latency_p50_ms": v["latency_ms"]["p50"], "latency_p99_ms": v["latency_ms"]["p99"]}
                      for k, v in ev["plain"].items()}}
-    for g in ("cost", "best", "none"):
+    for g in ("cost", "best", "best-concurrent", "none"):
         e = ev["learned_" + g]
-        res["learned_gate_" + g] = {"episode_cost": e["mean"], "ci95": e["ci95"], "k_prop": e["k_prop"],
+        res["learned_gate_" + g.replace("-", "_")] = {"episode_cost": e["mean"], "ci95": e["ci95"], "k_prop": e["k_prop"],
                                     "samples_per_step": e["samples_per_step"], "acceptance": e["acceptance"],
                                     "latency_p50_ms": e["latency_ms"]["p50"], "latency_p99_ms": e["latency_ms"]["p99"],
                                     "smallest_plain_K_matching": e["smallest_plain_K_matching"],
@@ -472,11 +475,12 @@ def bench_proposal(args):
                             "episode_cost_ci95": ev["learned_" + g]["ci95"],
                             "smallest_plain_K_matching": ev["learned_" + g]["smallest_plain_K_matching"],
                             "sample_ratio": ev["learned_" + g]["sample_ratio"]}
-                        for g in ("cost", "best", "none")},
+                        for g in ("cost", "best", "best-concurrent", "none")},
             "gates": "cost: the proposal's K/4 samples are rolled out, then the plain step's K samples only when "
                      "the proposal's centre costs more than the nominal (fallback); best: the same with the least "
-                     "cost over the proposal's samples other than the nominal; none: always the K/4 proposal "
-                     "samples alone, nominal kept as sample 1"},
+                     "cost over the proposal's samples other than the nominal; best-concurrent: the best-sample "
+                     "gate with both sample sets rolled out in one launch on every step; none: always the K/4 "
+                     "proposal samples alone, nominal kept as sample 1"},
         "batched_equal_cost": evb,
         "epoch_seconds": train_s / max(len(hist), 1), "train_steps": train_steps,
         "generation": {"seconds": gen_s, "batch_seconds": st["seconds"], "episodes": st["episodes"],

@@ -139,16 +139,27 @@ mppi_status mppi_policy_pairs(int n_rec, int steps, int n_knots, const float *d_
  * Then, as in mppi_step, the first control goes to d_u0_out, the nominal is shifted and
  * the step counter advances.  The decision is made on the device, so the call does not
  * synchronise.  With the lane-split rollout the plain K samples are rolled out only on a
- * fallback (after the proposal and the gate, on the bound stream); with the quad rollout
- * they are rolled out beside the proposal on an internal stream that mppi_bind creates.
- * MPPI_PROPOSAL_GATE_NONE always takes the proposal branch (the nominal still competes as
- * sample 1) and rolls out only the proposal.  2 <= k_prop <= K.  The proposal steps use
- * the running cost (EINVAL for a controller created with MPPI_COST_TRACKING). */
+ * fallback (after the proposal and the gate, on the bound stream): a step rolls out
+ * k_prop samples, or k_prop + K one rollout after the other when it falls back.  With
+ * the quad rollout the plain K samples are rolled out beside the proposal's, on an
+ * internal stream that mppi_bind creates.  With MPPI_PROPOSAL_CONCURRENT added to the gate
+ * (either rollout) one rollout launch covers both sets on every step: k_prop + K samples
+ * in about one rollout's time, whatever the process's other streams.  The plain samples
+ * are then the same draws taken as offsets from the proposal's centre,
+ * theta_n = c + ((mu - c) + sigma eps_n) with the offset rounded once in FP32 (the
+ * workspace holds both sets): the gate decides as without the flag, an accepted step is
+ * the same bit for bit, and a fallback step agrees within that rounding.
+ * MPPI_PROPOSAL_GATE_NONE always takes the proposal
+ * branch (the nominal still competes as sample 1) and rolls out only the proposal.
+ * 2 <= k_prop <= K.  The proposal steps use the running cost (EINVAL for a controller
+ * created with MPPI_COST_TRACKING). */
 enum {
     MPPI_PROPOSAL_GATE_COST = 0, /* proposal only if its centre's cost is finite and not above the nominal's */
     MPPI_PROPOSAL_GATE_NONE = 1, /* always the proposal's k_prop samples */
-    MPPI_PROPOSAL_GATE_BEST = 2  /* proposal only if its best sample other than the nominal is finite and not
+    MPPI_PROPOSAL_GATE_BEST = 2, /* proposal only if its best sample other than the nominal is finite and not
                                     above the nominal's cost */
+    MPPI_PROPOSAL_CONCURRENT = 4 /* added to GATE_COST or GATE_BEST: the fallback's samples are rolled out with
+                                    the proposal's in one launch on every step (latency of one rollout) */
 };
 mppi_status mppi_step_proposal(mppi_ctx *ctx, const float *d_x0, const float *d_center, const float *d_sd,
                                int k_prop, int gate, float *d_u0_out);
@@ -165,9 +176,9 @@ mppi_status mppi_proposal_stats(mppi_ctx *ctx, int *accepted, int *steps);
 
 /* ---- batched serving side ---------------------------------------------------------
  * Makes instance id of a batch (mppi.h) take its samples from the policy, ungated: each
- * mppi_batch_step then runs, for all such instances together and before the batch's
- * graph, the features of each one's current state, one forward pass over them as a
- * batch, and the head; the instance's K admitted samples are then theta_0 = centre,
+ * mppi_batch_step then runs, for all such instances together and as the first nodes of
+ * the batch's graph, the features of each one's current state, one forward pass over
+ * them as a batch, and the head; the instance's K admitted samples are then theta_0 = centre,
  * theta_1 = its shifted nominal, theta_n = centre + sd * eps_n (its own Philox counters,
  * as mppi_step_proposal draws them), and Eq. 1 / Eq. 2 over them give the new nominal,
  * as mppi_step_proposal does with MPPI_PROPOSAL_GATE_NONE.  The admitted sigma is the

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(PKG, "libmppi.so")
 
 OK, WARN_ALL_NONFINITE, EINVAL, ENOMEM, EHIP, ESTATE = 0, 1, -1, -2, -3, -6
 ARITH = {"fp64": 0, "fp32": 1, "mixed": 2}
-GATE = {"cost": 0, "none": 1, "best": 2}
+# proposal gates (include/mppi_policy.h); "-concurrent" rolls out the fallback beside the proposal
+GATE = {"cost": 0, "none": 1, "best": 2, "cost-concurrent": 4, "best-concurrent": 6}
 
 
 class MppiError(RuntimeError):

@@ -420,8 +420,10 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     c->off_cmd = o; o = align256(o + sizeof(float) * 8);
     c->off_center = o; o = align256(o + sizeof(float) * c->D);
     c->off_sd = o; o = align256(o + sizeof(float) * c->D);
-    c->off_costs_p = o; o = align256(o + sizeof(float) * p->K);
-    c->off_eps_p = o; o = align256(o + sizeof(float) * (size_t)c->D * p->K);
+    // room for both sample sets of the concurrent gated step (k_prop <= K proposal samples,
+    // then the K plain ones)
+    c->off_costs_p = o; o = align256(o + sizeof(float) * 2 * p->K);
+    c->off_eps_p = o; o = align256(o + sizeof(float) * (size_t)c->D * 2 * p->K);
     c->off_pstats = o; o = align256(o + sizeof(int) * 2);
     c->off_gate = o; o = align256(o + sizeof(float) * 4);
     if (p->cost == MPPI_COST_TRACKING) {
@@ -628,11 +630,21 @@ mppi_status mppi_update(mppi_ctx* c, const float* d_costs, const float* d_eps, f
 // a plain step with K samples around the nominal otherwise.  With the lane-split rollout
 // the gate is decided on the device right after the proposal rollout and the plain
 // rollout runs only on a fallback (it returns at once when the proposal was taken), so a
-// step rolls out k_prop + K samples only when it falls back; with the quad rollout the
-// plain rollout runs beside the proposal's on an internal stream.  The update kernel
+// step rolls out k_prop + K samples only when it falls back.  With the gate's
+// MPPI_PROPOSAL_CONCURRENT bit one rollout launch covers both sets on every step; with
+// the quad rollout the plain rollout runs beside the proposal's on an internal stream;
+// the gate kernel follows both.  The update kernel
 // reads the gate costs and updates over whichever set was chosen; no host round trip.
 // Accepted: mu' = c + sum w_n e_n / sum w_n, the weighted mean of theta (centre c, unit
 // scale).  Ungated: the proposal rollout alone.
+// GATE_COST, GATE_NONE or GATE_BEST, the gated two with the CONCURRENT bit allowed
+static bool valid_gate(int gate)
+{
+    const int g = gate & ~MPPI_PROPOSAL_CONCURRENT;
+    if (g != MPPI_PROPOSAL_GATE_COST && g != MPPI_PROPOSAL_GATE_NONE && g != MPPI_PROPOSAL_GATE_BEST) return false;
+    return !((gate & MPPI_PROPOSAL_CONCURRENT) && g == MPPI_PROPOSAL_GATE_NONE);
+}
+
 static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int kp,
                                  int gate, float* d_u0_out)
 {
@@ -659,16 +671,37 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
     a.costs = costs_p;
     a.samples_per_block = 16;
     a.direct = c->p.basis == MPPI_BASIS_DIRECT;
+    const bool concurrent = (gate & MPPI_PROPOSAL_CONCURRENT) != 0;
+    gate &= ~MPPI_PROPOSAL_CONCURRENT;
     const bool gated = gate == MPPI_PROPOSAL_GATE_COST || gate == MPPI_PROPOSAL_GATE_BEST;
     const int best = gate == MPPI_PROPOSAL_GATE_BEST;
     float* costs = wsf(c, c->off_costs);
-    if (gated && c->split) {
+    if (gated && c->split && !concurrent) {
         // proposal rollout, the gate, then the plain rollout (skipped when the gate takes
         // the proposal), all on the bound stream
         if ((s = hip_check(c, launch_roll(c, Pp, a, c->stream), "proposal rollout launch")) ||
             (s = hip_check(c, prop::launch_gate(kp, costs_p, best, g, skip, c->stream), "gate launch")) ||
             (s = rollout(c, d_x0, nullptr, costs, nullptr, skip)))
             return s;
+    } else if (gated && concurrent) {
+        // one rollout launch over both sample sets: the proposal's kp samples as above, then
+        // the plain step's K samples as offsets from the proposal's centre
+        // (theta = c + (mu - c) + sigma eps, drawn from the plain step's counters); the gate
+        // reads the first kp costs, the update the rest on a fallback
+        const mppi::DevParams P = dev_params(c);
+        float* ep = e + (size_t)kp * c->D;
+        mppi::DevParams P2 = Pp;
+        P2.K = kp + c->p.K;
+        a.costs = costs_p;
+        a.input_status = (int*)wsf(c, c->off_status) + 1;
+        if ((s = hip_check(c, mppi::launch_sample(P, c->D, ep, nullptr, c->stream), "plain noise launch")) ||
+            (s = hip_check(c, prop::launch_pair_noise(c->p.K, c->D, c->p.sigma, ep, wsf(c, c->off_mu), d_center,
+                                                      wsf(c, c->off_eps), c->stream),
+                           "plain offsets launch")) ||
+            (s = hip_check(c, launch_roll(c, P2, a, c->stream), "paired rollout launch")) ||
+            (s = hip_check(c, prop::launch_gate(kp, costs_p, best, g, skip, c->stream), "gate launch")))
+            return s;
+        costs = costs_p + kp;
     } else if (gated) {
         if (!c->side) return fail(c, MPPI_ESTATE, "no side stream (bind the controller again)");
         if ((s = hip_check(c, hipEventRecord(c->ev_fork, c->stream), "fork record")) ||
@@ -852,8 +885,7 @@ mppi_status mppi_step_proposal(mppi_ctx* c, const float* d_x0, const float* d_ce
     if ((s = need_bound(c))) return s;
     if (!d_x0 || !d_center || !d_sd || !d_u0_out) return fail(c, MPPI_EINVAL, "null argument");
     if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
-    if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE && gate != MPPI_PROPOSAL_GATE_BEST)
-        return fail(c, MPPI_EINVAL, "unknown gate");
+    if (!valid_gate(gate)) return fail(c, MPPI_EINVAL, "unknown gate");
     if (c->p.cost != MPPI_COST_RUNNING) return fail(c, MPPI_EINVAL, "the proposal step uses the running cost");
     return step_proposal(c, d_x0, d_center, d_sd, k_prop, gate, d_u0_out);
 }
@@ -871,8 +903,7 @@ mppi_status mppi_set_proposal(mppi_ctx* c, mppi_policy* pol, int k_prop, int gat
     if (c->p.cost != MPPI_COST_RUNNING) return fail(c, MPPI_EINVAL, "the proposal step uses the running cost");
     if (k_prop < 2 || k_prop > c->p.K) return fail(c, MPPI_EINVAL, "k_prop must be in [2, K]");
     if (!cmd || !origin_xy) return fail(c, MPPI_EINVAL, "null command or origin");
-    if (gate != MPPI_PROPOSAL_GATE_COST && gate != MPPI_PROPOSAL_GATE_NONE && gate != MPPI_PROPOSAL_GATE_BEST)
-        return fail(c, MPPI_EINVAL, "unknown gate");
+    if (!valid_gate(gate)) return fail(c, MPPI_EINVAL, "unknown gate");
     if (!(c->p.sigma > 0.f)) return fail(c, MPPI_EINVAL, "the proposal needs sigma > 0 (upper std clamp)");
     for (int i = 0; i < 3; ++i) c->cmd_origin[i] = cmd[i];
     c->cmd_origin[3] = origin_xy[0];

@@ -8,6 +8,8 @@
 //                           instances of a batch, one row per instance
 //   gate_kernel           - the fallback decision of a gated proposal step from the
 //                           proposal's costs, before the plain samples are rolled out
+//   pair_noise_kernel     - the plain step's samples as offsets from the proposal's centre,
+//                           so that one rollout launch covers both sample sets
 #include <hip/hip_runtime.h>
 
 #include "mppi_device.h"
@@ -61,6 +63,33 @@ __global__ __launch_bounds__(256) void gate_kernel(int Kp, const float* __restri
 hipError_t launch_gate(int Kp, const float* costs_p, int best, float* g, int* skip, hipStream_t st)
 {
     hipLaunchKernelGGL(gate_kernel, dim3(1), dim3(256), 0, st, Kp, costs_p, best, g, skip);
+    return hipGetLastError();
+}
+
+// e (K x D) holds the plain step's eps_n on entry (the sampler's order: e[n D + d]); on
+// exit theta_n = c + e_n is the plain sample mu + sigma eps_n (mu itself for n = 0, the
+// nominal), with (mu - c) + sigma eps_n rounded once, and eps_n is stored to
+// eps_out[d K + n], where the update reads the plain step's noise
+__global__ __launch_bounds__(256) void pair_noise_kernel(int K, int D, float sigma, float* __restrict__ e,
+                                                         const float* __restrict__ nominal,
+                                                         const float* __restrict__ center,
+                                                         float* __restrict__ eps_out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= K * D) return;
+    const int n = i / D, d = i - n * D;
+    const float eps = e[i];
+    const float off = nominal[d] - center[d];
+    e[i] = n == 0 ? off : fmaf(sigma, eps, off);
+    eps_out[(size_t)d * K + n] = eps;
+}
+
+hipError_t launch_pair_noise(int K, int D, float sigma, float* e, const float* nominal, const float* center,
+                             float* eps_out, hipStream_t st)
+{
+    const long n = (long)K * D;
+    hipLaunchKernelGGL(pair_noise_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, K, D, sigma, e,
+                       nominal, center, eps_out);
     return hipGetLastError();
 }
 

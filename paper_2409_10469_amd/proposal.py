@@ -235,7 +235,7 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384),
         log(f"  plain K={K}: episode cost {np.mean(costs):.3f}, step latency p50 {np.percentile(lat, 50):.3f} "
             f"p99 {np.percentile(lat, 99):.3f} ms")
     kp = K_learned // ratio
-    for gate in ("cost", "best", "none"):
+    for gate in ("cost", "best", "best-concurrent", "none"):
         lat = []
         res = [episode(model, dict(p, K=K_learned), s, steps, policy=policy, k_prop=kp, arith=arith, gate=gate,
                        lat=lat) for s in seeds]
@@ -243,8 +243,14 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384),
         acc = sum(r[2] for r in res)
         n = sum(r[3] for r in res)
         # a gated step on the lane-split rollout rolls out the proposal and, only when the
-        # gate falls back, the plain step's K samples; the ungated step the proposal only
-        samples = float(kp + (1.0 - acc / max(n, 1)) * K_learned) if gate != "none" else float(kp)
+        # gate falls back, the plain step's K samples; the concurrent gate both on every
+        # step (beside each other); the ungated step the proposal only
+        if gate == "none":
+            samples = float(kp)
+        elif gate.endswith("-concurrent"):
+            samples = float(kp + K_learned)
+        else:
+            samples = float(kp + (1.0 - acc / max(n, 1)) * K_learned)
         out["learned_" + gate] = dict(mean=float(np.mean(costs)), ci95=ci95(costs), costs=costs, k_prop=kp,
                                       K_fallback=K_learned,
                                       accepted=acc, steps=n, acceptance=acc / max(n, 1), samples_per_step=samples,

@@ -47,6 +47,9 @@ static float* dev(size_t n)
 
 // robot and scenes of the synthetic workloads (FP32 values on both sides)
 static const float kTrunk[3] = {0.38f, 0.094f, 0.114f};
+// the static box of scene 2: centre and half extents (set per case)
+static float g_sbox[6] = {0.71f, 0.f, 0.15f, 0.5f, 0.5f, 0.15f};
+
 static void fill(int scene, mppi_model_desc& d, orc_model& o, std::vector<float>& hf, std::vector<double>& hfd)
 {
     d = mppi_model_desc{};
@@ -63,6 +66,11 @@ static void fill(int scene, mppi_model_desc& d, orc_model& o, std::vector<float>
     if (scene == MPPI_SCENE_FREE_BOX) {
         d.box_half[0] = d.box_half[1] = 0.2f; d.box_half[2] = 0.15f; d.box_mass = 2.f;
     }
+    if (scene == MPPI_SCENE_STATIC_BOX)
+        for (int i = 0; i < 3; ++i) {
+            d.sbox_center[i] = g_sbox[i];
+            d.sbox_half[i] = g_sbox[3 + i];
+        }
     o = orc_model{};
     for (int i = 0; i < 3; ++i) o.trunk_size[i] = d.trunk_size[i];
     o.trunk_mass = d.trunk_mass; o.hip_x = d.hip_x; o.hip_y = d.hip_y; o.thigh_len = d.thigh_len;
@@ -76,6 +84,10 @@ static void fill(int scene, mppi_model_desc& d, orc_model& o, std::vector<float>
     }
     for (int i = 0; i < 3; ++i) o.box_half[i] = d.box_half[i];
     o.box_mass = d.box_mass;
+    for (int i = 0; i < 3; ++i) {
+        o.sbox_center[i] = d.sbox_center[i];
+        o.sbox_half[i] = d.sbox_half[i];
+    }
 }
 
 static int g_lanes = MPPI_LANES_QUAD;  // rollout decomposition of the controllers made here
@@ -219,7 +231,8 @@ static void rollout_case(int scene, int K, int nk, float box_x = 1.f)
     mppi_model_destroy(m);
 }
 
-// the proposal step with an explicit centre and spread (both branches of the cost gate)
+// the proposal step with an explicit centre and spread (each gate, with and without the
+// concurrent flag, and ungated)
 static void proposal_case()
 {
     mppi_model_desc d; orc_model o; std::vector<float> hf; std::vector<double> hfd;
@@ -231,7 +244,9 @@ static void proposal_case()
     mppi_ctx* c = controller(m, p);
     const int D = 48, Kp = 16;
     float *x = dev(37), *u0 = dev(12), *mu = dev(D), *center = dev(D), *sd = dev(D);
-    for (int gate = 0; gate < 2; ++gate) {
+    for (int gate : {(int)MPPI_PROPOSAL_GATE_COST, (int)MPPI_PROPOSAL_GATE_NONE, (int)MPPI_PROPOSAL_GATE_BEST,
+                     MPPI_PROPOSAL_GATE_COST | MPPI_PROPOSAL_CONCURRENT,
+                     MPPI_PROPOSAL_GATE_BEST | MPPI_PROPOSAL_CONCURRENT}) {
         std::vector<float> xs = start_state(37, 5), ms = stance_knots(4, 5), cs = stance_knots(4, 6);
         std::memcpy(x, xs.data(), 4 * 37);
         std::memcpy(mu, ms.data(), 4 * D);
@@ -244,8 +259,8 @@ static void proposal_case()
         std::vector<double> ox = to_d(xs.data(), 37), omu = to_d(ms.data(), D), oc = to_d(cs.data(), D),
                             osd = to_d(sd, D), ou0(12);
         int acc = 0;
-        orc_mppi_step_proposal(&o, &op, 5, ox.data(), omu.data(), oc.data(), osd.data(), Kp, gate, ou0.data(), nullptr,
-                               nullptr, &acc, 1);
+        orc_mppi_step_proposal(&o, &op, 5, ox.data(), omu.data(), oc.data(), osd.data(), Kp,
+                               gate & ~MPPI_PROPOSAL_CONCURRENT, ou0.data(), nullptr, nullptr, &acc, 1);
         char what[128];
         std::snprintf(what, sizeof what, "proposal step (gate %d, oracle %s)", gate, acc ? "accepted" : "fell back");
         check(what, std::fmax(max_abs_diff(u0, ou0.data(), 12), max_abs_diff(mu, omu.data(), D)), 1e-3);
@@ -391,6 +406,12 @@ int main(int argc, char** argv)
     rollout_case(MPPI_SCENE_FLAT, 21, 4);
     rollout_case(MPPI_SCENE_FREE_BOX, 9, 8);  // the contact passes read only what the tests wrote
     rollout_case(MPPI_SCENE_FREE_BOX, 9, 8, 0.4f);  // front feet on the ground and against the box
+    proposal_case();  // gated: the proposal and the fallback in one launch, or one after the other
+    // the static box: front feet against its face, then on its top
+    rollout_case(MPPI_SCENE_STATIC_BOX, 9, 6);
+    g_sbox[0] = 0.6f; g_sbox[2] = -0.13f;
+    rollout_case(MPPI_SCENE_STATIC_BOX, 9, 6);
+    g_sbox[0] = 0.71f; g_sbox[2] = 0.15f;
     if (!quick) {
         steps_case("split heightfield K=16 H=12", MPPI_SCENE_HEIGHTFIELD, 16, 12, 6, 0.01f, 1);
         steps_case("split free box K=18 H=10", MPPI_SCENE_FREE_BOX, 18, 10, 8, 0.01f, 1);

@@ -119,13 +119,20 @@ static void controller(mppi_model* m, mppi_policy* pol, int nx, int K, int H, in
     OK(mppi_update_shift(c, costs, u0, w));
     OK(mppi_step(c, x, u0));
     if (nx == 37 && K >= 2) {
-        for (int gate : {MPPI_PROPOSAL_GATE_COST, MPPI_PROPOSAL_GATE_NONE, MPPI_PROPOSAL_GATE_BEST}) {
+        for (int gate : {(int)MPPI_PROPOSAL_GATE_COST, (int)MPPI_PROPOSAL_GATE_NONE, (int)MPPI_PROPOSAL_GATE_BEST,
+                         MPPI_PROPOSAL_GATE_COST | MPPI_PROPOSAL_CONCURRENT,
+                         MPPI_PROPOSAL_GATE_BEST | MPPI_PROPOSAL_CONCURRENT}) {
             OK(mppi_step_proposal(c, x, center, sd, 2, gate, u0));
             OK(mppi_step_proposal(c, x, center, sd, K, gate, u0));
         }
         const float cmd[3] = {0.5f, 0, 0}, org[2] = {0, 0};
         OK(mppi_set_proposal(c, pol, K / 4 >= 2 ? K / 4 : 2, MPPI_PROPOSAL_GATE_COST, cmd, org));
         OK(mppi_step(c, x, u0));
+        OK(mppi_set_proposal(c, pol, 2, MPPI_PROPOSAL_GATE_BEST | MPPI_PROPOSAL_CONCURRENT, cmd, org));
+        OK(mppi_step(c, x, u0));
+        REFUSED(mppi_set_proposal(c, pol, 2, MPPI_PROPOSAL_GATE_NONE | MPPI_PROPOSAL_CONCURRENT, cmd, org));
+        REFUSED(mppi_step_proposal(c, x, center, sd, 2, MPPI_PROPOSAL_GATE_NONE | MPPI_PROPOSAL_CONCURRENT, u0));
+        REFUSED(mppi_step_proposal(c, x, center, sd, 2, 3, u0));
         OK(mppi_set_proposal(c, nullptr, 0, 0, nullptr, nullptr));
     }
     REFUSED(mppi_step_proposal(c, x, center, sd, K + 1, MPPI_PROPOSAL_GATE_NONE, u0));

@@ -242,6 +242,17 @@ hipError_t launch_gate(int Kp, const float* costs_p, int best, float* g, int* sk
     return hipSuccess;
 }
 
+hipError_t launch_pair_noise(int K, int D, float sigma, float* e, const float* nominal, const float* center,
+                             float* eps_out, hipStream_t)
+{
+    if (K < 1 || D < 1 || !(sigma >= 0.f)) fail("pair noise shape");
+    range_check(e, 4ull * K * D, "pair noise offsets");
+    range_check(nominal, 4ull * D, "pair noise nominal");
+    range_check(center, 4ull * D, "pair noise centre");
+    range_check(eps_out, 4ull * K * D, "pair noise eps out");
+    return hipSuccess;
+}
+
 hipError_t launch_features(const float* x, const float* co, float* f, hipStream_t)
 {
     range_check(x, 4 * 37, "features state");

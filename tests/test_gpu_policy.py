@@ -405,11 +405,13 @@ def test_training_pipeline_on_closed_loop_data(B):
 # ---------------------------------------------------------------------------- proposal step
 @pytest.mark.parametrize("lanes", [4, 16])
 @pytest.mark.parametrize("accept,gate", [(True, "cost"), (False, "cost"), (False, "none"), (True, "best"),
-                                         (False, "best")])
+                                         (False, "best"), (True, "best-concurrent"), (False, "best-concurrent"),
+                                         (False, "cost-concurrent")])
 def test_proposal_step_on_plain_kernels_matches_oracle(B, accept, gate, lanes):
     """The proposal step in both branches of each gate, and ungated, against the oracle's
     proposal step; with the lane-split rollout the plain fallback is rolled out only when
-    the gate rejects, with the quad rollout beside the proposal."""
+    the gate rejects unless the concurrent flag asks for both rollouts side by side, with
+    the quad rollout always beside the proposal."""
     md, p, orc, ctl = _ctl(B, lanes=lanes)
     D = 12 * p["nk"]
     rng = np.random.default_rng(2)
@@ -429,7 +431,7 @@ def test_proposal_step_on_plain_kernels_matches_oracle(B, accept, gate, lanes):
     nom = ctl.get_nominal().cpu().numpy()
     acc, steps = ctl.proposal_stats()
     ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, Kp,
-                                                         gate={"cost": 0, "none": 1, "best": 2}[gate])
+                                                         gate={"cost": 0, "none": 1, "best": 2}[gate.split("-")[0]])
     taken = accept or gate == "none"
     assert oacc == taken and acc == int(taken) and steps == 1
     assert ctl.sync_status() == (0 if taken else 2) and ctl.step_counter == 6  # 2: MPPI_WARN_FALLBACK
@@ -469,6 +471,66 @@ def test_gated_step_is_bitwise_the_chosen_branch(B, accept):
     assert steps == (3 if accept else 2) and acc == (3 if accept else 0)
     for u, n in runs[1:]:
         assert np.array_equal(u, runs[0][0]) and np.array_equal(n, runs[0][1])
+
+
+@pytest.mark.parametrize("lanes", [4, 16])
+@pytest.mark.parametrize("accept", [True, False])
+@pytest.mark.parametrize("gate", ["cost", "best"])
+def test_concurrent_gate_matches_the_sequential_gate(B, accept, gate, lanes):
+    """The concurrent flag rolls out the proposal and the plain samples in one launch on
+    every step.  The proposal's samples are the sequential gate's, so the gate decides the
+    same and an accepted step is the sequential one bit for bit; the plain samples are the
+    same draws as offsets from the proposal's centre (theta = c + ((mu - c) + sigma eps),
+    rounded once in FP32), so a fallback step agrees within that rounding.  Two steps in a
+    row; counters, status and step count equal."""
+    md, p, orc, ctl = _ctl(B, lanes=lanes)
+    D = 12 * p["nk"]
+    rng = np.random.default_rng(7)
+    mu = f32(W.stance_knots(p["nk"]))
+    x0 = _dev(W.initial_state(3))
+    if accept:
+        nominal = f32(mu + 0.5)
+        center = f32(mu + 0.02 * rng.normal(size=D))
+    else:
+        nominal = mu
+        center = f32(mu + 0.8)
+    sd, c = _dev(rng.uniform(0.05, 0.2, D)), _dev(center)
+    runs = []
+    for g in (gate, gate + "-concurrent"):
+        ctl.set_nominal(_dev(nominal))
+        ctl.set_step(5)
+        out = []
+        for _ in range(2):
+            a0, n0 = ctl.proposal_stats()
+            u0 = ctl.step_proposal(x0, c, sd, 16, gate=g)
+            a1, n1 = ctl.proposal_stats()
+            assert n1 == n0 + 1
+            out.append((u0.cpu().numpy(), ctl.get_nominal().cpu().numpy(), ctl.sync_status(), a1 - a0))
+        runs.append((out, ctl.step_counter))
+    (o1, s1), (o2, s2) = runs
+    assert s1 == s2
+    assert o1[0][3] == int(accept)  # the first step takes the branch the inputs were made for
+    exact = True  # bit for bit until a fallback step (then within rounding)
+    for (u1, m1, st1, acc1), (u2, m2, st2, acc2) in zip(o1, o2):
+        assert st1 == st2 and acc1 == acc2
+        exact = exact and acc1 == 1
+        if exact:
+            assert np.array_equal(u1, u2) and np.array_equal(m1, m2)
+        else:
+            assert np.abs(u1 - u2).max() <= KNOT_TOL and np.abs(m1 - m2).max() <= KNOT_TOL
+
+
+def test_concurrent_flag_rejected_without_a_gate(B):
+    """The concurrent flag names a way to roll out the fallback: with gate none there is
+    none, and the step is refused before any work."""
+    md, p, orc, ctl = _ctl(B, lanes=16)
+    D = 12 * p["nk"]
+    mu = _dev(W.stance_knots(p["nk"]))
+    x0 = _dev(W.initial_state(3))
+    sd = _dev(np.full(D, 0.1))
+    u0 = _dev(np.zeros(12))
+    rc = B.lib().mppi_step_proposal(ctl.h, B._ptr(x0), B._ptr(mu), B._ptr(sd), 16, 1 | 4, B._ptr(u0))
+    assert rc == -1
 
 
 def test_learned_step_on_plain_kernels_matches_oracle_chain(B):
