@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_2409_10469_amd.roofline import PEAK_TFLOPS, flops_per_rollout_step  # noqa: E402
+from paper_2409_10469_amd.timing import DeviceEvent  # noqa: E402
 
 SCENE_NAMES = {0: "flat ground", 1: "heightfield 64x64", 2: "flat ground + static box (climb)",
                3: "flat ground + free box (push)"}
@@ -233,19 +234,19 @@ def main():
         x[0].copy_(x0s[e])
         cur["i"] = 0
 
-    def control_step(ev=None, weights=None):
+    def control_step(ev_start=None, ev_roll=None, ev_end=None, weights=None):
         i, ctl = cur["i"], cur["ctl"]
         xi, xo = x[i % 2], x[(i + 1) % 2]
-        if ev:
-            ev[0].record(stream)
+        if ev_start:
+            ev_start.record(stream)
         ctl.rollout_batch(xi, costs=costs)
-        if ev:
-            ev[1].record(stream)
+        if ev_roll:
+            ev_roll.record(stream)
         ctl.update_shift(costs, u0, weights=weights)
         model.sim_step_into(xi.view(1, -1), u0.view(1, -1), p["kp"], p["kd"], p["dt"], xo.view(1, -1),
                             arith=args.arith)
-        if ev:
-            ev[2].record(stream)
+        if ev_end:
+            ev_end.record(stream)
         cur["i"] = i + 1
 
     if args.copy_calibration:
@@ -259,18 +260,28 @@ def main():
     for _ in range(args.warmup):
         control_step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    # Stream events (device-scope release, see timing.py); each record costs the stream a
+    # few microseconds, so a step records one at its start, its latency running to the
+    # next step's start (to an event of its own at the end of an episode, so that the
+    # next episode's reset is not counted), and every ROLL_EVERY-th step one more after
+    # its rollout for the rollout kernel's duration
+    ROLL_EVERY = 4
+    last = lambda k: (k + 1) % args.episode_steps == 0 or k == args.steps - 1  # noqa: E731
+    ev_start = [DeviceEvent() for _ in range(args.steps)]
+    ev_roll = {k: DeviceEvent() for k in range(0, args.steps, ROLL_EVERY)}
+    ev_end = {k: DeviceEvent() for k in range(args.steps) if last(k)}
     wbuf = torch.empty((args.steps, K), dtype=torch.float32, device="cuda")  # each step's Eq. 1 weights
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         if k % args.episode_steps == 0:
             start_episode(k // args.episode_steps)
-        control_step(evs[k], wbuf[k])
+        control_step(ev_start[k], ev_roll.get(k), ev_end.get(k), wbuf[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
-    roll_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    step_ms = np.array([ev_start[k].elapsed_time(ev_end[k] if k in ev_end else ev_start[k + 1])
+                        for k in range(args.steps)])
+    roll_ms = np.array([ev_start[k].elapsed_time(e) for k, e in sorted(ev_roll.items())])
     status = max(c.sync_status() for c in ctls)
     w64 = wbuf.double()
     ess = (w64.sum(1) ** 2 / (w64 ** 2).sum(1)).cpu().numpy()  # effective sample size per step
@@ -301,6 +312,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "mean": float(step_ms.mean())},
         "rollout_kernel_ms": float(roll_ms.mean()),
+        "timing": f"stream events: every step's start (latency to the next start, or to an event of its own at an "
+                  f"episode's end), and the rollout's end on every {ROLL_EVERY}th step ({roll_ms.size} launches)",
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic_from_profile(wl["name"], args.arith, args.lanes),
                      "flops_per_rollout_step": flops_per_rollout_step(wl["scene"], nk),
@@ -433,7 +446,7 @@ def bench_proposal(args):
     loss = torch.empty(1, device="cuda")
     for _ in range(5):
         pol.train_step(data["X"], data["Y"], index=idx, B=4096, lr=0.0, loss=loss)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = DeviceEvent(), DeviceEvent()
     n_t = 50
     e0.record(stream)
     for _ in range(n_t):
@@ -543,7 +556,7 @@ def bench_tracking(args):
         ctl.set_nominal(torch.tensor(W.stance_knots(p["nk"]), dtype=torch.float32, device="cuda"))
         for _ in range(10):
             ctl.step(x, u0)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(200)]
+        ev = [(DeviceEvent(), DeviceEvent()) for _ in range(200)]
         for a, b in ev:
             a.record()
             ctl.step(x, u0)

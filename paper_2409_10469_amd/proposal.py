@@ -26,6 +26,7 @@ import numpy as np
 
 from . import binding as B
 from . import workloads as W
+from .timing import DeviceEvent
 
 CONFIGS = (W.FLAT_WALK, W.TERRAIN_WALK)
 V_RANGE = (0.0, 0.8)
@@ -191,7 +192,7 @@ def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="co
     ev = []
     for _ in range(steps):
         if lat is not None:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0, e1 = DeviceEvent(), DeviceEvent()
             e0.record()
         ctl.step(x, u0)
         if lat is not None:
@@ -314,7 +315,7 @@ def evaluate_batched(policy, n_inst=256, K_plain=(256, 1024), k_prop=256, steps=
         ev = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0, e1 = DeviceEvent(), DeviceEvent()
             e0.record()
             batch.step()
             e1.record()

@@ -14,6 +14,7 @@ import numpy as np
 
 from . import binding as B
 from . import workloads as W
+from .timing import DeviceEvent
 
 # per-task controller settings (flat walking, heightfield walking, box climbing, box pushing)
 TASKS = {
@@ -123,7 +124,7 @@ class ServingSim:
             tune = self.batch.autotune(steps=1) + (self.batch.tuning()[2],)
         self.stream.synchronize()
         lat, host_ms, work, flops, live = [], [], 0, 0.0, []
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        evs = [(DeviceEvent(), DeviceEvent()) for _ in range(steps)]
         t0 = time.perf_counter()
         for i in range(steps):
             h0 = time.perf_counter()
