@@ -144,12 +144,12 @@ mppi_status mppi_policy_pairs(int n_rec, int steps, int n_knots, const float *d_
  * the quad rollout the plain K samples are rolled out beside the proposal's, on an
  * internal stream that mppi_bind creates.  With MPPI_PROPOSAL_CONCURRENT added to the gate
  * (either rollout) one rollout launch covers both sets on every step: k_prop + K samples
- * in about one rollout's time, whatever the process's other streams.  The plain samples
- * are then the same draws taken as offsets from the proposal's centre,
- * theta_n = c + ((mu - c) + sigma eps_n) with the offset rounded once in FP32 (the
- * workspace holds both sets): the gate decides as without the flag, an accepted step is
- * the same bit for bit, and a fallback step agrees within that rounding.
- * MPPI_PROPOSAL_GATE_NONE always takes the proposal
+ * in about one rollout's time, whatever the process's other streams.  That launch is
+ * centred on the nominal mu: the plain samples are mu + sigma eps_n (the product rounded
+ * once in FP32), so whatever the proposal holds cannot reach the fallback, and the
+ * proposal's are mu + ((c - mu) + e_n) (the offset rounded once; theta_1 = mu exactly).
+ * The step agrees with the sequential gate within that rounding (the workspace holds
+ * both sets).  MPPI_PROPOSAL_GATE_NONE always takes the proposal
  * branch (the nominal still competes as sample 1) and rolls out only the proposal.
  * 2 <= k_prop <= K.  The proposal steps use the running cost (EINVAL for a controller
  * created with MPPI_COST_TRACKING). */

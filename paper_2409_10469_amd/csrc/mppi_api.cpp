@@ -42,6 +42,7 @@ struct mppi_ctx {
     size_t off_B, off_S, off_hf, off_mu, off_eps, off_costs, off_w, off_status, total;
     // learned proposal: command and origin, centre, std, proposal costs and noise
     size_t off_cmd, off_center, off_sd, off_costs_p, off_eps_p;
+    size_t off_eps_pair, off_costs_pair;  // the concurrent gated step's two sets in one launch
     uint32_t step = 0;
     mppi_policy* policy = nullptr;
     int k_prop = 0, prop_gate = 0;
@@ -420,10 +421,12 @@ mppi_status mppi_create(const mppi_model* model, const mppi_params* p, mppi_ctx*
     c->off_cmd = o; o = align256(o + sizeof(float) * 8);
     c->off_center = o; o = align256(o + sizeof(float) * c->D);
     c->off_sd = o; o = align256(o + sizeof(float) * c->D);
-    // room for both sample sets of the concurrent gated step (k_prop <= K proposal samples,
-    // then the K plain ones)
-    c->off_costs_p = o; o = align256(o + sizeof(float) * 2 * p->K);
-    c->off_eps_p = o; o = align256(o + sizeof(float) * (size_t)c->D * 2 * p->K);
+    c->off_costs_p = o; o = align256(o + sizeof(float) * p->K);
+    c->off_eps_p = o; o = align256(o + sizeof(float) * (size_t)c->D * p->K);
+    // both sample sets of the concurrent gated step (K plain, then k_prop <= K proposal
+    // samples): offsets from the nominal and costs
+    c->off_eps_pair = o; o = align256(o + sizeof(float) * (size_t)c->D * 2 * p->K);
+    c->off_costs_pair = o; o = align256(o + sizeof(float) * 2 * p->K);
     c->off_pstats = o; o = align256(o + sizeof(int) * 2);
     c->off_gate = o; o = align256(o + sizeof(float) * 4);
     if (p->cost == MPPI_COST_TRACKING) {
@@ -622,6 +625,14 @@ mppi_status mppi_update(mppi_ctx* c, const float* d_costs, const float* d_eps, f
     return update(c, d_costs, d_eps, d_knots_out, nullptr, nullptr, d_weights_out);
 }
 
+// GATE_COST, GATE_NONE or GATE_BEST, the gated two with the CONCURRENT bit allowed
+static bool valid_gate(int gate)
+{
+    const int g = gate & ~MPPI_PROPOSAL_CONCURRENT;
+    if (g != MPPI_PROPOSAL_GATE_COST && g != MPPI_PROPOSAL_GATE_NONE && g != MPPI_PROPOSAL_GATE_BEST) return false;
+    return !((gate & MPPI_PROPOSAL_CONCURRENT) && g == MPPI_PROPOSAL_GATE_NONE);
+}
+
 // Proposal step on the plain kernels: the k_prop samples theta_n = c + e_n are rolled out
 // through the explicit-noise path with unit scale, where e holds Philox noise scaled by
 // sd for n >= 2, zero for the centre (n = 0) and nominal - c for n = 1.  A gated step
@@ -631,20 +642,12 @@ mppi_status mppi_update(mppi_ctx* c, const float* d_costs, const float* d_eps, f
 // the gate is decided on the device right after the proposal rollout and the plain
 // rollout runs only on a fallback (it returns at once when the proposal was taken), so a
 // step rolls out k_prop + K samples only when it falls back.  With the gate's
-// MPPI_PROPOSAL_CONCURRENT bit one rollout launch covers both sets on every step; with
-// the quad rollout the plain rollout runs beside the proposal's on an internal stream;
-// the gate kernel follows both.  The update kernel
-// reads the gate costs and updates over whichever set was chosen; no host round trip.
-// Accepted: mu' = c + sum w_n e_n / sum w_n, the weighted mean of theta (centre c, unit
-// scale).  Ungated: the proposal rollout alone.
-// GATE_COST, GATE_NONE or GATE_BEST, the gated two with the CONCURRENT bit allowed
-static bool valid_gate(int gate)
-{
-    const int g = gate & ~MPPI_PROPOSAL_CONCURRENT;
-    if (g != MPPI_PROPOSAL_GATE_COST && g != MPPI_PROPOSAL_GATE_NONE && g != MPPI_PROPOSAL_GATE_BEST) return false;
-    return !((gate & MPPI_PROPOSAL_CONCURRENT) && g == MPPI_PROPOSAL_GATE_NONE);
-}
-
+// MPPI_PROPOSAL_CONCURRENT bit one rollout launch, centred on the nominal, covers both
+// sets on every step; with the quad rollout the plain rollout runs beside the proposal's
+// on an internal stream; the gate kernel follows both.  The update kernel reads the gate
+// costs and updates over whichever set was chosen; no host round trip.  Accepted:
+// mu' = c + sum w_n e_n / sum w_n, the weighted mean of theta (centre c, unit scale).
+// Ungated: the proposal rollout alone.
 static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_center, const float* d_sd, int kp,
                                  int gate, float* d_u0_out)
 {
@@ -684,24 +687,28 @@ static mppi_status step_proposal(mppi_ctx* c, const float* d_x0, const float* d_
             (s = rollout(c, d_x0, nullptr, costs, nullptr, skip)))
             return s;
     } else if (gated && concurrent) {
-        // one rollout launch over both sample sets: the proposal's kp samples as above, then
-        // the plain step's K samples as offsets from the proposal's centre
-        // (theta = c + (mu - c) + sigma eps, drawn from the plain step's counters); the gate
-        // reads the first kp costs, the update the rest on a fallback
+        // one rollout launch over both sample sets, centred on the nominal mu with unit
+        // scale: the plain step's K samples (mu + sigma eps, drawn from its counters), then
+        // the proposal's kp as offsets (c - mu) + e_n; the gate reads the proposal's costs,
+        // the update the plain ones on a fallback
         const mppi::DevParams P = dev_params(c);
-        float* ep = e + (size_t)kp * c->D;
+        float* E = wsf(c, c->off_eps_pair);
+        float* cpair = wsf(c, c->off_costs_pair);
         mppi::DevParams P2 = Pp;
-        P2.K = kp + c->p.K;
-        a.costs = costs_p;
+        P2.K = c->p.K + kp;
+        a.mu = wsf(c, c->off_mu);
+        a.eps_in = E;
+        a.costs = cpair;
         a.input_status = (int*)wsf(c, c->off_status) + 1;
-        if ((s = hip_check(c, mppi::launch_sample(P, c->D, ep, nullptr, c->stream), "plain noise launch")) ||
-            (s = hip_check(c, prop::launch_pair_noise(c->p.K, c->D, c->p.sigma, ep, wsf(c, c->off_mu), d_center,
+        costs = cpair;
+        costs_p = cpair + c->p.K;
+        if ((s = hip_check(c, mppi::launch_sample(P, c->D, E, nullptr, c->stream), "plain noise launch")) ||
+            (s = hip_check(c, prop::launch_pair_noise(kp, c->p.K, c->D, c->p.sigma, E, e, wsf(c, c->off_mu), d_center,
                                                       wsf(c, c->off_eps), c->stream),
-                           "plain offsets launch")) ||
+                           "paired offsets launch")) ||
             (s = hip_check(c, launch_roll(c, P2, a, c->stream), "paired rollout launch")) ||
             (s = hip_check(c, prop::launch_gate(kp, costs_p, best, g, skip, c->stream), "gate launch")))
             return s;
-        costs = costs_p + kp;
     } else if (gated) {
         if (!c->side) return fail(c, MPPI_ESTATE, "no side stream (bind the controller again)");
         if ((s = hip_check(c, hipEventRecord(c->ev_fork, c->stream), "fork record")) ||

@@ -8,8 +8,8 @@
 //                           instances of a batch, one row per instance
 //   gate_kernel           - the fallback decision of a gated proposal step from the
 //                           proposal's costs, before the plain samples are rolled out
-//   pair_noise_kernel     - the plain step's samples as offsets from the proposal's centre,
-//                           so that one rollout launch covers both sample sets
+//   pair_noise_kernel     - both sample sets as offsets from the nominal, so that one
+//                           rollout launch covers them
 #include <hip/hip_runtime.h>
 
 #include "mppi_device.h"
@@ -66,30 +66,37 @@ hipError_t launch_gate(int Kp, const float* costs_p, int best, float* g, int* sk
     return hipGetLastError();
 }
 
-// e (K x D) holds the plain step's eps_n on entry (the sampler's order: e[n D + d]); on
-// exit theta_n = c + e_n is the plain sample mu + sigma eps_n (mu itself for n = 0, the
-// nominal), with (mu - c) + sigma eps_n rounded once, and eps_n is stored to
-// eps_out[d K + n], where the update reads the plain step's noise
-__global__ __launch_bounds__(256) void pair_noise_kernel(int K, int D, float sigma, float* __restrict__ e,
+// The two sample sets of the concurrent gated step as offsets from the nominal mu, for one
+// rollout launch centred on mu with unit scale: rows 0..K-1 of E hold the plain step's
+// eps_n on entry (the sampler's order, E[n D + d]) and sigma eps_n on exit (0 for n = 0,
+// the nominal), so the plain samples are mu + sigma eps_n whatever the proposal holds;
+// rows K..K+Kp-1 receive the proposal's samples c + e_n as (c - mu) + e_n, each offset
+// rounded once (sample 1, e_1 = mu - c, lands on mu exactly).  eps_n is also stored to
+// eps_out[d K + n], where the update reads the plain step's noise.
+__global__ __launch_bounds__(256) void pair_noise_kernel(int Kp, int K, int D, float sigma, float* __restrict__ E,
+                                                         const float* __restrict__ e_prop,
                                                          const float* __restrict__ nominal,
                                                          const float* __restrict__ center,
                                                          float* __restrict__ eps_out)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= K * D) return;
+    if (i >= (K + Kp) * D) return;
     const int n = i / D, d = i - n * D;
-    const float eps = e[i];
-    const float off = nominal[d] - center[d];
-    e[i] = n == 0 ? off : fmaf(sigma, eps, off);
-    eps_out[(size_t)d * K + n] = eps;
+    if (n < K) {
+        const float eps = E[i];
+        E[i] = n == 0 ? 0.f : sigma * eps;
+        eps_out[(size_t)d * K + n] = eps;
+    } else {
+        E[i] = (center[d] - nominal[d]) + e_prop[(size_t)(n - K) * D + d];
+    }
 }
 
-hipError_t launch_pair_noise(int K, int D, float sigma, float* e, const float* nominal, const float* center,
-                             float* eps_out, hipStream_t st)
+hipError_t launch_pair_noise(int Kp, int K, int D, float sigma, float* E, const float* e_prop, const float* nominal,
+                             const float* center, float* eps_out, hipStream_t st)
 {
-    const long n = (long)K * D;
-    hipLaunchKernelGGL(pair_noise_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, K, D, sigma, e,
-                       nominal, center, eps_out);
+    const long n = (long)(K + Kp) * D;
+    hipLaunchKernelGGL(pair_noise_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Kp, K, D, sigma, E,
+                       e_prop, nominal, center, eps_out);
     return hipGetLastError();
 }
 

@@ -23,10 +23,11 @@ hipError_t launch_proposal_noise(int Kp, int D, float* e, const float* center, c
 // 1: the least cost of its samples other than the nominal, sample 1) against the
 // nominal's: g = {that cost, nominal's}, skip = 1 when the proposal is taken
 hipError_t launch_gate(int Kp, const float* costs_p, int best, float* g, int* skip, hipStream_t st);
-// the concurrent gated step: e (K x D) from the plain step's eps to offsets from the
-// centre (c + e_n = mu + sigma eps_n; mu for n = 0), eps copied to eps_out (D x K)
-hipError_t launch_pair_noise(int K, int D, float sigma, float* e, const float* nominal, const float* center,
-                             float* eps_out, hipStream_t st);
+// the concurrent gated step: E ((K + Kp) x D) as offsets from the nominal, rows 0..K-1
+// from the plain step's eps (sigma eps_n, 0 for n = 0; eps copied to eps_out, D x K),
+// rows K.. from the proposal's e_prop (Kp x D, offsets from the centre): (c - mu) + e_n
+hipError_t launch_pair_noise(int Kp, int K, int D, float sigma, float* E, const float* e_prop, const float* nominal,
+                             const float* center, float* eps_out, hipStream_t st);
 // state x (37 floats) and cmd_origin = (cmd[3], origin[2]) -> 40 raw features
 hipError_t launch_features(const float* x, const float* cmd_origin, float* feat, hipStream_t st);
 // raw features (np x 40) of the proposal rows' current states

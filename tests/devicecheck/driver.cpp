@@ -232,22 +232,28 @@ static void rollout_case(int scene, int K, int nk, float box_x = 1.f)
 }
 
 // the proposal step with an explicit centre and spread (each gate, with and without the
-// concurrent flag, and ungated)
-static void proposal_case()
+// concurrent flag, and ungated); quick: the falling-back inputs only, and of the gates
+// the cost gate, no gate, and the best-sample gate with the flag
+static void proposal_case(bool quick)
 {
     mppi_model_desc d; orc_model o; std::vector<float> hf; std::vector<double> hfd;
     fill(MPPI_SCENE_FLAT, d, o, hf, hfd);
     mppi_model* m = nullptr;
     must("model", mppi_model_create(&d, &m));
     mppi_params p; orc_params op;
-    params(64, 25, 4, 0.02f, p, op);
+    params(24, 8, 4, 0.02f, p, op);
     mppi_ctx* c = controller(m, p);
-    const int D = 48, Kp = 16;
+    const int D = 48, Kp = 8;
     float *x = dev(37), *u0 = dev(12), *mu = dev(D), *center = dev(D), *sd = dev(D);
+    for (int bad_nominal = 0; bad_nominal < (quick ? 1 : 2); ++bad_nominal)
     for (int gate : {(int)MPPI_PROPOSAL_GATE_COST, (int)MPPI_PROPOSAL_GATE_NONE, (int)MPPI_PROPOSAL_GATE_BEST,
                      MPPI_PROPOSAL_GATE_COST | MPPI_PROPOSAL_CONCURRENT,
                      MPPI_PROPOSAL_GATE_BEST | MPPI_PROPOSAL_CONCURRENT}) {
+        if (quick && (gate == MPPI_PROPOSAL_GATE_BEST || gate == (MPPI_PROPOSAL_GATE_COST | MPPI_PROPOSAL_CONCURRENT)))
+            continue;
         std::vector<float> xs = start_state(37, 5), ms = stance_knots(4, 5), cs = stance_knots(4, 6);
+        if (bad_nominal)  // a nominal far off the stance, so that the gates take the proposal
+            for (float& v : ms) v += 0.5f;
         std::memcpy(x, xs.data(), 4 * 37);
         std::memcpy(mu, ms.data(), 4 * D);
         std::memcpy(center, cs.data(), 4 * D);
@@ -392,7 +398,7 @@ int main(int argc, char** argv)
     const bool no_batch = argc > 2 && std::strcmp(argv[2], "no-batch") == 0;
     steps_case("flat K=64 H=25", MPPI_SCENE_FLAT, 64, 25, 4, 0.02f, quick ? 1 : 3);
     rollout_case(MPPI_SCENE_FLAT, 20, 4);
-    proposal_case();
+    proposal_case(quick);
     if (!quick) {
         steps_case("heightfield K=16 H=12", MPPI_SCENE_HEIGHTFIELD, 16, 12, 6, 0.01f, 1);
         steps_case("free box K=16 H=10", MPPI_SCENE_FREE_BOX, 16, 10, 8, 0.01f, 1);
@@ -406,13 +412,13 @@ int main(int argc, char** argv)
     rollout_case(MPPI_SCENE_FLAT, 21, 4);
     rollout_case(MPPI_SCENE_FREE_BOX, 9, 8);  // the contact passes read only what the tests wrote
     rollout_case(MPPI_SCENE_FREE_BOX, 9, 8, 0.4f);  // front feet on the ground and against the box
-    proposal_case();  // gated: the proposal and the fallback in one launch, or one after the other
-    // the static box: front feet against its face, then on its top
-    rollout_case(MPPI_SCENE_STATIC_BOX, 9, 6);
-    g_sbox[0] = 0.6f; g_sbox[2] = -0.13f;
-    rollout_case(MPPI_SCENE_STATIC_BOX, 9, 6);
-    g_sbox[0] = 0.71f; g_sbox[2] = 0.15f;
+    proposal_case(quick);  // gated: the proposal and the fallback in one launch, or one after the other
     if (!quick) {
+        // the static box: front feet against its face, then on its top
+        rollout_case(MPPI_SCENE_STATIC_BOX, 9, 6);
+        g_sbox[0] = 0.6f; g_sbox[2] = -0.13f;
+        rollout_case(MPPI_SCENE_STATIC_BOX, 9, 6);
+        g_sbox[0] = 0.71f; g_sbox[2] = 0.15f;
         steps_case("split heightfield K=16 H=12", MPPI_SCENE_HEIGHTFIELD, 16, 12, 6, 0.01f, 1);
         steps_case("split free box K=18 H=10", MPPI_SCENE_FREE_BOX, 18, 10, 8, 0.01f, 1);
     }

@@ -242,14 +242,15 @@ hipError_t launch_gate(int Kp, const float* costs_p, int best, float* g, int* sk
     return hipSuccess;
 }
 
-hipError_t launch_pair_noise(int K, int D, float sigma, float* e, const float* nominal, const float* center,
-                             float* eps_out, hipStream_t)
+hipError_t launch_pair_noise(int Kp, int K, int D, float sigma, float* E, const float* e_prop, const float* nominal,
+                             const float* center, float* eps_out, hipStream_t)
 {
-    if (K < 1 || D < 1 || !(sigma >= 0.f)) fail("pair noise shape");
-    range_check(e, 4ull * K * D, "pair noise offsets");
-    range_check(nominal, 4ull * D, "pair noise nominal");
-    range_check(center, 4ull * D, "pair noise centre");
-    range_check(eps_out, 4ull * K * D, "pair noise eps out");
+    if (Kp < 2 || K < 1 || D < 1 || !(sigma >= 0.f)) fail("pair noise shape");
+    range_check(E, 4ull * (K + Kp) * D, "pair offsets");
+    range_check(e_prop, 4ull * Kp * D, "pair proposal noise");
+    range_check(nominal, 4ull * D, "pair nominal");
+    range_check(center, 4ull * D, "pair centre");
+    range_check(eps_out, 4ull * K * D, "pair eps out");
     return hipSuccess;
 }
 

@@ -478,11 +478,12 @@ def test_gated_step_is_bitwise_the_chosen_branch(B, accept):
 @pytest.mark.parametrize("gate", ["cost", "best"])
 def test_concurrent_gate_matches_the_sequential_gate(B, accept, gate, lanes):
     """The concurrent flag rolls out the proposal and the plain samples in one launch on
-    every step.  The proposal's samples are the sequential gate's, so the gate decides the
-    same and an accepted step is the sequential one bit for bit; the plain samples are the
-    same draws as offsets from the proposal's centre (theta = c + ((mu - c) + sigma eps),
-    rounded once in FP32), so a fallback step agrees within that rounding.  Two steps in a
-    row; counters, status and step count equal."""
+    every step, centred on the nominal: the plain samples mu + sigma eps_n (the product
+    rounded once in FP32), the proposal's mu + ((c - mu) + e_n) (the offset rounded once).
+    The gate decides as the sequential gate does and every step agrees with it within that
+    rounding; the nominal's own sample (theta_1 = mu) is exact, so the cost gate's
+    comparison differs only in the centre's cost.  Two steps in a row; counters, status
+    and step count equal."""
     md, p, orc, ctl = _ctl(B, lanes=lanes)
     D = 12 * p["nk"]
     rng = np.random.default_rng(7)
@@ -510,14 +511,39 @@ def test_concurrent_gate_matches_the_sequential_gate(B, accept, gate, lanes):
     (o1, s1), (o2, s2) = runs
     assert s1 == s2
     assert o1[0][3] == int(accept)  # the first step takes the branch the inputs were made for
-    exact = True  # bit for bit until a fallback step (then within rounding)
     for (u1, m1, st1, acc1), (u2, m2, st2, acc2) in zip(o1, o2):
         assert st1 == st2 and acc1 == acc2
-        exact = exact and acc1 == 1
-        if exact:
-            assert np.array_equal(u1, u2) and np.array_equal(m1, m2)
-        else:
-            assert np.abs(u1 - u2).max() <= KNOT_TOL and np.abs(m1 - m2).max() <= KNOT_TOL
+        assert np.abs(u1 - u2).max() <= KNOT_TOL and np.abs(m1 - m2).max() <= KNOT_TOL
+
+
+@pytest.mark.parametrize("lanes", [4, 16])
+@pytest.mark.parametrize("gate", ["cost-concurrent", "best-concurrent"])
+def test_concurrent_gate_falls_back_cleanly_from_a_corrupted_proposal(B, gate, lanes):
+    """The one launch of the concurrent gate is centred on the nominal, so a proposal whose
+    centre is not finite, or absurdly far off, spoils only its own samples: the gate
+    rejects it and the step is the plain step within the FP32 rounding of the plain
+    offsets, the acceptance counter unchanged."""
+    md, p, orc, ctl = _ctl(B, K=64, H=10, lanes=lanes)
+    D = 12 * p["nk"]
+    x0 = f32(W.initial_state(5))
+    mu = f32(W.stance_knots(p["nk"]))
+    sd = np.full(D, 0.1, np.float32)
+    ref = B.Controller(B.Model(md), p)
+    for bad in (np.nan, 1.0e30):
+        center = mu.copy()
+        center[3] = bad
+        for c in (ctl, ref):
+            c.set_nominal(_dev(mu))
+            c.set_step(2)
+        a0, n0 = ctl.proposal_stats()
+        u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), 16, gate=gate).cpu().numpy()
+        a1, n1 = ctl.proposal_stats()
+        assert (a1 - a0, n1 - n0) == (0, 1)
+        assert ctl.sync_status() == 2  # MPPI_WARN_FALLBACK
+        ur = ref.step(_dev(x0)).cpu().numpy()
+        assert np.all(np.isfinite(u0))
+        assert np.abs(u0 - ur).max() <= KNOT_TOL
+        assert np.abs(ctl.get_nominal().cpu().numpy() - ref.get_nominal().cpu().numpy()).max() <= KNOT_TOL
 
 
 def test_concurrent_flag_rejected_without_a_gate(B):
