@@ -338,8 +338,8 @@ def learned_vs_plain(args):
     2e5 closed-loop pairs from the flat and heightfield walks, 6 Adam epochs, then the
     heightfield walk (v_ref 0.5, 5 held-out seeds x 100 steps) with plain MPPI at K in
     {256, 512, 1024, 2048, 4096} against the proposal at 256 samples with plain MPPI at
-    K = 1024 as the fallback (cost gate, best-sample gate, best-sample gate with the
-    fallback rolled out concurrently) and ungated."""
+    K = 1024 as the fallback (cost gate, best-sample gate, best-sample gate with both sets
+    rolled out in one launch on every step) and ungated."""
     from paper_2409_10469_amd import binding as B
     from paper_2409_10469_amd import proposal as PR
     log = lambda m: print(m, file=sys.stderr, flush=True)
@@ -358,11 +358,11 @@ def learned_vs_plain(args):
                      for k, v in ev["plain"].items()}}
     for g in ("cost", "best", "best-concurrent", "none"):
         e = ev["learned_" + g]
-        res["learned_gate_" + g.replace("-", "_")] = {"episode_cost": e["mean"], "ci95": e["ci95"], "k_prop": e["k_prop"],
-                                    "samples_per_step": e["samples_per_step"], "acceptance": e["acceptance"],
-                                    "latency_p50_ms": e["latency_ms"]["p50"], "latency_p99_ms": e["latency_ms"]["p99"],
-                                    "smallest_plain_K_matching": e["smallest_plain_K_matching"],
-                                    "sample_ratio": e["sample_ratio"]}
+        res["learned_gate_" + g.replace("-", "_")] = {
+            "episode_cost": e["mean"], "ci95": e["ci95"], "k_prop": e["k_prop"],
+            "samples_per_step": e["samples_per_step"], "acceptance": e["acceptance"],
+            "latency_p50_ms": e["latency_ms"]["p50"], "latency_p99_ms": e["latency_ms"]["p99"],
+            "smallest_plain_K_matching": e["smallest_plain_K_matching"], "sample_ratio": e["sample_ratio"]}
     return res
 
 

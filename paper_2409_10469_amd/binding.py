@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(PKG, "libmppi.so")
 
 OK, WARN_ALL_NONFINITE, EINVAL, ENOMEM, EHIP, ESTATE = 0, 1, -1, -2, -3, -6
 ARITH = {"fp64": 0, "fp32": 1, "mixed": 2}
-# proposal gates (include/mppi_policy.h); "-concurrent" rolls out the fallback beside the proposal
+# proposal gates (include/mppi_policy.h); "-concurrent": one launch rolls out the proposal and the
+# plain fallback on every step
 GATE = {"cost": 0, "none": 1, "best": 2, "cost-concurrent": 4, "best-concurrent": 6}
 
 
@@ -359,9 +360,11 @@ class Controller:
 
     def step_proposal(self, x0, center, sd, k_prop, u0=None, gate="cost"):
         """One control step sampling k_prop knots around an explicit proposal (mean, std).
-        gate "cost": the plain step's K samples are rolled out beside the proposal's and the
-        update keeps the proposal only if its centre costs no more than the nominal (decided
-        on the device); "none": the proposal's samples alone."""
+        gate "cost": the update keeps the proposal only if its centre costs no more than the
+        nominal, and runs the plain step's K samples otherwise (decided on the device);
+        "best": the same with the proposal's least sample cost other than the nominal's;
+        "cost-concurrent" / "best-concurrent": the same gates with both sample sets rolled
+        out in one launch on every step; "none": the proposal's samples alone."""
         import torch
         u0 = u0 if u0 is not None else torch.empty(12, dtype=torch.float32, device="cuda")
         self._s(lib().mppi_step_proposal(self.h, _ptr(x0), _ptr(center), _ptr(sd), int(k_prop), GATE[gate],

@@ -245,7 +245,7 @@ def evaluate(policy, K_plain=(64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384),
         n = sum(r[3] for r in res)
         # a gated step on the lane-split rollout rolls out the proposal and, only when the
         # gate falls back, the plain step's K samples; the concurrent gate both on every
-        # step (beside each other); the ungated step the proposal only
+        # step (in one launch); the ungated step the proposal only
         if gate == "none":
             samples = float(kp)
         elif gate.endswith("-concurrent"):
