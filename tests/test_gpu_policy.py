@@ -223,10 +223,10 @@ def test_head_matches_oracle(B, nk):
 
 
 # ---------------------------------------------------------------------------- proposal step
-def _ctl(B, K=64, H=10, lanes=0):
+def _ctl(B, K=64, H=10, lanes=0, **extra):
     wl = W.FLAT_WALK
     md = round_model(W.model_dict(wl, 0))
-    p = round_params(W.params_dict(wl, 3, K=K, H=H, lanes=lanes))
+    p = round_params(W.params_dict(wl, 3, K=K, H=H, lanes=lanes, **extra))
     return md, p, O.Oracle(md), B.Controller(B.Model(md), p)
 
 
@@ -514,6 +514,39 @@ def test_concurrent_gate_matches_the_sequential_gate(B, accept, gate, lanes):
     for (u1, m1, st1, acc1), (u2, m2, st2, acc2) in zip(o1, o2):
         assert st1 == st2 and acc1 == acc2
         assert np.abs(u1 - u2).max() <= KNOT_TOL and np.abs(m1 - m2).max() <= KNOT_TOL
+
+
+@pytest.mark.parametrize("variant", ["direct basis", "mixed arithmetic"])
+@pytest.mark.parametrize("accept", [True, False])
+def test_concurrent_gate_with_direct_basis_and_mixed_arithmetic(B, variant, accept):
+    """The concurrent best-sample gate on the lane-split rollout with one value per control
+    step (nk = H, noise drawn in the step loop) and with the mixed arithmetic: the oracle's
+    proposal step within the knot bar, and the sequential gate's decision."""
+    extra = dict(basis=3, nk=10) if variant == "direct basis" else dict(arith="mixed")
+    md, p, orc, ctl = _ctl(B, H=10, lanes=16, **extra)
+    D = 12 * p["nk"]
+    rng = np.random.default_rng(4)
+    mu = f32(W.stance_knots(p["nk"]))
+    x0 = f32(W.initial_state(3))
+    if accept:
+        nominal = f32(mu + 0.5)
+        center = f32(mu + 0.02 * rng.normal(size=D))
+    else:
+        nominal = mu
+        center = f32(mu + 0.8)
+    sd = f32(rng.uniform(0.05, 0.2, D))
+    out = {}
+    for g in ("best", "best-concurrent"):
+        ctl.set_nominal(_dev(nominal))
+        ctl.set_step(5)
+        a0, _ = ctl.proposal_stats()
+        u0 = ctl.step_proposal(_dev(x0), _dev(center), _dev(sd), 16, gate=g).cpu().numpy()
+        out[g] = (u0, ctl.get_nominal().cpu().numpy(), ctl.proposal_stats()[0] - a0, ctl.sync_status())
+    ou0, onom, cp, cf, oacc, rc = orc.mppi_step_proposal(p, 5, x0, nominal, center, sd, 16, gate=2)
+    assert oacc == accept
+    for g, (u0, nom, acc, st) in out.items():
+        assert acc == int(accept) and st == (0 if accept else 2), g
+        assert np.abs(u0 - ou0).max() <= KNOT_TOL and np.abs(nom - onom).max() <= KNOT_TOL, g
 
 
 @pytest.mark.parametrize("lanes", [4, 16])
