@@ -142,7 +142,8 @@ mppi_status mppi_policy_pairs(int n_rec, int steps, int n_knots, const float *d_
  * fallback (after the proposal and the gate, on the bound stream): a step rolls out
  * k_prop samples, or k_prop + K one rollout after the other when it falls back.  With
  * the quad rollout the plain K samples are rolled out beside the proposal's, on an
- * internal stream that mppi_bind creates.  With MPPI_PROPOSAL_CONCURRENT added to the gate
+ * internal stream that mppi_bind creates (side by side only while the process's streams
+ * do not outnumber its hardware queues).  With MPPI_PROPOSAL_CONCURRENT added to the gate
  * (either rollout) one rollout launch covers both sets on every step: k_prop + K samples
  * in about one rollout's time, whatever the process's other streams.  That launch is
  * centred on the nominal mu: the plain samples are mu + sigma eps_n (the product rounded

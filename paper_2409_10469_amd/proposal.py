@@ -175,7 +175,7 @@ def episode(model, p, seed, steps, policy=None, k_prop=0, arith="fp64", gate="co
     episode cost sum dt * l, the final state and the proposal counters.  With a list
     `lat`, appends each control step's latency in ms: stream events around the step, so
     the time runs from the moment the plant state is on the device to the first control
-    (with the cost gate: both rollouts, side by side, and the gated update)."""
+    (with a gate: the proposal's rollout, the plain one where it runs, and the gated update)."""
     import torch
     from . import binding as Bd
     ctl = Bd.Controller(model, dict(p, seed=seed, arith=arith))
