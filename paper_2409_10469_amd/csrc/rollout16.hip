@@ -553,9 +553,12 @@ __device__ __forceinline__ void step16(const ModelT<R>& MR, const ModelT<S>& MS,
 // type, S: system type (FP32/FP32, FP64/FP64, or FP32 geometry with the FP64 system).
 // LDS: the summation rows [4][NV][kPitch] (NV summed values of the scene) and sums
 // [4][kSumPitch] (type S), then the heightfield (scene 1).  eps addressing as in the quad kernel: eps_in[n * eps_sn + d *
-// eps_sd] when given, otherwise Philox noise stored to eps_out[d * K + n].
+// eps_sd] when given, otherwise Philox noise stored to eps_out[d * K + n].  DIRECT: one
+// value per control step (the direct representation, whose noise is drawn inside the step
+// loop; the `direct` argument equals it); a separate instantiation, so that the knot
+// representations carry no per-step sampling code and its registers in their step loop.
 // ------------------------------------------------------------------------------
-template <int SCENE, typename R, typename S>
+template <int SCENE, typename R, typename S, bool DIRECT>
 __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> Ms, DevParams P,
                                                        const double* __restrict__ gB,
                                                        const float* __restrict__ ghf, const float* __restrict__ mu,
@@ -604,7 +607,7 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
 #pragma unroll
     for (int i = 0; i < kMaxKnots; ++i) {
         th[i] = R(0);
-        if (!direct && i < nk) {
+        if (!DIRECT && i < nk) {
             const int d = (3 * leg + jl) * nk + i;
             R e;
             if (eps_in) {
@@ -645,7 +648,7 @@ __global__ __launch_bounds__(64) void rollout16_kernel(ModelT<R> Mr, ModelT<S> M
     R L = R(0);
     for (int k = 0; k < P.H; ++k) {
         R uj = R(0);
-        if (direct) {
+        if constexpr (DIRECT) {
             // value k of this lane's joint (nk == H): theta = mu + sigma eps
             const int d = (3 * leg + jl) * nk + k;
             R e;
@@ -694,10 +697,15 @@ hipError_t launch_t(const ModelT<R>& Mr, const ModelT<S>& Ms, const DevParams& P
     const int blocks = (P.K + kSamples - 1) / kSamples;
     const size_t lds = lds_bytes<S>(Mr.scene, Mr.hf_nx * Mr.hf_ny);
     if (lds > 65536) return hipErrorInvalidValue;
-#define MPPI_LAUNCH_R16(SC)                                                                                     \
-    hipLaunchKernelGGL((rollout16_kernel<SC, R, S>), dim3(blocks), dim3(64), lds, st, Mr, Ms, P, a.B, a.hf, a.mu, \
-                       a.x0, a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj, a.direct, a.skip, \
+#define MPPI_LAUNCH_R16_D(SC, D)                                                                               \
+    hipLaunchKernelGGL((rollout16_kernel<SC, R, S, D>), dim3(blocks), dim3(64), lds, st, Mr, Ms, P, a.B, a.hf,     \
+                       a.mu, a.x0, a.eps_in, a.eps_sn, a.eps_sd, a.eps_out, a.costs, a.traj, a.direct, a.skip,     \
                        a.input_status)
+#define MPPI_LAUNCH_R16(SC)          \
+    if (a.direct)                    \
+        MPPI_LAUNCH_R16_D(SC, true); \
+    else                             \
+        MPPI_LAUNCH_R16_D(SC, false)
     switch (Mr.scene) {
     case 0: MPPI_LAUNCH_R16(0); break;
     case 1: MPPI_LAUNCH_R16(1); break;
@@ -706,6 +714,7 @@ hipError_t launch_t(const ModelT<R>& Mr, const ModelT<S>& Ms, const DevParams& P
     default: return hipErrorInvalidValue;
     }
 #undef MPPI_LAUNCH_R16
+#undef MPPI_LAUNCH_R16_D
     return hipGetLastError();
 }
 
